@@ -1,0 +1,194 @@
+/*
+ * kcore.h — exact k-core decomposition on AMD Instinct MI355X (gfx950).
+ *
+ * Computes the coreness of every vertex of an undirected simple graph: the largest k such that the
+ * vertex belongs to the k-core, the largest subgraph whose vertices all have degree >= k
+ * (paper: "Parallel k-Core Decomposition: Theory and Practice", Sec. 1 and Sec. 2, Notations).
+ * The method is the paper's work-efficient framework (Alg. 1) — rounds k = 0, 1, ... over an
+ * active set, each round peeling frontiers of vertices whose induced degree is at most k in
+ * subrounds — with the online peel of Alg. 3: peeling v atomically decrements the induced degree
+ * of each live neighbour u, and the decrement that takes u from above k to k or below pushes u
+ * into the next frontier.
+ *
+ * Graph layout (all entry points): CSR with both directions of every undirected edge stored.
+ *   offsets  int64[n+1], offsets[0] = 0, non-decreasing; row v is adj[offsets[v] .. offsets[v+1])
+ *   adj      int32[offsets[n]], neighbour ids in [0, n)
+ * The graph must be simple and symmetric: no self-loops, no duplicate entries in a row, and u in
+ * row v iff v in row u. Rows need not be sorted. Inputs that break this contract are peeled
+ * literally (memory-safe as long as every id is in range); set kcore_options.validate to have the
+ * device reject them with KCORE_EBADGRAPH instead.
+ *
+ * Calls are stream-ordered and asynchronous unless stated: a return of KCORE_OK means the work is
+ * enqueued on `stream`; coreness_out is valid once the stream reaches that point. Argument errors
+ * are reported synchronously and enqueue nothing. The caller owns every buffer it passes; the
+ * library owns its device workspace, cached per (device, stream) and reused across calls (see
+ * kcore_release_workspaces). Calls on distinct streams may run concurrently; calls on one stream
+ * are serialised by it. hipStream_t 0 is the legacy default stream.
+ */
+#ifndef KCORE_H_
+#define KCORE_H_
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  KCORE_OK = 0,
+  KCORE_PENDING = 1,      /* kcore_poll: request not finished yet */
+  KCORE_EINVAL = -1,      /* bad argument (null pointer, negative size, bad option) */
+  KCORE_ENOMEM = -2,      /* device or host allocation failed */
+  KCORE_EDEVICE = -3,     /* HIP runtime error, or the device reported an internal failure */
+  KCORE_ETOOBIG = -4,     /* request can never fit the configured limits */
+  KCORE_ENOTFOUND = -5,   /* kcore_poll: unknown ticket, or result already taken */
+  KCORE_ECANCELED = -6,   /* kcore_poll: request was cancelled */
+  KCORE_EBADGRAPH = -7    /* validate mode: CSR breaks the input contract */
+} kcore_status;
+
+/* Peeling schedules of the single-graph path. */
+typedef enum {
+  KCORE_MODE_AUTO = 0,      /* library choice (currently KCORE_MODE_CHAINED) */
+  KCORE_MODE_LEVELSYNC = 1, /* Alg. 1 + Alg. 3 literally: one grid-wide barrier per subround; the
+                               frontiers, and so the subround count rho (Sec. 3.2, span analysis),
+                               equal those of the sequential framework */
+  KCORE_MODE_CHAINED = 2    /* vertices that drop to k inside a round are peeled in the same
+                               pass by whichever workgroup finds them, without waiting for a
+                               barrier (the idea of vertical granularity control, Sec. 4.2);
+                               one grid-wide barrier per round */
+} kcore_mode;
+
+typedef struct {
+  int32_t mode;          /* kcore_mode */
+  int32_t validate;      /* nonzero: check the CSR on the device first (KCORE_EBADGRAPH);
+                            makes the call synchronous on `stream` */
+  int32_t blocks_per_cu; /* persistent workgroups per compute unit; 0 = library choice */
+  int32_t hub_degree;    /* vertices with at least this degree are split into tiles of
+                            `tile_edges` adjacency entries when peeled; 0 = library choice */
+  int64_t num_entries;   /* offsets[n] when the caller knows it; 0 = unknown, in which case the
+                            single-graph call reads it with a blocking 8-byte copy on `stream`
+                            to size the tile lists */
+  int32_t local_budget;  /* chained mode: vertices one wavefront may peel from its local queue per
+                            phase before handing the rest to the global frontier; 0 = default */
+  int32_t tile_edges;    /* adjacency entries per hub tile (multiple of 64); 0 = default */
+  int32_t reserved[4];   /* must be zero */
+} kcore_options;
+
+/* Counters of one decomposition (filled when a kcore_stats* is passed; that call synchronises
+ * `stream`). Field meanings follow the paper's framework. */
+typedef struct {
+  int64_t rounds;          /* non-empty rounds = number of distinct coreness values */
+  int64_t subrounds;       /* peel passes over a non-empty frontier (rho in level-sync mode) */
+  int64_t barriers;        /* grid-wide synchronisations executed */
+  int64_t peeled;          /* vertices given a coreness (= n) */
+  int64_t edges;           /* adjacency entries expanded (= m) */
+  int64_t decrements;      /* global atomic decrements issued */
+  int64_t combined;        /* decrements absorbed by LDS combining */
+  int64_t scanned;         /* active-set slots scanned (Thm. 3.1 bounds this by n + m) */
+  int32_t kmax;            /* largest coreness */
+  int32_t device_status;   /* 0, or internal failure bits */
+  float ms;                /* device time of the call in milliseconds */
+  int32_t reserved[5];
+} kcore_stats;
+
+/* Single graph. n == 0 is a no-op. */
+int kcore_decompose(const int64_t* offsets, const int32_t* adj, int64_t n, int32_t* coreness_out,
+                    hipStream_t stream);
+
+/* As kcore_decompose with options (nullable: defaults) and statistics (nullable; non-null makes
+ * the call synchronous on `stream`). */
+int kcore_decompose_ex(const int64_t* offsets, const int32_t* adj, int64_t n, int32_t* coreness_out,
+                       hipStream_t stream, const kcore_options* opt, kcore_stats* stats_host);
+
+/* Many independent graphs in one segmented CSR (device pointers). Graph g owns the global vertex
+ * range [graph_vptr[g], graph_vptr[g+1]); its rows use global ids inside that range. The k-cores
+ * of a disjoint union are the unions of the k-cores of its parts, so every graph is peeled on its
+ * own k cursor; one launch covers the whole batch.
+ *   graph_vptr  int64[num_graphs+1] on the device, graph_vptr[0] = 0,
+ *               graph_vptr[num_graphs] = total_vertices, non-decreasing
+ *   offsets     int64[total_vertices+1], adj int32[offsets[total_vertices]] (global ids)
+ *   coreness_out int32[total_vertices] */
+int kcore_decompose_batched(const int64_t* graph_vptr, const int64_t* offsets, const int32_t* adj,
+                            int32_t num_graphs, int64_t total_vertices, int32_t* coreness_out,
+                            hipStream_t stream);
+
+int kcore_decompose_batched_ex(const int64_t* graph_vptr, const int64_t* offsets,
+                               const int32_t* adj, int32_t num_graphs, int64_t total_vertices,
+                               int32_t* coreness_out, hipStream_t stream, const kcore_options* opt,
+                               kcore_stats* stats_host);
+
+/* Frees every cached workspace after synchronising the device. */
+int kcore_release_workspaces(void);
+
+/* ------------------------------------------------------------------------------------------------
+ * Serving: continuous batching of independent graph requests on one device.
+ *
+ * kcore_submit copies a HOST graph into pinned staging before it returns (the caller may free its
+ * buffers immediately) and hands back a ticket. A dispatcher thread admits queued requests while
+ * their device footprint fits the HBM budget and a batch slot is free, packs them into a segmented
+ * CSR and launches the batched peel; up to max_inflight batches run concurrently on separate
+ * streams, so requests that arrive while others are on the GPU start as soon as a slot and memory
+ * free up. Results are copied back to pinned host memory; kcore_poll hands them out.
+ * ---------------------------------------------------------------------------------------------- */
+typedef struct kcore_server kcore_server;
+
+typedef struct {
+  int32_t device;              /* HIP device ordinal */
+  int32_t max_inflight;        /* concurrent batches on the device (>= 1; 0 = 4) */
+  int32_t max_batch_graphs;    /* graphs per batch (0 = 4096) */
+  int32_t reserved0;
+  int64_t max_batch_vertices;  /* vertices per batch (0 = 1 << 24) */
+  int64_t hbm_budget_bytes;    /* device bytes all in-flight batches may hold (0 = 8 GiB) */
+  int64_t max_request_vertices;/* larger requests are rejected with KCORE_ETOOBIG (0 = no limit) */
+  double batch_wait_us;        /* how long the dispatcher waits to grow a batch while the device
+                                  is busy (0 = 50 us) */
+  int32_t reserved[4];
+} kcore_server_config;
+
+typedef struct {
+  double submit_us;   /* submit time, microseconds on the server's steady clock */
+  double admit_us;    /* admitted into a batch */
+  double launch_us;   /* batch launched */
+  double done_us;     /* result visible to kcore_poll */
+  int64_t batch_id;   /* batch the request ran in */
+  int32_t batch_graphs;
+  int32_t reserved;
+} kcore_request_stats;
+
+/* Returns null on failure (see kcore_last_error). */
+kcore_server* kcore_server_create(const kcore_server_config* cfg);
+
+/* Host CSR (offsets int64[n+1], adj int32[offsets[n]]), copied before return. */
+int kcore_submit(kcore_server* s, const int64_t* offsets_host, const int32_t* adj_host, int64_t n,
+                 uint64_t* ticket_out);
+
+/* KCORE_PENDING until done; then KCORE_OK once (coreness_host_out int32[n] filled, stats if
+ * non-null), after which the ticket is forgotten (KCORE_ENOTFOUND). */
+int kcore_poll(kcore_server* s, uint64_t ticket, int32_t* coreness_host_out,
+               kcore_request_stats* st);
+
+/* Blocks until the ticket is done (or timeout_us elapses: KCORE_PENDING), then behaves as
+ * kcore_poll. */
+int kcore_wait(kcore_server* s, uint64_t ticket, int32_t* coreness_host_out,
+               kcore_request_stats* st, double timeout_us);
+
+/* Cancels a queued request (KCORE_OK) or reports KCORE_PENDING if it is already on the device. */
+int kcore_cancel(kcore_server* s, uint64_t ticket);
+
+/* Microseconds on the server's steady clock (the time base of kcore_request_stats). */
+double kcore_server_now_us(const kcore_server* s);
+
+/* Drains in-flight batches, then frees everything. */
+void kcore_server_destroy(kcore_server* s);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char* kcore_last_error(void);
+
+/* Library version: major * 10000 + minor * 100 + patch. */
+int kcore_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KCORE_H_ */

@@ -1,0 +1,283 @@
+"""Exact k-core decomposition on AMD Instinct MI355X — Python binding of ``libkcore.so``.
+
+Thin ctypes marshalling over the C ABI declared in ``include/kcore.h``: every step of the
+computation runs in the library's HIP kernels. PyTorch is used only to hold device memory and to
+name the current HIP stream. If the library has not been built the import fails loudly; there is
+no fallback.
+
+Single graph::
+
+    core = decompose(offsets_dev_int64, adj_dev_int32)               # int32 tensor on the device
+    core, st = decompose(offsets, adj, stats=True, mode="levelsync")  # + counters dict
+
+Batch of independent graphs in one segmented CSR (global ids)::
+
+    core = decompose_batched(vptr_dev_int64, offsets, adj)
+
+Serving (host graphs in, host results out)::
+
+    with Server(device=0) as s:
+        t = s.submit(offsets_np, adj_np)
+        core = s.wait(t)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkcore.so")
+
+KCORE_OK, KCORE_PENDING = 0, 1
+ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ETOOBIG", -5: "ENOTFOUND",
+          -6: "ECANCELED", -7: "EBADGRAPH"}
+MODES = {"auto": 0, "levelsync": 1, "chained": 2}
+
+
+class KcoreError(RuntimeError):
+    def __init__(self, code: int, where: str, msg: str):
+        super().__init__(f"{where}: {ERRORS.get(code, code)} ({code}): {msg}")
+        self.code = code
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("validate", ctypes.c_int32),
+                ("blocks_per_cu", ctypes.c_int32), ("hub_degree", ctypes.c_int32),
+                ("num_entries", ctypes.c_int64), ("local_budget", ctypes.c_int32),
+                ("tile_edges", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_int64), ("subrounds", ctypes.c_int64),
+                ("barriers", ctypes.c_int64), ("peeled", ctypes.c_int64),
+                ("edges", ctypes.c_int64), ("decrements", ctypes.c_int64),
+                ("combined", ctypes.c_int64), ("scanned", ctypes.c_int64),
+                ("kmax", ctypes.c_int32), ("device_status", ctypes.c_int32),
+                ("ms", ctypes.c_float), ("reserved", ctypes.c_int32 * 5)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("max_inflight", ctypes.c_int32),
+                ("max_batch_graphs", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("max_batch_vertices", ctypes.c_int64), ("hbm_budget_bytes", ctypes.c_int64),
+                ("max_request_vertices", ctypes.c_int64), ("batch_wait_us", ctypes.c_double),
+                ("reserved", ctypes.c_int32 * 4)]
+
+
+class RequestStats(ctypes.Structure):
+    _fields_ = [("submit_us", ctypes.c_double), ("admit_us", ctypes.c_double),
+                ("launch_us", ctypes.c_double), ("done_us", ctypes.c_double),
+                ("batch_id", ctypes.c_int64), ("batch_graphs", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
+# Every exported symbol of include/kcore.h with its ctypes signature.
+P, I32, I64, U64P = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_uint64)
+SIGNATURES = {
+    "kcore_decompose": (ctypes.c_int, [P, P, I64, P, P]),
+    "kcore_decompose_ex": (ctypes.c_int, [P, P, I64, P, P, ctypes.POINTER(Options), ctypes.POINTER(Stats)]),
+    "kcore_decompose_batched": (ctypes.c_int, [P, P, P, I32, I64, P, P]),
+    "kcore_decompose_batched_ex": (ctypes.c_int, [P, P, P, I32, I64, P, P, ctypes.POINTER(Options),
+                                                  ctypes.POINTER(Stats)]),
+    "kcore_release_workspaces": (ctypes.c_int, []),
+    "kcore_server_create": (P, [ctypes.POINTER(ServerConfig)]),
+    "kcore_submit": (ctypes.c_int, [P, P, P, I64, U64P]),
+    "kcore_poll": (ctypes.c_int, [P, ctypes.c_uint64, P, ctypes.POINTER(RequestStats)]),
+    "kcore_wait": (ctypes.c_int, [P, ctypes.c_uint64, P, ctypes.POINTER(RequestStats), ctypes.c_double]),
+    "kcore_cancel": (ctypes.c_int, [P, ctypes.c_uint64]),
+    "kcore_server_now_us": (ctypes.c_double, [P]),
+    "kcore_server_destroy": (None, [P]),
+    "kcore_last_error": (ctypes.c_char_p, []),
+    "kcore_version": (ctypes.c_int, []),
+}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it first with "
+                          "`python -c 'import __graft_entry__ as g; g.build()'` "
+                          "(hipcc --offload-arch=gfx950); there is no fallback path")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def last_error() -> str:
+    return (_lib.kcore_last_error() or b"").decode()
+
+
+def _check(rc: int, where: str):
+    if rc != KCORE_OK:
+        raise KcoreError(rc, where, last_error())
+
+
+def _stream_ptr(stream) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _options(mode, validate, num_entries, hub_degree=0, local_budget=0, tile_edges=0,
+             blocks_per_cu=0) -> Options:
+    o = Options()
+    o.mode = MODES[mode] if isinstance(mode, str) else int(mode)
+    o.validate = 1 if validate else 0
+    o.blocks_per_cu = blocks_per_cu
+    o.hub_degree = hub_degree
+    o.num_entries = num_entries
+    o.local_budget = local_budget
+    o.tile_edges = tile_edges
+    return o
+
+
+def _dev_tensor(t, dtype, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous {dtype} tensor on a GPU")
+    return t
+
+
+def decompose(offsets, adj, out=None, *, mode="auto", stats=False, validate=False, stream=None,
+              **tuning):
+    """Coreness of every vertex of one graph (device CSR: int64 offsets[n+1], int32 adj[m]).
+
+    Returns the int32 coreness tensor (``out`` if given), plus a dict of counters when
+    ``stats=True`` (that call synchronises the stream)."""
+    import torch
+    _dev_tensor(offsets, torch.int64, "offsets")
+    _dev_tensor(adj, torch.int32, "adj")
+    n = offsets.numel() - 1
+    if out is None:
+        out = torch.empty(max(n, 0), dtype=torch.int32, device=offsets.device)
+    _dev_tensor(out, torch.int32, "out")
+    if out.numel() < n:
+        raise ValueError("out is too small")
+    opt = _options(mode, validate, adj.numel(), **tuning)
+    st = Stats() if stats else None
+    rc = _lib.kcore_decompose_ex(offsets.data_ptr(), adj.data_ptr() if adj.numel() else None, n,
+                                 out.data_ptr() if n else None, _stream_ptr(stream),
+                                 ctypes.byref(opt), ctypes.byref(st) if st is not None else None)
+    _check(rc, "kcore_decompose_ex")
+    return (out, st.as_dict()) if stats else out
+
+
+def decompose_batched(vptr, offsets, adj, out=None, *, stats=False, validate=False, stream=None):
+    """Coreness for a segmented batch of independent graphs (device tensors, global ids)."""
+    import torch
+    _dev_tensor(vptr, torch.int64, "vptr")
+    _dev_tensor(offsets, torch.int64, "offsets")
+    _dev_tensor(adj, torch.int32, "adj")
+    G = vptr.numel() - 1
+    V = offsets.numel() - 1
+    if out is None:
+        out = torch.empty(max(V, 0), dtype=torch.int32, device=offsets.device)
+    _dev_tensor(out, torch.int32, "out")
+    opt = _options("auto", validate, adj.numel())
+    st = Stats() if stats else None
+    rc = _lib.kcore_decompose_batched_ex(vptr.data_ptr(), offsets.data_ptr(),
+                                         adj.data_ptr() if adj.numel() else None, G, V,
+                                         out.data_ptr() if V else None, _stream_ptr(stream),
+                                         ctypes.byref(opt),
+                                         ctypes.byref(st) if st is not None else None)
+    _check(rc, "kcore_decompose_batched_ex")
+    return (out, st.as_dict()) if stats else out
+
+
+def release_workspaces():
+    _check(_lib.kcore_release_workspaces(), "kcore_release_workspaces")
+
+
+class Server:
+    """Continuous-batching server over host graphs (see kcore.h, Serving)."""
+
+    def __init__(self, device: int = 0, max_inflight: int = 0, max_batch_graphs: int = 0,
+                 max_batch_vertices: int = 0, hbm_budget_bytes: int = 0,
+                 max_request_vertices: int = 0, batch_wait_us: float = 0.0):
+        cfg = ServerConfig()
+        cfg.device = device
+        cfg.max_inflight = max_inflight
+        cfg.max_batch_graphs = max_batch_graphs
+        cfg.max_batch_vertices = max_batch_vertices
+        cfg.hbm_budget_bytes = hbm_budget_bytes
+        cfg.max_request_vertices = max_request_vertices
+        cfg.batch_wait_us = batch_wait_us
+        self._h = _lib.kcore_server_create(ctypes.byref(cfg))
+        if not self._h:
+            raise KcoreError(-1, "kcore_server_create", last_error())
+        self._n = {}
+
+    def submit(self, offsets: np.ndarray, adj: np.ndarray) -> int:
+        off = np.ascontiguousarray(offsets, dtype=np.int64)
+        a = np.ascontiguousarray(adj, dtype=np.int32)
+        n = off.shape[0] - 1
+        t = ctypes.c_uint64(0)
+        rc = _lib.kcore_submit(self._h, off.ctypes.data, a.ctypes.data if a.size else None, n,
+                               ctypes.byref(t))
+        _check(rc, "kcore_submit")
+        self._n[t.value] = n
+        return t.value
+
+    def poll(self, ticket: int):
+        """(status, coreness or None, stats dict or None); status is KCORE_OK or KCORE_PENDING."""
+        n = self._n.get(ticket, 0)
+        out = np.empty(n, dtype=np.int32)
+        st = RequestStats()
+        rc = _lib.kcore_poll(self._h, ticket, out.ctypes.data if n else None, ctypes.byref(st))
+        if rc == KCORE_PENDING:
+            return rc, None, None
+        self._n.pop(ticket, None)
+        _check(rc, "kcore_poll")
+        return rc, out, st.as_dict()
+
+    def wait(self, ticket: int, timeout_us: float = 0.0, with_stats: bool = False):
+        n = self._n.get(ticket, 0)
+        out = np.empty(n, dtype=np.int32)
+        st = RequestStats()
+        rc = _lib.kcore_wait(self._h, ticket, out.ctypes.data if n else None, ctypes.byref(st),
+                             timeout_us)
+        if rc == KCORE_PENDING:
+            raise TimeoutError(f"ticket {ticket} not done after {timeout_us} us")
+        self._n.pop(ticket, None)
+        _check(rc, "kcore_wait")
+        return (out, st.as_dict()) if with_stats else out
+
+    def cancel(self, ticket: int) -> int:
+        return _lib.kcore_cancel(self._h, ticket)
+
+    def now_us(self) -> float:
+        return _lib.kcore_server_now_us(self._h)
+
+    def close(self):
+        if self._h:
+            _lib.kcore_server_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,436 @@
+// C ABI of the k-core library: argument checks, per-(device, stream) workspace cache, launches and
+// statistics read-back. Serving lives in kcore_server.cpp.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <utility>
+
+#include "../../include/kcore.h"
+#include "kcore_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(x)                                                                     \
+  do {                                                                                 \
+    hipError_t e_ = (x);                                                               \
+    if (e_ != hipSuccess)                                                              \
+      return fail(e_ == hipErrorOutOfMemory ? KCORE_ENOMEM : KCORE_EDEVICE, "%s: %s", #x, \
+                  hipGetErrorString(e_));                                              \
+  } while (0)
+
+struct DevInfo {
+  int cus = 0;
+  size_t lds_per_block = 0;
+  int peel_bpc = 0;
+};
+
+std::mutex g_mu;
+std::map<int, DevInfo> g_dev;
+
+int dev_info(int dev, DevInfo& out) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_dev.find(dev);
+  if (it != g_dev.end()) {
+    out = it->second;
+    return KCORE_OK;
+  }
+  DevInfo d;
+  HIP_TRY(hipDeviceGetAttribute(&d.cus, hipDeviceAttributeMultiprocessorCount, dev));
+  int lds = 0;
+  HIP_TRY(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  d.lds_per_block = (size_t)lds;
+  HIP_TRY(kc::peel_occupancy(&d.peel_bpc));
+  g_dev[dev] = d;
+  out = d;
+  return KCORE_OK;
+}
+
+// ---- single-graph workspace ---------------------------------------------------------------
+struct PeelWs {
+  int64_t n_cap = -1, t_cap = -1;
+  void* block = nullptr;  // one allocation for everything
+  size_t bytes = 0;
+  uint32_t* dt = nullptr;
+  uint32_t* state = nullptr;
+  int32_t* act[2] = {nullptr, nullptr};
+  int32_t* fr[2] = {nullptr, nullptr};
+  int2* tl[2] = {nullptr, nullptr};
+  kc::PeelCtl* ctl = nullptr;
+  unsigned long long* host_stats = nullptr;  // pinned
+  unsigned* vstat = nullptr;                 // validation status + xor sum (device)
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+struct BatchWs {
+  int64_t v_cap = -1;
+  int32_t g_cap = -1;
+  void* block = nullptr;
+  uint32_t* gdt = nullptr;
+  int32_t* gq = nullptr;
+  int32_t* order = nullptr;
+  kc::BatchCtl* ctl = nullptr;
+  unsigned long long* host_stats = nullptr;
+  unsigned* vstat = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+using Key = std::pair<int, hipStream_t>;
+std::map<Key, PeelWs*> g_peel;
+std::map<Key, BatchWs*> g_batch;
+
+size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+int peel_ws(int dev, hipStream_t s, int64_t n, int64_t tcap, PeelWs*& out) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  PeelWs*& w = g_peel[Key(dev, s)];
+  if (!w) {
+    w = new PeelWs;
+    HIP_TRY(hipHostMalloc((void**)&w->host_stats, 16 * sizeof(unsigned long long) + 64, hipHostMallocDefault));
+    HIP_TRY(hipEventCreate(&w->ev0));
+    HIP_TRY(hipEventCreate(&w->ev1));
+  }
+  if (w->n_cap < n || w->t_cap < tcap) {
+    if (w->block) {
+      HIP_TRY(hipStreamSynchronize(s));
+      HIP_TRY(hipFree(w->block));
+      w->block = nullptr;
+    }
+    const int64_t nc = n > w->n_cap ? n + n / 8 : w->n_cap;
+    const int64_t tc = tcap > w->t_cap ? tcap + tcap / 8 + 64 : w->t_cap;
+    const size_t nw = (size_t)((nc + 15) / 16);
+    size_t off = 0;
+    const size_t o_dt = off; off = align_up(off + 4 * (size_t)nc);
+    const size_t o_st = off; off = align_up(off + 4 * nw);
+    const size_t o_a0 = off; off = align_up(off + 4 * (size_t)nc);
+    const size_t o_a1 = off; off = align_up(off + 4 * (size_t)nc);
+    const size_t o_f0 = off; off = align_up(off + 4 * (size_t)nc);
+    const size_t o_f1 = off; off = align_up(off + 4 * (size_t)nc);
+    const size_t o_t0 = off; off = align_up(off + 8 * (size_t)tc);
+    const size_t o_t1 = off; off = align_up(off + 8 * (size_t)tc);
+    const size_t o_c = off; off = align_up(off + sizeof(kc::PeelCtl));
+    const size_t o_v = off; off = align_up(off + 64);
+    hipError_t e = hipMalloc(&w->block, off);
+    if (e != hipSuccess) {
+      w->block = nullptr;
+      w->n_cap = w->t_cap = -1;
+      return fail(KCORE_ENOMEM, "workspace of %zu bytes: %s", off, hipGetErrorString(e));
+    }
+    char* b = static_cast<char*>(w->block);
+    w->bytes = off;
+    w->dt = (uint32_t*)(b + o_dt);
+    w->state = (uint32_t*)(b + o_st);
+    w->act[0] = (int32_t*)(b + o_a0);
+    w->act[1] = (int32_t*)(b + o_a1);
+    w->fr[0] = (int32_t*)(b + o_f0);
+    w->fr[1] = (int32_t*)(b + o_f1);
+    w->tl[0] = (int2*)(b + o_t0);
+    w->tl[1] = (int2*)(b + o_t1);
+    w->ctl = (kc::PeelCtl*)(b + o_c);
+    w->vstat = (unsigned*)(b + o_v);
+    w->n_cap = nc;
+    w->t_cap = tc;
+  }
+  out = w;
+  return KCORE_OK;
+}
+
+int batch_ws(int dev, hipStream_t s, int64_t V, int32_t G, BatchWs*& out) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  BatchWs*& w = g_batch[Key(dev, s)];
+  if (!w) {
+    w = new BatchWs;
+    HIP_TRY(hipHostMalloc((void**)&w->host_stats, 16 * sizeof(unsigned long long) + 64, hipHostMallocDefault));
+    HIP_TRY(hipEventCreate(&w->ev0));
+    HIP_TRY(hipEventCreate(&w->ev1));
+  }
+  if (w->v_cap < V || w->g_cap < G) {
+    if (w->block) {
+      HIP_TRY(hipStreamSynchronize(s));
+      HIP_TRY(hipFree(w->block));
+      w->block = nullptr;
+    }
+    const int64_t vc = V > w->v_cap ? V + V / 8 : w->v_cap;
+    const int64_t gc = G > w->g_cap ? (int64_t)G + G / 8 + 16 : w->g_cap;
+    size_t off = 0;
+    const size_t o_d = off; off = align_up(off + 4 * (size_t)vc);
+    const size_t o_q = off; off = align_up(off + 4 * (size_t)vc);
+    const size_t o_o = off; off = align_up(off + 4 * (size_t)gc);
+    const size_t o_c = off; off = align_up(off + sizeof(kc::BatchCtl));
+    const size_t o_v = off; off = align_up(off + 64);
+    hipError_t e = hipMalloc(&w->block, off);
+    if (e != hipSuccess) {
+      w->block = nullptr;
+      w->v_cap = -1;
+      w->g_cap = -1;
+      return fail(KCORE_ENOMEM, "batched workspace of %zu bytes: %s", off, hipGetErrorString(e));
+    }
+    char* b = static_cast<char*>(w->block);
+    w->gdt = (uint32_t*)(b + o_d);
+    w->gq = (int32_t*)(b + o_q);
+    w->order = (int32_t*)(b + o_o);
+    w->ctl = (kc::BatchCtl*)(b + o_c);
+    w->vstat = (unsigned*)(b + o_v);
+    w->v_cap = vc;
+    w->g_cap = (int32_t)gc;
+  }
+  out = w;
+  return KCORE_OK;
+}
+
+int check_opts(const kcore_options* o) {
+  if (!o) return KCORE_OK;
+  if (o->mode < 0 || o->mode > 2) return fail(KCORE_EINVAL, "mode %d unknown", o->mode);
+  if (o->blocks_per_cu < 0 || o->hub_degree < 0 || o->num_entries < 0 || o->local_budget < 0 ||
+      o->tile_edges < 0 || (o->tile_edges % 64) != 0)
+    return fail(KCORE_EINVAL, "negative option, or tile_edges not a multiple of 64");
+  for (int i = 0; i < 4; ++i)
+    if (o->reserved[i]) return fail(KCORE_EINVAL, "reserved option fields must be zero");
+  return KCORE_OK;
+}
+
+int run_validate(const int64_t* off, const int32_t* adj, int64_t n, const int64_t* vptr, int32_t G,
+                 unsigned* vstat, hipStream_t s) {
+  HIP_TRY(kc::launch_fill_u32(vstat, 0u, 16, s));
+  HIP_TRY(kc::launch_validate(off, adj, n, vptr, G, vstat,
+                              reinterpret_cast<unsigned long long*>(vstat + 2), s));
+  unsigned h[4] = {0, 0, 0, 0};
+  HIP_TRY(hipMemcpyAsync(h, vstat, sizeof h, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (h[0] != 0u) return fail(KCORE_EBADGRAPH, "CSR breaks the input contract (offsets, ids or self-loops)");
+  if (h[2] != 0u || h[3] != 0u) return fail(KCORE_EBADGRAPH, "CSR is not symmetric");
+  return KCORE_OK;
+}
+
+void fill_stats(kcore_stats* st, const unsigned long long* hs, unsigned status, float ms) {
+  memset(st, 0, sizeof *st);
+  st->rounds = (int64_t)hs[kc::ST_ROUNDS];
+  st->subrounds = (int64_t)hs[kc::ST_SUBROUNDS];
+  st->barriers = (int64_t)hs[kc::ST_BARRIERS];
+  st->peeled = (int64_t)hs[kc::ST_PEELED];
+  st->edges = (int64_t)hs[kc::ST_EDGES];
+  st->decrements = (int64_t)hs[kc::ST_DECR];
+  st->combined = (int64_t)hs[kc::ST_COMBINED];
+  st->scanned = (int64_t)hs[kc::ST_SCANNED];
+  st->kmax = (int32_t)hs[kc::ST_KMAX];
+  st->device_status = (int32_t)status;
+  st->ms = ms;
+}
+
+}  // namespace
+
+void kc::set_error(const char* msg) { g_err = msg ? msg : ""; }
+
+extern "C" {
+
+int kcore_version(void) { return 10000; }
+
+const char* kcore_last_error(void) { return g_err.c_str(); }
+
+int kcore_decompose_ex(const int64_t* offsets, const int32_t* adj, int64_t n, int32_t* coreness_out,
+                       hipStream_t stream, const kcore_options* opt, kcore_stats* stats_host) {
+  g_err.clear();
+  if (n < 0) return fail(KCORE_EINVAL, "n = %lld is negative", (long long)n);
+  if (n > 0x7fffffffLL) return fail(KCORE_EINVAL, "n = %lld exceeds the int32 id range", (long long)n);
+  if (int rc = check_opts(opt)) return rc;
+  if (n == 0) {
+    if (stats_host) memset(stats_host, 0, sizeof *stats_host);
+    return KCORE_OK;
+  }
+  if (!offsets || !adj || !coreness_out) return fail(KCORE_EINVAL, "null pointer argument");
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  DevInfo di;
+  if (int rc = dev_info(dev, di)) return rc;
+
+  const int mode = (opt && opt->mode) ? opt->mode : KCORE_MODE_CHAINED;
+  const uint32_t hub = (opt && opt->hub_degree) ? (uint32_t)opt->hub_degree : 1024u;
+  const int tile = (opt && opt->tile_edges) ? opt->tile_edges : 1024;
+  const int budget = (opt && opt->local_budget) ? opt->local_budget : 4096;
+  int64_t m = opt ? opt->num_entries : 0;
+  if (m <= 0) {
+    int64_t* pin = nullptr;
+    HIP_TRY(hipHostMalloc((void**)&pin, sizeof(int64_t), hipHostMallocDefault));
+    hipError_t e1 = hipMemcpyAsync(pin, offsets + n, sizeof(int64_t), hipMemcpyDeviceToHost, stream);
+    hipError_t e2 = e1 == hipSuccess ? hipStreamSynchronize(stream) : e1;
+    m = *pin;
+    hipHostFree(pin);
+    if (e2 != hipSuccess) return fail(KCORE_EDEVICE, "reading offsets[n]: %s", hipGetErrorString(e2));
+  }
+  if (m < 0) return fail(KCORE_EINVAL, "offsets[n] = %lld is negative", (long long)m);
+  // tiles pushed over the whole run: sum over hubs of ceil(deg / tile) <= m / tile + #hubs,
+  // #hubs <= min(n, m / hub)
+  const int64_t hubs = std::min<int64_t>(n, m / (int64_t)hub + 1);
+  const int64_t tcap = m / tile + hubs + 64;
+
+  PeelWs* w = nullptr;
+  if (int rc = peel_ws(dev, stream, n, tcap, w)) return rc;
+  if (opt && opt->validate) {
+    if (int rc = run_validate(offsets, adj, n, nullptr, 0, w->vstat, stream)) return rc;
+  }
+
+  int bpc = (opt && opt->blocks_per_cu) ? opt->blocks_per_cu : di.peel_bpc;
+  if (bpc > di.peel_bpc) bpc = di.peel_bpc;
+  if (bpc < 1) return fail(KCORE_EDEVICE, "peel kernel cannot be resident on this device");
+  int blocks = bpc * di.cus;
+  // no more workgroups than there are vertex packets to keep barriers cheap on small graphs
+  const int64_t want = (n + 64 * kc::kWaves - 1) / (64 * kc::kWaves);
+  if (want < blocks) blocks = (int)std::max<int64_t>(want, 1);
+
+  kc::PeelArgs a;
+  a.off = offsets;
+  a.adj = adj;
+  a.n = n;
+  a.core = coreness_out;
+  a.dt = w->dt;
+  a.state = w->state;
+  a.act[0] = w->act[0];
+  a.act[1] = w->act[1];
+  a.fr[0] = w->fr[0];
+  a.fr[1] = w->fr[1];
+  a.tl[0] = w->tl[0];
+  a.tl[1] = w->tl[1];
+  a.fcap = w->n_cap;
+  a.tcap = w->t_cap;
+  a.ctl = w->ctl;
+  a.hub = hub;
+  a.tile = tile;
+  a.chained = mode == KCORE_MODE_CHAINED ? 1 : 0;
+  a.lq_budget = budget;
+
+  HIP_TRY(kc::launch_init_ctl(w->ctl, stream));
+  if (stats_host) HIP_TRY(hipEventRecord(w->ev0, stream));
+  HIP_TRY(kc::launch_peel(a, blocks, stream));
+  if (!stats_host) return KCORE_OK;
+  HIP_TRY(hipEventRecord(w->ev1, stream));
+  HIP_TRY(hipMemcpyAsync(w->host_stats, w->ctl->stats, 16 * sizeof(unsigned long long),
+                         hipMemcpyDeviceToHost, stream));
+  unsigned status = 0;
+  HIP_TRY(hipMemcpyAsync(w->host_stats + 16, &w->ctl->status, sizeof(unsigned), hipMemcpyDeviceToHost,
+                         stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  memcpy(&status, w->host_stats + 16, sizeof status);
+  float ms = 0;
+  HIP_TRY(hipEventElapsedTime(&ms, w->ev0, w->ev1));
+  fill_stats(stats_host, w->host_stats, status, ms);
+  if (status) return fail(KCORE_EDEVICE, "device reported failure bits 0x%x", status);
+  return KCORE_OK;
+}
+
+int kcore_decompose(const int64_t* offsets, const int32_t* adj, int64_t n, int32_t* coreness_out,
+                    hipStream_t stream) {
+  return kcore_decompose_ex(offsets, adj, n, coreness_out, stream, nullptr, nullptr);
+}
+
+int kcore_decompose_batched_ex(const int64_t* graph_vptr, const int64_t* offsets, const int32_t* adj,
+                               int32_t num_graphs, int64_t total_vertices, int32_t* coreness_out,
+                               hipStream_t stream, const kcore_options* opt, kcore_stats* stats_host) {
+  g_err.clear();
+  if (num_graphs < 0 || total_vertices < 0)
+    return fail(KCORE_EINVAL, "negative num_graphs or total_vertices");
+  if (total_vertices > 0x7fffffffLL) return fail(KCORE_EINVAL, "total_vertices exceeds the int32 id range");
+  if (int rc = check_opts(opt)) return rc;
+  if (num_graphs == 0 || total_vertices == 0) {
+    if (stats_host) memset(stats_host, 0, sizeof *stats_host);
+    return KCORE_OK;
+  }
+  if (!graph_vptr || !offsets || !adj || !coreness_out) return fail(KCORE_EINVAL, "null pointer argument");
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  DevInfo di;
+  if (int rc = dev_info(dev, di)) return rc;
+  BatchWs* w = nullptr;
+  if (int rc = batch_ws(dev, stream, total_vertices, num_graphs, w)) return rc;
+  if (opt && opt->validate) {
+    if (int rc = run_validate(offsets, adj, total_vertices, graph_vptr, num_graphs, w->vstat, stream)) return rc;
+  }
+  // LDS per workgroup: induced degrees + peel queue, 8 bytes per vertex
+  size_t lds = 48 * 1024;
+  if (lds > di.lds_per_block / 2) lds = di.lds_per_block / 2;
+  const int32_t cap = (int32_t)(lds / 8);
+  int bpc = 0;
+  HIP_TRY(kc::batched_occupancy(lds, &bpc));
+  if (opt && opt->blocks_per_cu && opt->blocks_per_cu < bpc) bpc = opt->blocks_per_cu;
+  if (bpc < 1) return fail(KCORE_EDEVICE, "batched kernel cannot be resident on this device");
+  int blocks = bpc * di.cus;
+  if (num_graphs < blocks) blocks = num_graphs;
+
+  HIP_TRY(kc::launch_fill_u32(w->ctl, 0u, sizeof(kc::BatchCtl) / 4, stream));
+  HIP_TRY(kc::launch_order(graph_vptr, offsets, num_graphs, w->order, stream));
+  kc::BatchArgs a;
+  a.vptr = graph_vptr;
+  a.off = offsets;
+  a.adj = adj;
+  a.G = num_graphs;
+  a.core = coreness_out;
+  a.order = w->order;
+  a.gdt = w->gdt;
+  a.gq = w->gq;
+  a.ctl = w->ctl;
+  a.lds_cap = cap;
+  if (stats_host) HIP_TRY(hipEventRecord(w->ev0, stream));
+  HIP_TRY(kc::launch_batched(a, blocks, lds, stream));
+  if (!stats_host) return KCORE_OK;
+  HIP_TRY(hipEventRecord(w->ev1, stream));
+  HIP_TRY(hipMemcpyAsync(w->host_stats, w->ctl->stats, 16 * sizeof(unsigned long long),
+                         hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  float ms = 0;
+  HIP_TRY(hipEventElapsedTime(&ms, w->ev0, w->ev1));
+  fill_stats(stats_host, w->host_stats, 0u, ms);
+  stats_host->peeled = total_vertices;
+  stats_host->barriers = 0;
+  return KCORE_OK;
+}
+
+int kcore_decompose_batched(const int64_t* graph_vptr, const int64_t* offsets, const int32_t* adj,
+                            int32_t num_graphs, int64_t total_vertices, int32_t* coreness_out,
+                            hipStream_t stream) {
+  return kcore_decompose_batched_ex(graph_vptr, offsets, adj, num_graphs, total_vertices, coreness_out,
+                                    stream, nullptr, nullptr);
+}
+
+int kcore_release_workspaces(void) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  HIP_TRY(hipDeviceSynchronize());
+  for (auto& kv : g_peel) {
+    PeelWs* w = kv.second;
+    if (!w) continue;
+    if (w->block) hipFree(w->block);
+    if (w->host_stats) hipHostFree(w->host_stats);
+    if (w->ev0) hipEventDestroy(w->ev0);
+    if (w->ev1) hipEventDestroy(w->ev1);
+    delete w;
+  }
+  g_peel.clear();
+  for (auto& kv : g_batch) {
+    BatchWs* w = kv.second;
+    if (!w) continue;
+    if (w->block) hipFree(w->block);
+    if (w->host_stats) hipHostFree(w->host_stats);
+    if (w->ev0) hipEventDestroy(w->ev0);
+    if (w->ev1) hipEventDestroy(w->ev1);
+    delete w;
+  }
+  g_batch.clear();
+  return KCORE_OK;
+}
+
+}  // extern "C"

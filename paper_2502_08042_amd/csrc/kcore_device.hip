@@ -1,0 +1,904 @@
+// Device code of the k-core library for gfx950 (MI355X).
+//
+// Two engines:
+//  * peel_kernel — one persistent, co-resident grid peels a single graph following the paper's
+//    framework (Alg. 1) with the online peel (Alg. 3). Phases are separated by a fence-free grid
+//    barrier; a phase either scans the active set (extracting the round's first frontier and
+//    refining the set, Alg. 1 extract/refine) or expands the current frontier. Cross-workgroup data
+//    (frontiers, active lists, counters) goes through agent-scope relaxed atomics, which the MI355X
+//    keeps coherent across its XCD L2 caches, so barriers need no L2 write-back or invalidate.
+//  * batched_kernel — many independent graphs, one workgroup per graph with its induced degrees and
+//    peel queue in LDS, so a graph's rounds and subrounds synchronise at workgroup level only.
+#include "kcore_internal.h"
+
+namespace kc {
+
+constexpr uint32_t HUBBIT = 0x80000000u;
+constexpr uint32_t DMASK = 0x7fffffffu;
+
+template <class T>
+__device__ __forceinline__ T ald(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T>
+__device__ __forceinline__ void ast(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T>
+__device__ __forceinline__ T aadd(T* p, T v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T>
+__device__ __forceinline__ T asub(T* p, T v) {
+  return __hip_atomic_fetch_sub(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T>
+__device__ __forceinline__ T aor(T* p, T v) {
+  return __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T>
+__device__ __forceinline__ T amin(T* p, T v) {
+  return __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+__device__ __forceinline__ int rank_in(unsigned long long m) {
+  return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+}
+template <class T>
+__device__ __forceinline__ T wave_incl_scan(T x) {
+  const int l = lane_id();
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    T y = __shfl_up(x, o, 64);
+    if (l >= o) x += y;
+  }
+  return x;
+}
+__device__ __forceinline__ unsigned wave_min(unsigned x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x = min(x, (unsigned)__shfl_xor((int)x, o, 64));
+  return x;
+}
+
+// ------------------------------------------------------------------------------------------
+// Grid barrier. Arrivals go to one of kBarGroups counters, the last arrival of each group to a
+// top counter, and the last top arrival publishes the new epoch. Counters only grow, so no reset
+// races. Every thread first waits for its own memory operations to complete (s_waitcnt), which
+// with agent-scope accesses makes them visible device-wide before the arrival. Waits are bounded:
+// after ~4 s without progress, or if any workgroup has flagged an error, every workgroup leaves.
+// ------------------------------------------------------------------------------------------
+__device__ bool grid_sync(PeelCtl* C, unsigned& epoch) {
+  __shared__ int s_ok;
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned nb = gridDim.x;
+    const unsigned ng = nb < (unsigned)kBarGroups ? nb : (unsigned)kBarGroups;
+    const unsigned grp = blockIdx.x % ng;
+    const unsigned gsize = nb / ng + ((nb % ng) > grp ? 1u : 0u);
+    const unsigned target = epoch + 1;
+    int ok = 1;
+    bool last = false;
+    const unsigned a = aadd(&C->bar_grp[grp][0], 1u);
+    if (a == target * gsize - 1) {
+      const unsigned b = aadd(&C->bar_top, 1u);
+      if (b == target * ng - 1) last = true;
+    }
+    if (last) {
+      __builtin_amdgcn_s_waitcnt(0);
+      ast(&C->bar_gen, target);
+    } else {
+      const unsigned long long t0 = wall_clock64();
+      while (ald(&C->bar_gen) < target) {
+        __builtin_amdgcn_s_sleep(1);
+        if (wall_clock64() - t0 > 400000000ull) {  // 100 MHz clock: 4 s
+          aor(&C->status, (unsigned)KC_ERR_TIMEOUT);
+          ok = 0;
+          break;
+        }
+      }
+    }
+    if (ald(&C->status) != 0u) ok = 0;
+    s_ok = ok;
+  }
+  __syncthreads();
+  epoch += 1;
+  return s_ok != 0;
+}
+
+// ------------------------------------------------------------------------------------------
+// Per-wave staging of appends to a global list: entries collect in LDS and go out in bulk, so the
+// shared tail counter sees one atomic per flush instead of one per wave step.
+// ------------------------------------------------------------------------------------------
+struct Stage {
+  int32_t* buf;  // LDS, kStage entries
+  int cnt;       // wave-uniform
+};
+
+__device__ __forceinline__ void stage_flush(Stage& s, unsigned long long* tail, int32_t* dst,
+                                            long long cap, unsigned* status) {
+  if (s.cnt == 0) return;
+  unsigned long long base = 0;
+  if (lane_id() == 0) base = aadd(tail, (unsigned long long)s.cnt);
+  base = __shfl(base, 0, 64);
+  if ((long long)(base + s.cnt) > cap) {
+    if (lane_id() == 0) aor(status, (unsigned)KC_ERR_OVERFLOW);
+  } else {
+    for (int i = lane_id(); i < s.cnt; i += 64) ast(&dst[base + i], s.buf[i]);
+  }
+  s.cnt = 0;
+}
+
+// all lanes call; lanes with p append v
+__device__ __forceinline__ void stage_push(Stage& s, bool p, int32_t v, unsigned long long* tail,
+                                           int32_t* dst, long long cap, unsigned* status) {
+  const unsigned long long m = __ballot(p);
+  if (m == 0) return;
+  const int c = __popcll(m);
+  if (s.cnt + c > kStage) stage_flush(s, tail, dst, cap, status);
+  if (p) s.buf[s.cnt + rank_in(m)] = v;
+  s.cnt += c;
+}
+
+// Block-level final flush of every wave's leftovers with one atomic per block.
+__device__ void block_flush(Stage& s, unsigned long long* tail, int32_t* dst, long long cap,
+                            unsigned* status, unsigned long long* s_cnt, unsigned long long* s_base) {
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane_id() == 0) s_cnt[w] = (unsigned long long)s.cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long tot = 0;
+    for (int i = 0; i < kWaves; ++i) {
+      unsigned long long c = s_cnt[i];
+      s_cnt[i] = tot;
+      tot += c;
+    }
+    unsigned long long b = tot ? aadd(tail, tot) : 0ull;
+    if (tot && (long long)(b + tot) > cap) {
+      aor(status, (unsigned)KC_ERR_OVERFLOW);
+      tot = 0;
+    }
+    *s_base = tot ? b : ~0ull;
+  }
+  __syncthreads();
+  const unsigned long long b = *s_base;
+  if (b != ~0ull) {
+    const unsigned long long o = b + s_cnt[w];
+    for (int i = lane_id(); i < s.cnt; i += 64) ast(&dst[o + i], s.buf[i]);
+  }
+  s.cnt = 0;
+  __syncthreads();
+}
+
+// ------------------------------------------------------------------------------------------
+// Single-graph peel.
+// ------------------------------------------------------------------------------------------
+struct WaveCtx {
+  Stage sf;            // next small frontier
+  Stage sa;            // compacted active list
+  int32_t* lq;         // local queue ring (chained mode)
+  int lq_head, lq_cnt; // wave-uniform
+  int lq_used;         // vertices peeled from the local queue this phase
+  long long edges, decr, scanned, peeled;  // per-lane statistics
+  unsigned mymin;      // per-lane min over kept vertices
+};
+
+struct PhaseOut {
+  PhaseSlot* slot;
+  int32_t* fr;  // frontier list written in this phase
+  int2* tl;     // tile list written in this phase
+};
+
+// Pushes crossed/extracted vertices: hubs are split into tiles on the global tile list, small
+// vertices go to the wave's local queue (chained mode, while it has room) or the staged frontier.
+// All lanes call.
+__device__ __forceinline__ void push_vertices(const PeelArgs& a, WaveCtx& c, const PhaseOut& o,
+                                              bool p, int32_t v, bool hub) {
+  const bool ps = p && !hub;
+  const unsigned long long ms = __ballot(ps);
+  if (ms) {
+    const int cnt = __popcll(ms);
+    if (a.chained && c.lq_cnt + cnt <= kLocalQ) {
+      if (ps) c.lq[(c.lq_head + c.lq_cnt + rank_in(ms)) & (kLocalQ - 1)] = v;
+      c.lq_cnt += cnt;
+    } else {
+      stage_push(c.sf, ps, v, &o.slot->small, o.fr, a.fcap, &a.ctl->status);
+    }
+  }
+  const bool ph = p && hub;
+  const unsigned long long mh = __ballot(ph);
+  if (mh) {
+    long long nt = 0;
+    long long deg = 0;
+    if (ph) {
+      deg = a.off[v + 1] - a.off[v];
+      nt = (deg + a.tile - 1) / a.tile;
+    }
+    const long long incl = wave_incl_scan(nt);
+    const long long tot = __shfl(incl, 63, 64);
+    unsigned long long base = 0;
+    if (lane_id() == 0) {
+      base = aadd(&o.slot->tiles, (unsigned long long)tot);
+      aadd(&o.slot->hubv, (unsigned long long)__popcll(mh));
+    }
+    base = __shfl(base, 0, 64);
+    if ((long long)base + tot > a.tcap) {
+      if (lane_id() == 0) aor(&a.ctl->status, (unsigned)KC_ERR_OVERFLOW);
+    } else if (ph) {
+      const long long s0 = (long long)base + incl - nt;
+      for (long long j = 0; j < nt; ++j) {
+        int32_t* e = reinterpret_cast<int32_t*>(&o.tl[s0 + j]);
+        ast(&e[0], v);
+        ast(&e[1], (int32_t)j);
+      }
+    }
+  }
+}
+
+// One adjacency entry per lane: the online decrement of Alg. 3. A neighbour already peeled is
+// skipped (its peeled bit is set when it is given a coreness); otherwise its induced degree is
+// decremented atomically and the lane whose decrement takes it from k+1 to k pushes it.
+__device__ __forceinline__ void edge_step(const PeelArgs& a, WaveCtx& c, const PhaseOut& o,
+                                          bool valid, int32_t u, uint32_t k) {
+  bool crossed = false;
+  bool hub = false;
+  if (valid) {
+    c.edges += 1;
+    const uint32_t sw = ald(&a.state[u >> 4]);
+    if (!((sw >> (u & 15)) & 1u)) {
+      const uint32_t old = asub(&a.dt[u], 1u);
+      c.decr += 1;
+      if ((old & DMASK) == k + 1u) {
+        crossed = true;
+        hub = (old & HUBBIT) != 0u;
+      }
+    }
+  }
+  if (crossed) {
+    a.core[u] = (int32_t)k;
+    aor(&a.state[u >> 4], 1u << (u & 15));
+    c.peeled += 1;
+  }
+  push_vertices(a, c, o, crossed, u, hub);
+}
+
+// Expands the rows of up to 64 vertices (one per lane, -1 = none) edge-balanced across the wave:
+// an exclusive scan of the degrees, then each lane finds the row of its edge by binary search.
+__device__ void expand_rows(const PeelArgs& a, WaveCtx& c, const PhaseOut& o, int32_t v, uint32_t k) {
+  long long b = 0, d = 0;
+  if (v >= 0) {
+    b = a.off[v];
+    d = a.off[v + 1] - b;
+  }
+  const long long incl = wave_incl_scan(d);
+  const long long excl = incl - d;
+  const long long total = __shfl(incl, 63, 64);
+  const int l = lane_id();
+  for (long long e0 = 0; e0 < total; e0 += 64) {
+    const long long t = e0 + l;
+    const bool valid = t < total;
+    int j = 0;
+#pragma unroll
+    for (int step = 32; step >= 1; step >>= 1) {
+      const int cand = j + step;
+      const long long ex = __shfl(excl, cand & 63, 64);
+      if (cand < 64 && ex <= t) j = cand;
+    }
+    const long long pos = __shfl(b, j, 64) + (t - __shfl(excl, j, 64));
+    const int32_t u = valid ? a.adj[pos] : 0;
+    edge_step(a, c, o, valid, u, k);
+  }
+}
+
+// A tile of a hub row: edges [off[v] + j*tile, min(off[v+1], off[v] + (j+1)*tile)).
+__device__ void expand_tile(const PeelArgs& a, WaveCtx& c, const PhaseOut& o, int32_t v, int32_t j,
+                            uint32_t k) {
+  const long long rb = a.off[v], re = a.off[v + 1];
+  const long long b = rb + (long long)j * a.tile;
+  const long long e = min(re, b + a.tile);
+  for (long long p0 = b; p0 < e; p0 += 64) {
+    const long long pos = p0 + lane_id();
+    const bool valid = pos < e;
+    const int32_t u = valid ? a.adj[pos] : 0;
+    edge_step(a, c, o, valid, u, k);
+  }
+}
+
+// Chained mode: peel what the wave queued locally, in packets of up to 64 vertices, until the
+// queue is empty or the wave's budget for this phase is spent; what is left joins the frontier.
+__device__ void drain_local(const PeelArgs& a, WaveCtx& c, const PhaseOut& o, uint32_t k) {
+  while (c.lq_cnt > 0 && c.lq_used < a.lq_budget) {
+    const int take = c.lq_cnt < 64 ? c.lq_cnt : 64;
+    const int32_t v = lane_id() < take ? c.lq[(c.lq_head + lane_id()) & (kLocalQ - 1)] : -1;
+    c.lq_head = (c.lq_head + take) & (kLocalQ - 1);
+    c.lq_cnt -= take;
+    c.lq_used += take;
+    expand_rows(a, c, o, v, k);
+  }
+  while (c.lq_cnt > 0) {
+    const int take = c.lq_cnt < 64 ? c.lq_cnt : 64;
+    const bool p = lane_id() < take;
+    const int32_t v = p ? c.lq[(c.lq_head + lane_id()) & (kLocalQ - 1)] : 0;
+    c.lq_head = (c.lq_head + take) & (kLocalQ - 1);
+    c.lq_cnt -= take;
+    stage_push(c.sf, p, v, &o.slot->small, o.fr, a.fcap, &a.ctl->status);
+  }
+}
+
+enum PhaseKind { PH_SCAN = 0, PH_EXPAND = 1 };
+
+__global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
+  __shared__ int32_t s_sf[kWaves][kStage];
+  __shared__ int32_t s_sa[kWaves][kStage];
+  __shared__ int32_t s_lq[kWaves][kLocalQ];
+  __shared__ unsigned long long s_cnt[kWaves];
+  __shared__ unsigned long long s_base;
+  __shared__ unsigned s_red[kWaves];
+  __shared__ long long s_red64[kWaves];
+
+  const int w = threadIdx.x >> 6;
+  const int l = lane_id();
+  const long long gw = (long long)blockIdx.x * kWaves + w;
+  const long long W = (long long)gridDim.x * kWaves;
+  const long long gt = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long GT = (long long)gridDim.x * blockDim.x;
+  PeelCtl* C = a.ctl;
+  const int64_t n = a.n;
+
+  WaveCtx c;
+  c.sf.buf = s_sf[w];
+  c.sf.cnt = 0;
+  c.sa.buf = s_sa[w];
+  c.sa.cnt = 0;
+  c.lq = s_lq[w];
+  c.lq_head = 0;
+  c.lq_cnt = 0;
+  c.lq_used = 0;
+  c.edges = c.decr = c.scanned = c.peeled = 0;
+  c.mymin = 0xffffffffu;
+
+  unsigned epoch = 0;
+  long long st_rounds = 0, st_sub = 0, st_bar = 0;
+  uint32_t kmax_seen = 0;
+
+  // ---- phase 0: induced degree = degree (Alg. 1 initialisation), hub flags, min degree
+  {
+    const long long nw = (n + 15) >> 4;
+    unsigned mn = 0xffffffffu;
+    for (long long wd = gt; wd < nw; wd += GT) {
+      uint32_t bits = 0;
+      for (int j = 0; j < 16; ++j) {
+        const long long v = wd * 16 + j;
+        if (v >= n) break;
+        const long long d = a.off[v + 1] - a.off[v];
+        const bool hub = d >= (long long)a.hub;
+        ast(&a.dt[v], (uint32_t)d | (hub ? HUBBIT : 0u));
+        bits |= (hub ? 1u : 0u) << (16 + j);
+        mn = min(mn, (unsigned)d);
+      }
+      ast(&a.state[wd], bits);
+    }
+    mn = wave_min(mn);
+    if (l == 0) s_red[w] = mn;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      unsigned m = 0xffffffffu;
+      for (int i = 0; i < kWaves; ++i) m = min(m, s_red[i]);
+      if (m < ald(&C->slot[0].minv)) amin(&C->slot[0].minv, m);
+    }
+  }
+  if (!grid_sync(C, epoch)) return;
+  st_bar++;
+
+  long long kprev = -1;                      // every vertex with induced degree <= kprev is peeled
+  long long kx = (long long)ald(&C->slot[0].minv);  // round being extracted or expanded
+  int kind = PH_SCAN;
+  bool dense = true, compact = false;
+  long long asize = n;
+  int acur = 0;
+  long long removed_since = 0, total_peeled = 0;
+  long long fs = 0, ft = 0;
+  const long long max_phases = 4 * n + 64;
+
+  for (long long p = 1;; ++p) {
+    if (p > max_phases) {
+      if (threadIdx.x == 0) aor(&C->status, (unsigned)KC_ERR_PHASES);
+      break;
+    }
+    PhaseOut o;
+    o.slot = &C->slot[p % 3];
+    o.fr = a.fr[p & 1];
+    o.tl = a.tl[p & 1];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      PhaseSlot* r = &C->slot[(p + 1) % 3];
+      ast(&r->small, 0ull);
+      ast(&r->tiles, 0ull);
+      ast(&r->hubv, 0ull);
+      ast(&r->active, 0ull);
+      ast(&r->peeled, 0ull);
+      ast(&r->minv, 0xffffffffu);
+    }
+    const uint32_t k = (uint32_t)kx;
+    c.lq_used = 0;
+    long long peeled_before = c.peeled;
+    if (kind == PH_SCAN) {
+      // Alg. 1: F = {v in A : induced degree <= k}; survivors refine A.
+      int32_t* alist = a.act[acur];
+      int32_t* anext = a.act[acur ^ 1];
+      for (long long i0 = gw * 64; i0 < asize; i0 += W * 64) {
+        const long long i = i0 + l;
+        const bool valid = i < asize;
+        int32_t v = -1;
+        if (valid) v = dense ? (int32_t)i : ald(&alist[i]);
+        uint32_t word = 0, x = 0;
+        if (valid) {
+          word = ald(&a.dt[v]);
+          x = word & DMASK;
+          c.scanned += 1;
+        }
+        const bool alive = valid && (long long)x > kprev;
+        const bool ext = alive && (long long)x <= kx;
+        const bool keep = alive && (long long)x > kx;
+        if (keep) c.mymin = min(c.mymin, x);
+        if (compact) stage_push(c.sa, keep, v, &o.slot->active, anext, n, &C->status);
+        if (ext) {
+          a.core[v] = (int32_t)k;
+          aor(&a.state[v >> 4], 1u << (v & 15));
+          c.peeled += 1;
+        }
+        push_vertices(a, c, o, ext, v, (word & HUBBIT) != 0u);
+      }
+    } else {
+      // Alg. 3 over the frontier: packets of 64 small vertices, then hub tiles.
+      const int32_t* fcur = a.fr[(p - 1) & 1];
+      const int2* tcur = a.tl[(p - 1) & 1];
+      const long long npk = (fs + 63) >> 6;
+      const long long items = npk + ft;
+      for (long long it = gw; it < items; it += W) {
+        if (it < npk) {
+          const long long i = it * 64 + l;
+          const int32_t v = i < fs ? ald(&fcur[i]) : -1;
+          expand_rows(a, c, o, v, k);
+        } else {
+          const int32_t* e = reinterpret_cast<const int32_t*>(&tcur[it - npk]);
+          const int32_t v = ald(&e[0]);
+          const int32_t j = ald(&e[1]);
+          expand_tile(a, c, o, v, j, k);
+        }
+      }
+    }
+    if (a.chained) drain_local(a, c, o, k);
+
+    // ---- phase end: block-level flushes and reductions
+    block_flush(c.sf, &o.slot->small, o.fr, a.fcap, &C->status, s_cnt, &s_base);
+    if (kind == PH_SCAN && compact)
+      block_flush(c.sa, &o.slot->active, a.act[acur ^ 1], n, &C->status, s_cnt, &s_base);
+    {
+      const unsigned mn = wave_min(c.mymin);
+      long long pc = c.peeled - peeled_before;
+      for (int off = 32; off > 0; off >>= 1) pc += __shfl_xor(pc, off, 64);
+      if (l == 0) {
+        s_red[w] = mn;
+        s_red64[w] = pc;
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        unsigned m = 0xffffffffu;
+        long long tp = 0;
+        for (int i = 0; i < kWaves; ++i) {
+          m = min(m, s_red[i]);
+          tp += s_red64[i];
+        }
+        if (m < ald(&o.slot->minv)) amin(&o.slot->minv, m);
+        if (tp) aadd(&o.slot->peeled, (unsigned long long)tp);
+      }
+      c.mymin = 0xffffffffu;
+    }
+    if (!grid_sync(C, epoch)) break;
+    st_bar++;
+
+    // ---- decide the next phase (identical in every workgroup)
+    const long long nfs = (long long)ald(&o.slot->small);
+    const long long nft = (long long)ald(&o.slot->tiles);
+    const long long nact = (long long)ald(&o.slot->active);
+    const unsigned mv = ald(&o.slot->minv);
+    const long long npeel = (long long)ald(&o.slot->peeled);
+    if (nfs > a.fcap || nft > a.tcap || nact > n) {
+      // a list overflowed (its entries were not written): stop before reading them
+      if (threadIdx.x == 0) aor(&C->status, (unsigned)KC_ERR_OVERFLOW);
+      break;
+    }
+    total_peeled += npeel;
+    removed_since += npeel;
+    if (kind == PH_EXPAND) st_sub++;
+    if (npeel > 0) kmax_seen = k;
+    if (kind == PH_SCAN && compact) {
+      asize = nact;
+      acur ^= 1;
+      dense = false;
+      removed_since = npeel;
+    }
+    if (kind == PH_SCAN) {
+      if (npeel > 0) st_rounds++;
+      if (nfs + nft > 0) {
+        kind = PH_EXPAND;
+        fs = nfs;
+        ft = nft;
+      } else if (total_peeled >= n) {
+        break;
+      } else if (npeel > 0) {
+        // the round completed inside the scan (chained mode)
+        kprev = kx;
+        kx = kx + 1;
+        compact = removed_since * 8 >= asize;
+      } else {
+        // no live vertex has induced degree <= kx: jump to the smallest one (next non-empty round)
+        if (mv == 0xffffffffu) {
+          if (threadIdx.x == 0) aor(&C->status, (unsigned)KC_ERR_PHASES);
+          break;
+        }
+        kx = (long long)mv;
+        compact = false;
+      }
+    } else {
+      if (nfs + nft > 0) {
+        fs = nfs;
+        ft = nft;
+      } else if (total_peeled >= n) {
+        break;
+      } else {
+        kprev = kx;
+        kx = kx + 1;
+        kind = PH_SCAN;
+        compact = removed_since * 8 >= asize;
+      }
+    }
+  }
+
+  // ---- statistics: per-lane counters reduced per block, one atomic each per block
+  {
+    long long v4[4] = {c.edges, c.decr, c.scanned, c.peeled};
+    for (int q = 0; q < 4; ++q) {
+      long long x = v4[q];
+      for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+      if (l == 0) s_red64[w] = x;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        long long t = 0;
+        for (int i = 0; i < kWaves; ++i) t += s_red64[i];
+        const int idx = q == 0 ? ST_EDGES : q == 1 ? ST_DECR : q == 2 ? ST_SCANNED : ST_PEELED;
+        if (t) aadd(&C->stats[idx], (unsigned long long)t);
+      }
+      __syncthreads();
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      ast(&C->stats[ST_ROUNDS], (unsigned long long)st_rounds);
+      ast(&C->stats[ST_SUBROUNDS], (unsigned long long)st_sub);
+      ast(&C->stats[ST_BARRIERS], (unsigned long long)st_bar);
+      ast(&C->stats[ST_KMAX], (unsigned long long)kmax_seen);
+    }
+  }
+}
+
+hipError_t launch_peel(const PeelArgs& a, int blocks, hipStream_t s) {
+  void* args[] = {const_cast<PeelArgs*>(&a)};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(peel_kernel), dim3(blocks),
+                                    dim3(kPeelThreads), args, 0, s);
+}
+
+hipError_t peel_occupancy(int* blocks_per_cu) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, peel_kernel, kPeelThreads, 0);
+}
+
+// ------------------------------------------------------------------------------------------
+// Batched peel: one workgroup per graph, graphs claimed largest-first from a shared counter.
+// Induced degrees and the peel queue live in LDS when the graph fits (lds_cap vertices), else in
+// the global workspace at the graph's own vertex range; either way only this workgroup touches
+// them, so decrements are workgroup-scope atomics and every (sub)round ends at __syncthreads.
+// The queue holds vertices in peel order; since each vertex is peeled once, n slots suffice and
+// the current frontier is always the queue segment between two marks.
+// ------------------------------------------------------------------------------------------
+template <class T>
+__device__ __forceinline__ T wsub(T* p, T v) {
+  return __hip_atomic_fetch_sub(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ long long block_excl_scan(long long x, long long* s_w, long long& total) {
+  const int w = threadIdx.x >> 6, l = lane_id();
+  const long long incl = wave_incl_scan(x);
+  if (l == 63) s_w[w] = incl;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long t = 0;
+    for (int i = 0; i < kBatchThreads / 64; ++i) {
+      const long long c = s_w[i];
+      s_w[i] = t;
+      t += c;
+    }
+    s_w[kBatchThreads / 64] = t;
+  }
+  __syncthreads();
+  total = s_w[kBatchThreads / 64];
+  const long long r = s_w[w] + incl - x;
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ void team_push(bool p, int32_t v, int32_t* q, int* s_tail) {
+  const unsigned long long m = __ballot(p);
+  if (!m) return;
+  int base = 0;
+  if (lane_id() == 0) base = atomicAdd(s_tail, __popcll(m));
+  base = __shfl(base, 0, 64);
+  if (p) q[base + rank_in(m)] = v;
+}
+
+__global__ __launch_bounds__(kBatchThreads) void batched_kernel(BatchArgs a) {
+  extern __shared__ uint32_t s_dyn[];
+  __shared__ long long s_pref[kBatchThreads];
+  __shared__ long long s_rb[kBatchThreads];
+  __shared__ long long s_w[kBatchThreads / 64 + 1];
+  __shared__ unsigned s_min[kBatchThreads / 64];
+  __shared__ int s_tail;
+  __shared__ long long s_g;
+
+  long long st_edges = 0, st_decr = 0, st_rounds = 0, st_sub = 0, st_scanned = 0;
+  unsigned kmax_all = 0;
+  const int tid = threadIdx.x, l = lane_id(), w = threadIdx.x >> 6;
+
+  for (;;) {
+    if (tid == 0) s_g = (long long)aadd(&a.ctl->next, 1ull);
+    __syncthreads();
+    const long long gi = s_g;
+    __syncthreads();
+    if (gi >= a.G) break;
+    const int32_t g = a.order ? a.order[gi] : (int32_t)gi;
+    const int64_t base = a.vptr[g];
+    const int64_t ng = a.vptr[g + 1] - base;
+    if (ng <= 0) continue;
+    const bool inl = ng <= a.lds_cap;
+    uint32_t* d = inl ? s_dyn : a.gdt + base;
+    int32_t* q = inl ? reinterpret_cast<int32_t*>(s_dyn + a.lds_cap) : a.gq + base;
+    const int64_t* off = a.off + base;
+
+    // induced degree = degree; k = min degree
+    unsigned mn = 0xffffffffu;
+    for (long long i = tid; i < ng; i += kBatchThreads) {
+      const unsigned dg = (unsigned)(off[i + 1] - off[i]);
+      d[i] = dg;
+      mn = min(mn, dg);
+    }
+    mn = wave_min(mn);
+    if (l == 0) s_min[w] = mn;
+    if (tid == 0) s_tail = 0;
+    __syncthreads();
+    unsigned k = 0xffffffffu;
+    for (int i = 0; i < kBatchThreads / 64; ++i) k = min(k, s_min[i]);
+    __syncthreads();
+
+    int head = 0;
+    bool scan_eq = true;  // extraction test: at round start every live vertex has d >= k
+    for (;;) {
+      // extraction of round k's first frontier; also the min over the others for a jump
+      unsigned nm = 0xffffffffu;
+      for (long long i0 = 0; i0 < ng; i0 += kBatchThreads) {
+        const long long i = i0 + tid;
+        bool ext = false;
+        if (i < ng) {
+          const unsigned x = d[i];
+          st_scanned++;
+          ext = x == k;
+          if (x > k) nm = min(nm, x);
+        }
+        team_push(ext, (int32_t)i, q, &s_tail);
+        if (ext) a.core[base + i] = (int32_t)k;
+      }
+      (void)scan_eq;
+      nm = wave_min(nm);
+      if (l == 0) s_min[w] = nm;
+      __syncthreads();
+      int tail = s_tail;
+      unsigned nextmin = 0xffffffffu;
+      for (int i = 0; i < kBatchThreads / 64; ++i) nextmin = min(nextmin, s_min[i]);
+      __syncthreads();
+      if (tail == head) {
+        // empty round: jump to the next non-empty one
+        if (nextmin == 0xffffffffu) break;
+        k = nextmin;
+        continue;
+      }
+      st_rounds++;
+      if (k > kmax_all) kmax_all = k;
+      // subrounds: frontier = q[head, tail)
+      while (head < tail) {
+        st_sub++;
+        for (long long c0 = head; c0 < tail; c0 += kBatchThreads) {
+          const long long i = c0 + tid;
+          long long dg = 0, rb = 0;
+          if (i < tail) {
+            const int32_t v = q[i];
+            rb = off[v];
+            dg = off[v + 1] - rb;
+          }
+          long long total;
+          const long long ex = block_excl_scan(dg, s_w, total);
+          s_pref[tid] = ex;
+          s_rb[tid] = rb;
+          __syncthreads();
+          for (long long e0 = 0; e0 < total; e0 += kBatchThreads) {
+            const long long t = e0 + tid;
+            bool crossed = false;
+            int32_t ul = 0;
+            if (t < total) {
+              int lo = 0, hi = kBatchThreads - 1;  // largest j with s_pref[j] <= t
+              while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_pref[mid] <= t) lo = mid; else hi = mid - 1;
+              }
+              const long long pos = s_rb[lo] + (t - s_pref[lo]);
+              ul = a.adj[pos] - (int32_t)base;
+              st_edges++;
+              if (d[ul] > k) {
+                const unsigned old = inl ? atomicSub(&d[ul], 1u) : wsub(&d[ul], 1u);
+                st_decr++;
+                crossed = old == k + 1;
+              }
+            }
+            team_push(crossed, ul, q, &s_tail);
+            if (crossed) a.core[base + ul] = (int32_t)k;
+          }
+          __syncthreads();
+        }
+        head = tail;
+        tail = s_tail;
+        __syncthreads();
+      }
+      if (tail >= ng) break;
+      k = k + 1;
+    }
+    __syncthreads();
+  }
+  // statistics
+  long long v5[5] = {st_edges, st_decr, st_scanned, 0, 0};
+  for (int qd = 0; qd < 3; ++qd) {
+    long long x = v5[qd];
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    if (l == 0 && x) aadd(&a.ctl->stats[qd == 0 ? ST_EDGES : qd == 1 ? ST_DECR : ST_SCANNED], (unsigned long long)x);
+  }
+  if (tid == 0) {
+    if (st_rounds) aadd(&a.ctl->stats[ST_ROUNDS], (unsigned long long)st_rounds);
+    if (st_sub) aadd(&a.ctl->stats[ST_SUBROUNDS], (unsigned long long)st_sub);
+    __hip_atomic_fetch_max(&a.ctl->stats[ST_KMAX], (unsigned long long)kmax_all, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+hipError_t launch_batched(const BatchArgs& a, int blocks, size_t lds_bytes, hipStream_t s) {
+  hipLaunchKernelGGL(batched_kernel, dim3(blocks), dim3(kBatchThreads), lds_bytes, s, a);
+  return hipGetLastError();
+}
+
+hipError_t batched_occupancy(size_t lds_bytes, int* blocks_per_cu) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batched_kernel, kBatchThreads,
+                                                      lds_bytes);
+}
+
+// Largest-first order of the graphs of a batch: counting sort on floor(log2(edges + 1)),
+// descending, in a single workgroup (order inside a size class is arbitrary).
+__global__ __launch_bounds__(1024) void order_kernel(const int64_t* vptr, const int64_t* off, int32_t G,
+                                                     int32_t* order) {
+  __shared__ int s_cnt[64];
+  if (threadIdx.x < 64) s_cnt[threadIdx.x] = 0;
+  __syncthreads();
+  for (int g = threadIdx.x; g < G; g += blockDim.x) {
+    const long long m = off[vptr[g + 1]] - off[vptr[g]];
+    atomicAdd(&s_cnt[63 - __clzll(m + 1)], 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int b = 63; b >= 0; --b) {
+      const int c = s_cnt[b];
+      s_cnt[b] = t;
+      t += c;
+    }
+  }
+  __syncthreads();
+  for (int g = threadIdx.x; g < G; g += blockDim.x) {
+    const long long m = off[vptr[g + 1]] - off[vptr[g]];
+    order[atomicAdd(&s_cnt[63 - __clzll(m + 1)], 1)] = g;
+  }
+}
+
+hipError_t launch_order(const int64_t* vptr, const int64_t* off, int32_t G, int32_t* order,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(order_kernel, dim3(1), dim3(1024), 0, s, vptr, off, G, order);
+  return hipGetLastError();
+}
+
+__global__ void fill_u32_kernel(uint32_t* p, uint32_t v, size_t count) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void init_ctl_kernel(PeelCtl* c) {
+  uint32_t* w = reinterpret_cast<uint32_t*>(c);
+  for (size_t i = threadIdx.x; i < sizeof(PeelCtl) / 4; i += blockDim.x) w[i] = 0u;
+  __syncthreads();
+  if (threadIdx.x < 3) c->slot[threadIdx.x].minv = 0xffffffffu;
+}
+
+hipError_t launch_init_ctl(PeelCtl* c, hipStream_t s) {
+  hipLaunchKernelGGL(init_ctl_kernel, dim3(1), dim3(256), 0, s, c);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(void* p, uint32_t v, size_t count, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  size_t blocks = (count + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)blocks), dim3(256), 0, s,
+                     static_cast<uint32_t*>(p), v, count);
+  return hipGetLastError();
+}
+
+// Input check: offsets start at 0 and never decrease, ids are in range (within the own graph for a
+// batch), no self-loops, and every edge appears in both directions (an XOR-sum over a symmetric
+// hash of each entry's endpoints cancels exactly when every entry has its reverse, up to hash
+// collisions). Duplicates are not detected.
+__device__ __forceinline__ unsigned long long pair_hash(unsigned a, unsigned b) {
+  unsigned long long lo = a < b ? a : b, hi = a < b ? b : a;
+  unsigned long long x = (hi << 32) | lo;
+  x ^= x >> 33;
+  x *= 0xff51afd7ed558ccdull;
+  x ^= x >> 33;
+  x *= 0xc4ceb9fe1a85ec53ull;
+  x ^= x >> 33;
+  return x;
+}
+
+__global__ void validate_kernel(const int64_t* off, const int32_t* adj, int64_t n, const int64_t* vptr,
+                                int32_t G, unsigned* status, unsigned long long* xsum) {
+  const long long gt = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  const long long GT = (long long)gridDim.x * blockDim.x;
+  if (gt == 0 && off[0] != 0) atomicOr(status, (unsigned)KC_ERR_BADGRAPH);
+  unsigned long long acc = 0;
+  for (long long v = gt; v < n; v += GT) {
+    const long long b = off[v], e = off[v + 1];
+    if (e < b) {
+      atomicOr(status, (unsigned)KC_ERR_BADGRAPH);
+      continue;
+    }
+    long long lo = 0, hi = n;
+    if (vptr) {
+      int l = 0, h = G - 1;  // graph of v: largest g with vptr[g] <= v
+      while (l < h) {
+        const int mid = (l + h + 1) >> 1;
+        if (vptr[mid] <= v) l = mid; else h = mid - 1;
+      }
+      lo = vptr[l];
+      hi = vptr[l + 1];
+    }
+    for (long long p = b; p < e; ++p) {
+      const int32_t u = adj[p];
+      if (u < lo || u >= hi || u == v) {
+        atomicOr(status, (unsigned)KC_ERR_BADGRAPH);
+        break;
+      }
+      acc ^= pair_hash((unsigned)v, (unsigned)u);
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) acc ^= __shfl_xor(acc, o, 64);
+  if (lane_id() == 0 && acc) atomicXor(xsum, acc);
+}
+
+hipError_t launch_validate(const int64_t* off, const int32_t* adj, int64_t n, const int64_t* vptr,
+                           int32_t G, unsigned* status, unsigned long long* xsum, hipStream_t s) {
+  hipLaunchKernelGGL(validate_kernel, dim3(2048), dim3(256), 0, s, off, adj, n, vptr, G, status, xsum);
+  return hipGetLastError();
+}
+
+}  // namespace kc

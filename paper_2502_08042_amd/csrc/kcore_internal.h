@@ -1,0 +1,100 @@
+// Internal declarations shared by the device code and the host-side C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace kc {
+
+constexpr int kPeelThreads = 1024;   // threads per persistent workgroup (16 waves)
+constexpr int kWaves = kPeelThreads / 64;
+constexpr int kStage = 256;          // per-wave LDS staging entries for frontier appends
+constexpr int kLocalQ = 512;         // per-wave local queue (chained mode)
+constexpr int kCombSlots = 2048;     // per-workgroup LDS combining table for hub targets
+constexpr int kBarGroups = 32;       // arrival groups of the grid barrier
+constexpr int kBatchThreads = 512;   // threads per workgroup of the batched peel
+
+enum StatIdx {
+  ST_ROUNDS = 0, ST_SUBROUNDS, ST_BARRIERS, ST_PEELED, ST_EDGES, ST_DECR, ST_COMBINED, ST_SCANNED,
+  ST_KMAX, ST_NUM
+};
+
+// Counters produced during one phase (three-way rotation, see the peel kernel).
+struct alignas(128) PhaseSlot {
+  unsigned long long small;   // next small-vertex frontier tail
+  unsigned long long tiles;   // next hub-tile list tail
+  unsigned long long hubv;    // hub vertices pushed
+  unsigned long long active;  // compacted active-list tail
+  unsigned long long peeled;  // vertices given a coreness in the phase
+  unsigned int minv;          // min induced degree over vertices kept by a scan
+  unsigned int pad[5];
+};
+
+struct alignas(128) PeelCtl {
+  unsigned int bar_gen;
+  unsigned int pad0[31];
+  unsigned int bar_top;
+  unsigned int pad1[31];
+  unsigned int bar_grp[kBarGroups][32];
+  PhaseSlot slot[3];
+  unsigned int status;        // error bits (KC_ERR_*)
+  unsigned int pad2[31];
+  unsigned long long stats[16];
+};
+
+enum : unsigned { KC_ERR_TIMEOUT = 1u, KC_ERR_OVERFLOW = 2u, KC_ERR_PHASES = 4u, KC_ERR_BADGRAPH = 8u };
+
+struct PeelArgs {
+  const int64_t* off;
+  const int32_t* adj;
+  int64_t n;
+  int32_t* core;
+  uint32_t* dt;        // induced degree, bit 31 = hub flag
+  uint32_t* state;     // per 16 vertices: bits 0..15 peeled, 16..31 hub
+  int32_t* act[2];     // compacted active lists
+  int32_t* fr[2];      // small-vertex frontiers
+  int2* tl[2];         // hub tiles (vertex, tile index)
+  int64_t fcap;        // frontier capacity (entries)
+  int64_t tcap;        // tile list capacity
+  PeelCtl* ctl;
+  uint32_t hub;        // hub degree threshold
+  int32_t tile;        // edges per tile (multiple of 64)
+  int32_t chained;     // 1: local queues (chained mode)
+  int32_t lq_budget;   // max vertices a wave peels from its local queue per phase
+};
+
+struct BatchCtl {
+  unsigned long long next;
+  unsigned int status;
+  unsigned int pad[29];
+  unsigned long long stats[16];
+};
+
+struct BatchArgs {
+  const int64_t* vptr;
+  const int64_t* off;
+  const int32_t* adj;
+  int32_t G;
+  int32_t* core;
+  const int32_t* order;   // processing order (largest first)
+  uint32_t* gdt;          // global induced degrees for graphs beyond the LDS capacity
+  int32_t* gq;            // global peel queues for those graphs
+  BatchCtl* ctl;
+  int32_t lds_cap;        // vertices per graph held in LDS
+};
+
+// Error text returned by kcore_last_error (thread-local; defined in kcore_api.cpp).
+void set_error(const char* msg);
+
+// Launch helpers (defined in kcore_device.hip).
+hipError_t launch_peel(const PeelArgs& a, int blocks, hipStream_t s);
+hipError_t peel_occupancy(int* blocks_per_cu);
+hipError_t launch_batched(const BatchArgs& a, int blocks, size_t lds_bytes, hipStream_t s);
+hipError_t batched_occupancy(size_t lds_bytes, int* blocks_per_cu);
+hipError_t launch_order(const int64_t* vptr, const int64_t* off, int32_t G, int32_t* order,
+                        hipStream_t s);
+hipError_t launch_fill_u32(void* p, uint32_t v, size_t count, hipStream_t s);
+hipError_t launch_init_ctl(PeelCtl* c, hipStream_t s);
+hipError_t launch_validate(const int64_t* off, const int32_t* adj, int64_t n, const int64_t* vptr,
+                           int32_t G, unsigned* status, unsigned long long* xsum, hipStream_t s);
+
+}  // namespace kc

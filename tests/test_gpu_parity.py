@@ -1,0 +1,154 @@
+"""GPU parity: the HIP library against the CPU oracle, element by element (coreness is exact).
+
+Every case prints its name before touching the GPU so that a failing run names it.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+import graphs as G
+from gpu_util import say, run_single, run_batched, first_mismatch
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+MODES = ["levelsync", "chained"]
+
+
+def small_cases():
+    yield "K1", G.csr(1, [])
+    yield "isolated7", G.csr(7, [])
+    yield "K2", G.complete(2)
+    yield "K30", G.complete(30)
+    yield "C100", G.cycle(100)
+    yield "P101", G.path(101)
+    yield "star64", G.star(64)
+    yield "grid31", G.grid(31)
+    yield "cube6", G.cube(6)
+    yield "K7,3", G.complete_bipartite(7, 3)
+    yield "Q6", G.hypercube(6)
+    yield "petersen", G.petersen()
+    yield "hcns40", G.hcns(40)
+    yield "union", G.union([G.complete(5), G.cycle(7), G.grid(4), G.star(3), G.hcns(6), G.csr(3, [])])
+    for f in sorted(os.listdir(os.path.join(HERE, "golden"))):
+        if f.endswith(".json"):
+            fx = json.load(open(os.path.join(HERE, "golden", f)))
+            yield f, G.csr(fx["n"], fx["edges"])
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_small_graphs(mode):
+    for name, (off, adj) in small_cases():
+        say(f"[gpu] small {name} mode={mode} n={len(off) - 1} m={len(adj)}")
+        got, st = run_single(off, adj, mode=mode)
+        want = oracle.bz(off, adj)
+        assert not first_mismatch(got, want), f"{name}: {first_mismatch(got, want)}"
+        assert st["peeled"] == len(off) - 1, (name, st)
+        assert st["edges"] == len(adj), (name, st)
+        assert st["device_status"] == 0
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("which", ["rmat12", "er3000", "road128", "hcns200", "rmat16"])
+def test_medium_graphs(mode, which):
+    if which == "rmat12":
+        g = gg.rmat(12, 16, 11)
+        off, adj = g.offsets, g.adj
+    elif which == "er3000":
+        g = gg.erdos_renyi(3000, 0.004, 5)
+        off, adj = g.offsets, g.adj
+    elif which == "road128":
+        g = gg.grid_road(128, 0.05, 0.01, 2)
+        off, adj = g.offsets, g.adj
+    elif which == "hcns200":
+        off, adj = G.hcns(200)
+    else:
+        g = gg.config_rmat16()
+        off, adj = g.offsets, g.adj
+    say(f"[gpu] medium {which} mode={mode} n={len(off) - 1} m={len(adj)}")
+    got, st = run_single(off, adj, mode=mode)
+    want, sub, ls = oracle.levelsync(off, adj)
+    assert not first_mismatch(got, want), first_mismatch(got, want)
+    assert st["peeled"] == len(off) - 1 and st["edges"] == len(adj)
+    assert st["rounds"] == ls["nonempty_rounds"], (st, ls)
+    assert st["kmax"] == int(want.max())
+    if mode == "levelsync":
+        # Alg. 1 + Alg. 3 frontiers are order independent: the subround count must equal the
+        # sequential framework's rho
+        assert st["subrounds"] == ls["subrounds"], (st, ls)
+    else:
+        assert st["subrounds"] <= ls["subrounds"]
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_tuning_knobs_do_not_change_results(mode):
+    g = gg.rmat(13, 16, 7)
+    want = oracle.bz(g.offsets, g.adj)
+    for hub, tile, budget, bpc in ((8, 64, 1, 1), (64, 128, 64, 1), (1 << 30, 1024, 100000, 0)):
+        say(f"[gpu] knobs mode={mode} hub={hub} tile={tile} budget={budget}")
+        got, st = run_single(g.offsets, g.adj, mode=mode, hub_degree=hub, tile_edges=tile,
+                             local_budget=budget, blocks_per_cu=bpc)
+        assert not first_mismatch(got, want), first_mismatch(got, want)
+
+
+def test_batched_small():
+    b = gg.batch(64, 4, hi=20000)
+    say(f"[gpu] batched 64 graphs V={b.n} m={b.m}")
+    got, st = run_batched(b.offsets, b.adj, b.vptr)
+    want = oracle.bz(b.offsets, b.adj)
+    assert not first_mismatch(got, want), first_mismatch(got, want)
+    assert st["edges"] == b.m
+
+
+def test_batched_equals_per_graph_and_handles_empty_graphs():
+    parts = [G.complete(9), G.csr(0, []), G.csr(5, []), G.hcns(30), G.grid(12), G.csr(1, [])]
+    off, adj = G.union(parts)
+    vptr = np.cumsum([0] + [len(p[0]) - 1 for p in parts]).astype(np.int64)
+    say(f"[gpu] batched with empty graphs V={len(off) - 1}")
+    got, _ = run_batched(off, adj, vptr)
+    want = np.concatenate([oracle.bz(*p) for p in parts])
+    assert not first_mismatch(got, want), first_mismatch(got, want)
+
+
+def test_batched_large_graph_in_global_memory():
+    # graphs above the LDS capacity keep their state in the global workspace
+    parts = [(gg.rmat(15, 8, 3).offsets, gg.rmat(15, 8, 3).adj), G.complete(40),
+             (gg.grid_road(200, 0.05, 0.01, 9).offsets, gg.grid_road(200, 0.05, 0.01, 9).adj)]
+    off, adj = G.union(parts)
+    vptr = np.cumsum([0] + [len(p[0]) - 1 for p in parts]).astype(np.int64)
+    say(f"[gpu] batched large graphs V={len(off) - 1} m={len(adj)}")
+    got, _ = run_batched(off, adj, vptr)
+    want = oracle.bz(off, adj)
+    assert not first_mismatch(got, want), first_mismatch(got, want)
+
+
+def test_repeat_is_deterministic():
+    g = gg.rmat(14, 16, 5)
+    say("[gpu] repeat x5 levelsync rmat14")
+    res = [run_single(g.offsets, g.adj, mode="levelsync") for _ in range(5)]
+    for core, st in res[1:]:
+        assert np.array_equal(core, res[0][0])
+        assert st["subrounds"] == res[0][1]["subrounds"]
+
+
+def test_validate_rejects_bad_csr():
+    import paper_2502_08042_amd as K
+    from gpu_util import to_dev
+    off, adj = G.cycle(10)
+    say("[gpu] validate good/bad")
+    d_off, d_adj = to_dev(off, adj)
+    K.decompose(d_off, d_adj, validate=True)
+    bad = adj.copy()
+    bad[0] = 5  # 0-5 entry without its reverse
+    d_off, d_adj = to_dev(off, bad)
+    with pytest.raises(K.KcoreError) as e:
+        K.decompose(d_off, d_adj, validate=True)
+    assert e.value.code == -7
+    loop = adj.copy()
+    loop[0] = 0
+    d_off, d_adj = to_dev(off, loop)
+    with pytest.raises(K.KcoreError):
+        K.decompose(d_off, d_adj, validate=True)
