@@ -22,8 +22,21 @@
 #include <new>
 #include <vector>
 #include <omp.h>
+#include <chrono>
+#include <cstdio>
 
 namespace {
+
+struct Timer {
+  const char* what;
+  std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+  explicit Timer(const char* w) : what(w) {}
+  ~Timer() {
+    if (std::getenv("GG_VERBOSE"))
+      std::fprintf(stderr, "[graphgen] %s %.3f s\n", what,
+                   std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
+  }
+};
 
 inline uint64_t splitmix64(uint64_t x) {
   x += 0x9E3779B97F4A7C15ull;
@@ -52,6 +65,7 @@ void build_csr(int64_t n, const std::vector<int32_t>& src, const std::vector<int
   const int64_t P = (int64_t)src.size();
   std::vector<int64_t> cnt(n + 1, 0);
   {
+    Timer t_("csr count");
     std::atomic<int64_t>* c = reinterpret_cast<std::atomic<int64_t>*>(cnt.data());
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < P; ++i) {
@@ -65,6 +79,7 @@ void build_csr(int64_t n, const std::vector<int32_t>& src, const std::vector<int
   for (int64_t v = 0; v < n; ++v) start[v + 1] = start[v] + cnt[v];
   std::vector<int32_t> tmp((size_t)start[n]);
   {
+    Timer t_("csr scatter");
     std::vector<int64_t> cur(start.begin(), start.end() - 1);
     std::atomic<int64_t>* c = reinterpret_cast<std::atomic<int64_t>*>(cur.data());
 #pragma omp parallel for schedule(static)
@@ -76,6 +91,7 @@ void build_csr(int64_t n, const std::vector<int32_t>& src, const std::vector<int
     }
   }
   std::vector<int64_t> ndeg(n, 0);
+  Timer t_sort("csr sort+copy");
 #pragma omp parallel for schedule(dynamic, 4096)
   for (int64_t v = 0; v < n; ++v) {
     int32_t* b = tmp.data() + start[v];
@@ -235,8 +251,26 @@ struct Alias {
 // endpoint pairs are drawn independently proportional to those weights. A dense block of block_n
 // distinct vertices (uniform over [0,n)) is planted with every block pair present with
 // probability block_p.
-void gen_chung_lu(int64_t n, double gamma, int64_t pairs, int64_t max_deg, int64_t block_n,
-                  double block_p, uint64_t seed, Csr& g) {
+// Block pair index t -> (a, b), a < b, row-major over the strict upper triangle of block positions.
+inline void block_pair(int64_t t, int64_t block_n, int64_t& a, int64_t& b) {
+  const double B = (double)block_n;
+  a = (int64_t)std::floor((2 * B - 1 - std::sqrt((2 * B - 1) * (2 * B - 1) - 8.0 * (double)t)) / 2);
+  if (a < 0) a = 0;
+  auto row_start = [&](int64_t r) { return r * (2 * block_n - r - 1) / 2; };
+  while (a > 0 && row_start(a) > t) --a;
+  while (row_start(a + 1) <= t) ++a;
+  b = a + 1 + (t - row_start(a));
+}
+
+// Chung-Lu: expected degree of vertex i proportional to (i+1)^(-1/(gamma-1)), scaled so the
+// expected degrees sum to 2*pairs, each capped at max_deg (scale found by bisection). `pairs`
+// endpoint pairs are drawn independently proportional to those weights (alias method). A dense
+// block of block_n distinct vertices (uniform over [0,n)) is planted with every block pair present
+// with probability block_p.
+void chung_lu_setup(int64_t n, double gamma, int64_t pairs, int64_t max_deg, int64_t block_n,
+                    double block_p, uint64_t seed, Alias& al, std::vector<int32_t>& blk,
+                    std::vector<int64_t>& bsel) {
+  Timer t_setup("chung-lu setup");
   std::vector<double> w(n);
   const double ex = -1.0 / (gamma - 1.0);
 #pragma omp parallel for schedule(static)
@@ -256,10 +290,12 @@ void gen_chung_lu(int64_t n, double gamma, int64_t pairs, int64_t max_deg, int64
   }
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; ++i) w[i] = std::min(hi * w[i], (double)max_deg);
-  Alias al;
-  al.build(w);
+  {
+    Timer t_("alias");
+    al.build(w);
+  }
   // block members: the first block_n distinct values of a uniform draw sequence
-  std::vector<int32_t> blk;
+  blk.clear();
   {
     std::vector<char> used(block_n > 0 ? n : 0, 0);
     for (uint64_t t = 0; (int64_t)blk.size() < block_n; ++t) {
@@ -270,39 +306,46 @@ void gen_chung_lu(int64_t n, double gamma, int64_t pairs, int64_t max_deg, int64
     }
   }
   const int64_t bpairs = block_n * (block_n - 1) / 2;
-  std::vector<int64_t> bsel;
+  bsel.clear();
   if (bpairs > 0) {
-    // pair index t -> (a, b) with a < b over block positions; keep with probability block_p
+    const uint64_t key = stream_key(seed, 22);
     std::vector<std::vector<int64_t>> part(omp_get_max_threads());
 #pragma omp parallel
     {
       auto& mine = part[omp_get_thread_num()];
 #pragma omp for schedule(static)
       for (int64_t t = 0; t < bpairs; ++t)
-        if (u01(rnd(seed, 22, (uint64_t)t)) < block_p) mine.push_back(t);
+        if (u01(splitmix64(key + (uint64_t)t)) < block_p) mine.push_back(t);
     }
     for (auto& p : part) bsel.insert(bsel.end(), p.begin(), p.end());
   }
+}
+
+void gen_chung_lu(int64_t n, double gamma, int64_t pairs, int64_t max_deg, int64_t block_n,
+                  double block_p, uint64_t seed, Csr& g) {
+  Timer t_all("chung-lu total");
+  Alias al;
+  std::vector<int32_t> blk;
+  std::vector<int64_t> bsel;
+  chung_lu_setup(n, gamma, pairs, max_deg, block_n, block_p, seed, al, blk, bsel);
   const int64_t E = pairs + (int64_t)bsel.size();
   std::vector<int32_t> src(E), dst(E);
+  {
+    Timer t_samp("sample");
+    const uint64_t k23 = stream_key(seed, 23), k24 = stream_key(seed, 24);
 #pragma omp parallel for schedule(static)
-  for (int64_t i = 0; i < pairs; ++i) {
-    src[i] = al.draw(rnd(seed, 23, 2 * (uint64_t)i), rnd(seed, 24, 2 * (uint64_t)i));
-    dst[i] = al.draw(rnd(seed, 23, 2 * (uint64_t)i + 1), rnd(seed, 24, 2 * (uint64_t)i + 1));
-  }
-  // decode pair index t into (a, b), a < b, row-major over the strict upper triangle
+    for (int64_t i = 0; i < pairs; ++i) {
+      const uint64_t j = 2 * (uint64_t)i;
+      src[i] = al.draw(splitmix64(k23 + j), splitmix64(k24 + j));
+      dst[i] = al.draw(splitmix64(k23 + j + 1), splitmix64(k24 + j + 1));
+    }
 #pragma omp parallel for schedule(static)
-  for (int64_t q = 0; q < (int64_t)bsel.size(); ++q) {
-    int64_t t = bsel[q];
-    double B = (double)block_n;
-    int64_t a = (int64_t)std::floor((2 * B - 1 - std::sqrt((2 * B - 1) * (2 * B - 1) - 8.0 * (double)t)) / 2);
-    if (a < 0) a = 0;
-    auto row_start = [&](int64_t r) { return r * (2 * block_n - r - 1) / 2; };
-    while (a > 0 && row_start(a) > t) --a;
-    while (row_start(a + 1) <= t) ++a;
-    int64_t b = a + 1 + (t - row_start(a));
-    src[pairs + q] = blk[a];
-    dst[pairs + q] = blk[b];
+    for (int64_t q = 0; q < (int64_t)bsel.size(); ++q) {
+      int64_t a, b;
+      block_pair(bsel[q], block_n, a, b);
+      src[pairs + q] = blk[a];
+      dst[pairs + q] = blk[b];
+    }
   }
   build_csr(n, src, dst, g);
 }
@@ -461,6 +504,44 @@ gg_graph* gg_batch(int32_t G, int64_t first_graph, uint64_t seed, double median,
   out.off[out.n] = e;
   return h;
 }
+
+// Chung-Lu sampling tables (exactly those gen_chung_lu uses) and the planted block's edge list,
+// for drawing the same graph elsewhere: prob/alias are [n], block pairs are returned through a
+// gg_graph handle whose adj holds (a, b) pairs flattened.
+struct gg_cl_tables {
+  std::vector<double> prob;
+  std::vector<int32_t> alias;
+  std::vector<int32_t> bpairs;
+};
+
+gg_cl_tables* gg_chung_lu_tables(int64_t n, double gamma, int64_t pairs, int64_t max_deg, int64_t block_n,
+                                 double block_p, uint64_t seed) {
+  if (n < 2 || gamma <= 1.0 || pairs < 0 || block_n < 0 || block_n > n) return nullptr;
+  auto* t = new (std::nothrow) gg_cl_tables;
+  if (!t) return nullptr;
+  Alias al;
+  std::vector<int32_t> blk;
+  std::vector<int64_t> bsel;
+  chung_lu_setup(n, gamma, pairs, max_deg, block_n, block_p, seed, al, blk, bsel);
+  t->prob = std::move(al.prob);
+  t->alias = std::move(al.alias);
+  t->bpairs.resize(2 * bsel.size());
+#pragma omp parallel for schedule(static)
+  for (int64_t q = 0; q < (int64_t)bsel.size(); ++q) {
+    int64_t a, b;
+    block_pair(bsel[q], block_n, a, b);
+    t->bpairs[2 * q] = blk[a];
+    t->bpairs[2 * q + 1] = blk[b];
+  }
+  return t;
+}
+int64_t gg_cl_block_pairs(const gg_cl_tables* t) { return t ? (int64_t)t->bpairs.size() / 2 : -1; }
+void gg_cl_fill(const gg_cl_tables* t, double* prob, int32_t* alias, int32_t* bpairs) {
+  std::memcpy(prob, t->prob.data(), sizeof(double) * t->prob.size());
+  std::memcpy(alias, t->alias.data(), sizeof(int32_t) * t->alias.size());
+  if (!t->bpairs.empty()) std::memcpy(bpairs, t->bpairs.data(), sizeof(int32_t) * t->bpairs.size());
+}
+void gg_cl_free(gg_cl_tables* t) { delete t; }
 
 int64_t gg_num_vertices(const gg_graph* h) { return h ? h->g.n : -1; }
 int64_t gg_num_entries(const gg_graph* h) { return h ? (int64_t)h->g.adj.size() : -1; }

@@ -92,7 +92,7 @@ typedef struct {
   int32_t reserved[5];
 } kcore_stats;
 
-/* Single graph. n == 0 is a no-op. */
+/* Single graph. n == 0 is a no-op; adj may be null when offsets[n] == 0. */
 int kcore_decompose(const int64_t* offsets, const int32_t* adj, int64_t n, int32_t* coreness_out,
                     hipStream_t stream);
 
@@ -107,7 +107,8 @@ int kcore_decompose_ex(const int64_t* offsets, const int32_t* adj, int64_t n, in
  * own k cursor; one launch covers the whole batch.
  *   graph_vptr  int64[num_graphs+1] on the device, graph_vptr[0] = 0,
  *               graph_vptr[num_graphs] = total_vertices, non-decreasing
- *   offsets     int64[total_vertices+1], adj int32[offsets[total_vertices]] (global ids)
+ *   offsets     int64[total_vertices+1], adj int32[offsets[total_vertices]] (global ids; must be
+ *               non-null even when the batch has no edges)
  *   coreness_out int32[total_vertices] */
 int kcore_decompose_batched(const int64_t* graph_vptr, const int64_t* offsets, const int32_t* adj,
                             int32_t num_graphs, int64_t total_vertices, int32_t* coreness_out,

@@ -187,13 +187,14 @@ def decompose_batched(vptr, offsets, adj, out=None, *, stats=False, validate=Fal
     _dev_tensor(adj, torch.int32, "adj")
     G = vptr.numel() - 1
     V = offsets.numel() - 1
+    if adj.numel() == 0:
+        adj = torch.zeros(1, dtype=torch.int32, device=offsets.device)
     if out is None:
         out = torch.empty(max(V, 0), dtype=torch.int32, device=offsets.device)
     _dev_tensor(out, torch.int32, "out")
     opt = _options("auto", validate, adj.numel())
     st = Stats() if stats else None
-    rc = _lib.kcore_decompose_batched_ex(vptr.data_ptr(), offsets.data_ptr(),
-                                         adj.data_ptr() if adj.numel() else None, G, V,
+    rc = _lib.kcore_decompose_batched_ex(vptr.data_ptr(), offsets.data_ptr(), adj.data_ptr(), G, V,
                                          out.data_ptr() if V else None, _stream_ptr(stream),
                                          ctypes.byref(opt),
                                          ctypes.byref(st) if st is not None else None)

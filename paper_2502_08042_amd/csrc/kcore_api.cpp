@@ -254,7 +254,7 @@ int kcore_decompose_ex(const int64_t* offsets, const int32_t* adj, int64_t n, in
     if (stats_host) memset(stats_host, 0, sizeof *stats_host);
     return KCORE_OK;
   }
-  if (!offsets || !adj || !coreness_out) return fail(KCORE_EINVAL, "null pointer argument");
+  if (!offsets || !coreness_out) return fail(KCORE_EINVAL, "null pointer argument");
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
   DevInfo di;
@@ -275,6 +275,7 @@ int kcore_decompose_ex(const int64_t* offsets, const int32_t* adj, int64_t n, in
     if (e2 != hipSuccess) return fail(KCORE_EDEVICE, "reading offsets[n]: %s", hipGetErrorString(e2));
   }
   if (m < 0) return fail(KCORE_EINVAL, "offsets[n] = %lld is negative", (long long)m);
+  if (m > 0 && !adj) return fail(KCORE_EINVAL, "adj is null but the graph has %lld entries", (long long)m);
   // tiles pushed over the whole run: sum over hubs of ceil(deg / tile) <= m / tile + #hubs,
   // #hubs <= min(n, m / hub)
   const int64_t hubs = std::min<int64_t>(n, m / (int64_t)hub + 1);
