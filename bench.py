@@ -1,0 +1,303 @@
+#!/usr/bin/env python3
+"""Benchmark of the MI355X k-core library.
+
+Default: single-graph peel of the 16M-vertex Chung-Lu power-law graph (gamma 2.1, ~1B directed
+entries, planted 5000-vertex G(n, 0.8) block; seed 3) — the headline workload. Reports peeled
+directed edges per second (GTEPS: adjacency entries m divided by the time of one decomposition,
+graph resident in HBM), the roofline position of the peel kernel and the CPU oracle's rate on the
+same graph.
+
+    python bench.py [--steps K] [--warmup W] [--workload chunglu|grid|rmat16|batch|serve]
+
+Prints exactly one JSON line. One GPU only: --gpus N with N > 1 exits with a message.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "peeled directed edges/sec (GTEPS) + % HBM peak; batched graphs/sec & p99 latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def alg_bytes(n: int, m: int, st: dict) -> int:
+    """Algorithmic bytes of one decomposition (the per-unit figures are documented in the design doc):
+    adjacency read once (4m), one liveness probe per entry (4m), one 4-byte read-modify-write per
+    live decrement (8 per decrement), degree init from offsets (8(n+1)) and induced-degree init
+    (4n), the offsets pair of each peeled vertex (16n), coreness write plus frontier write and read
+    (12n), and 4 bytes per scanned active-set slot (+4 per compacted write, bounded by the scan)."""
+    return (4 * m + 4 * m + 8 * st["decrements"] + 8 * (n + 1) + 4 * n + 16 * n + 12 * n
+            + 4 * st["scanned"])
+
+
+def build_workload(name: str):
+    import numpy as np
+    import torch
+    import graphgen as gg
+    if name == "chunglu":
+        import graphgen.gpu as gp
+        off, adj = gp.config_chung_lu_device()
+        desc = ("Chung-Lu n=2^24 gamma=2.1 32n endpoint pairs, degree cap 1e6, planted 5000-vertex "
+                "G(n,0.8) block, symmetric int32 CSR, seed 3")
+        return off, adj, desc
+    if name == "grid":
+        g = gg.config_grid4096()
+        desc = "road-like grid 4096x4096, 5% edges deleted, 1% unit-square diagonals, seed 2"
+    elif name == "rmat16":
+        g = gg.config_rmat16()
+        desc = "RMAT scale 16 edge factor 16 a=.57 b=.19 c=.19, symmetrized, seed 1"
+    else:
+        raise ValueError(name)
+    return (torch.from_numpy(g.offsets).cuda(), torch.from_numpy(g.adj).cuda(), desc)
+
+
+def bench_single(args):
+    import numpy as np
+    import torch
+    import paper_2502_08042_amd as K
+    t0 = time.time()
+    off, adj, desc = build_workload(args.workload)
+    torch.cuda.synchronize()
+    n, m = off.numel() - 1, adj.numel()
+    log(f"[bench] workload {args.workload}: n={n} m={m} built in {time.time() - t0:.1f}s")
+    out = torch.empty(n, dtype=torch.int32, device=off.device)
+    for _ in range(args.warmup):
+        K.decompose(off, adj, out, mode=args.mode)
+    _, st = K.decompose(off, adj, out, mode=args.mode, stats=True)
+    log(f"[bench] stats {json.dumps(st)}")
+    stream = torch.cuda.current_stream()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for e0, e1 in evs:
+        e0.record(stream)
+        K.decompose(off, adj, out, mode=args.mode)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    per = [e0.elapsed_time(e1) for e0, e1 in evs]
+    ms_step = (t2 - t1) * 1000.0 / args.steps
+    avg_ms = sum(per) / len(per)
+    value = m / (ms_step / 1000.0) / 1e9
+    B = alg_bytes(n, m, st)
+    achieved = B / (avg_ms / 1000.0) / 1e9
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", f"traffic_{args.workload}_{args.mode}.json")
+    if os.path.exists(tfile):
+        with open(tfile) as f:
+            tj = json.load(f)
+        if tj.get("kernel_source_sha") == kernel_sha():
+            traffic = tj.get("bytes_per_launch")
+    res = {
+        "metric": METRIC, "value": round(value, 4), "unit": "GTEPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "strong", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": desc, "n": n, "m": m, "mode": args.mode,
+                   "kmax": st["kmax"], "rounds": st["rounds"], "subrounds": st["subrounds"],
+                   "barriers": st["barriers"]},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
+                     "traffic": traffic, "alg_bytes_per_launch": B,
+                     "kernel_ms_per_launch": round(avg_ms, 4)},
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(off, adj, m, out)
+    return res
+
+
+def cpu_baseline(off, adj, m, out_dev):
+    """The oracle (sequential Batagelj-Zaversnik, one host thread) on the same graph, once."""
+    import numpy as np
+    import oracle
+    t0 = time.time()
+    h_off = off.cpu().numpy()
+    h_adj = adj.cpu().numpy()
+    log(f"[bench] host copy {time.time() - t0:.1f}s; running the oracle once on one core")
+    secs = oracle.time_bz(h_off, h_adj, repeats=1)[0]
+    return {"value": round(m / secs / 1e9, 5), "unit": "GTEPS", "cores": 1, "kind": "oracle",
+            "sample": f"whole graph, one run of the sequential oracle ({secs:.1f} s)"}
+
+
+def bench_batch(args):
+    """4096 lognormal-sized graphs in one segmented CSR: one batched launch vs a loop of the
+    single-graph call over the same graphs."""
+    import numpy as np
+    import torch
+    import graphgen as gg
+    import oracle
+    import paper_2502_08042_amd as K
+    t0 = time.time()
+    b = gg.config_batch()
+    G, V, m = len(b.vptr) - 1, b.n, b.m
+    vptr = torch.from_numpy(b.vptr).cuda()
+    off = torch.from_numpy(b.offsets).cuda()
+    adj = torch.from_numpy(b.adj).cuda()
+    log(f"[bench] batch G={G} V={V} m={m} built in {time.time() - t0:.1f}s")
+    out = torch.empty(V, dtype=torch.int32, device="cuda")
+    for _ in range(args.warmup):
+        K.decompose_batched(vptr, off, adj, out)
+    _, st = K.decompose_batched(vptr, off, adj, out, stats=True)
+    want = oracle.bz(b.offsets, b.adj)
+    parity = bool(np.array_equal(out.cpu().numpy(), want))
+    stream = torch.cuda.current_stream()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for e0, e1 in evs:
+        e0.record(stream)
+        K.decompose_batched(vptr, off, adj, out)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    ms_batch = (t2 - t1) * 1000.0 / args.steps
+    kern_ms = sum(e0.elapsed_time(e1) for e0, e1 in evs) / args.steps
+    # the same graphs, one single-graph call each (local ids)
+    parts = []
+    for g in range(G):
+        lo, hi = int(b.vptr[g]), int(b.vptr[g + 1])
+        e0_, e1_ = int(b.offsets[lo]), int(b.offsets[hi])
+        parts.append((off[lo:hi + 1] - e0_, adj[e0_:e1_] - lo, out[lo:hi], e1_ - e0_))
+    for o_, a_, c_, mm in parts[:64]:
+        K.decompose(o_, a_, c_)
+    out.fill_(-1)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    for o_, a_, c_, mm in parts:
+        K.decompose(o_, a_, c_)
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    ms_loop = (t4 - t3) * 1000.0
+    loop_parity = bool(np.array_equal(out.cpu().numpy(), want))
+    B = (4 * m + 4 * m + 8 * st["decrements"] + 8 * (V + 1) + 4 * V + 16 * V + 12 * V
+         + 4 * st["scanned"])
+    return {
+        "metric": METRIC, "value": round(G / (ms_batch / 1000.0), 1), "unit": "graphs/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_batch, 4),
+        "higher_is_better": True, "scaling": "strong", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": "4096 graphs, lognormal n (median 2000, sigma 1, 100..100000), even "
+                   "ER avg deg 8 / odd RMAT 8n draws, one segmented CSR, seed 4",
+                   "graphs": G, "vertices": V, "m": m},
+        "batched_gteps": round(m / (ms_batch / 1000.0) / 1e9, 4),
+        "per_graph_loop_ms": round(ms_loop, 3), "speedup_vs_loop": round(ms_loop / ms_batch, 2),
+        "parity": parity and loop_parity,
+        "roofline": {"bound": "hbm", "achieved": round(B / (kern_ms / 1000.0) / 1e9, 2),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(B / (kern_ms / 1000.0) / 1e9 / HBM_PEAK_GBS, 5), "traffic": None,
+                     "alg_bytes_per_launch": B, "kernel_ms_per_launch": round(kern_ms, 4)},
+    }
+
+
+def bench_serve(args, seconds: float = 5.0, rate: float = 20000.0):
+    """Open-loop Poisson arrivals (20k req/s) of graphs from the batched distribution, 1% replaced
+    by R-MAT scale 20 edge factor 16; latency = result visible - scheduled arrival."""
+    import threading
+    import numpy as np
+    import graphgen as gg
+    import oracle
+    import paper_2502_08042_amd as K
+    pool = gg.batch(512, 5, first_graph=100000)
+    small = [pool.subgraph(g) for g in range(512)]
+    big = [gg.rmat(20, 16, 50 + i) for i in range(2)]
+    want_small = [oracle.bz(g.offsets, g.adj) for g in small]
+    want_big = [oracle.bz(g.offsets, g.adj) for g in big]
+    nreq = int(seconds * rate)
+    u = gg.uniform(5, 91, 0, 3 * nreq)
+    gaps = -np.log1p(-u[:nreq]) / rate
+    arrivals = np.cumsum(gaps) * 1e6  # us
+    is_big = u[nreq:2 * nreq] < 0.01
+    pick = (u[2 * nreq:] * 512).astype(np.int64)
+    log(f"[bench] serving {nreq} requests over {arrivals[-1] / 1e6:.1f}s, {int(is_big.sum())} large")
+    srv = K.Server(device=0, max_inflight=4, hbm_budget_bytes=16 << 30)
+    tickets = [None] * nreq
+    results = {}
+    done_evt = threading.Event()
+
+    def collector():
+        for i in range(nreq):
+            while tickets[i] is None:
+                time.sleep(0.0002)
+            core, st = srv.wait(tickets[i], with_stats=True)
+            results[i] = (core, st)
+        done_evt.set()
+
+    th = threading.Thread(target=collector, daemon=True)
+    th.start()
+    t0 = srv.now_us()
+    for i in range(nreq):
+        due = t0 + arrivals[i]
+        while srv.now_us() < due:
+            pass
+        g = big[pick[i] % 2] if is_big[i] else small[pick[i]]
+        tickets[i] = srv.submit(g.offsets, g.adj)
+    done_evt.wait()
+    srv.close()
+    lat = np.empty(nreq)
+    ok = True
+    last_done = 0.0
+    for i in range(nreq):
+        core, st = results[i]
+        lat[i] = st["done_us"] - (t0 + arrivals[i])
+        last_done = max(last_done, st["done_us"])
+        want = want_big[pick[i] % 2] if is_big[i] else want_small[pick[i]]
+        ok = ok and bool(np.array_equal(core, want))
+    span_s = (last_done - t0) / 1e6
+    return {
+        "metric": METRIC, "value": round(nreq / span_s, 1), "unit": "graphs/s", "n_gpus": 1,
+        "steps": 1, "warmup": 0, "ms_per_step": round(span_s * 1000, 1), "higher_is_better": True,
+        "scaling": "strong", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": f"serving: Poisson {rate:.0f} req/s for {seconds}s, graphs from the "
+                   "batched distribution, 1% R-MAT scale 20 edge factor 16", "requests": nreq},
+        "p50_ms": round(float(np.percentile(lat, 50)) / 1000, 3),
+        "p99_ms": round(float(np.percentile(lat, 99)) / 1000, 3),
+        "p99_small_ms": round(float(np.percentile(lat[~is_big], 99)) / 1000, 3),
+        "p99_large_ms": round(float(np.percentile(lat[is_big], 99)) / 1000, 3) if is_big.any() else None,
+        "parity": ok,
+    }
+
+
+def kernel_sha() -> str:
+    import hashlib
+    h = hashlib.sha1()
+    with open(os.path.join(ROOT, "paper_2502_08042_amd", "csrc", "kcore_device.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="chunglu", choices=["chunglu", "grid", "rmat16", "batch", "serve"])
+    ap.add_argument("--mode", default="auto", choices=["auto", "levelsync", "chained"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the single-graph and batched "
+              "paths are single-device in this build", file=sys.stderr)
+        sys.exit(2)
+    if args.workload == "batch":
+        res = bench_batch(args)
+    elif args.workload == "serve":
+        res = bench_serve(args)
+    else:
+        res = bench_single(args)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -315,6 +315,7 @@ int kcore_decompose_ex(const int64_t* offsets, const int32_t* adj, int64_t n, in
   a.tile = tile;
   a.chained = mode == KCORE_MODE_CHAINED ? 1 : 0;
   a.lq_budget = budget;
+  a.big_phase = 16384;
 
   HIP_TRY(kc::launch_init_ctl(w->ctl, stream));
   if (stats_host) HIP_TRY(hipEventRecord(w->ev0, stream));
@@ -331,7 +332,9 @@ int kcore_decompose_ex(const int64_t* offsets, const int32_t* adj, int64_t n, in
   float ms = 0;
   HIP_TRY(hipEventElapsedTime(&ms, w->ev0, w->ev1));
   fill_stats(stats_host, w->host_stats, status, ms);
-  if (status) return fail(KCORE_EDEVICE, "device reported failure bits 0x%x", status);
+  if (status)
+    return fail(KCORE_EDEVICE, "device reported failure bits 0x%x (diag %llu %llu %llu %llu)", status,
+                w->host_stats[12], w->host_stats[13], w->host_stats[14], w->host_stats[15]);
   return KCORE_OK;
 }
 

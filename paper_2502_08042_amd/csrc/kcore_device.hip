@@ -181,9 +181,36 @@ struct WaveCtx {
   int32_t* lq;         // local queue ring (chained mode)
   int lq_head, lq_cnt; // wave-uniform
   int lq_used;         // vertices peeled from the local queue this phase
-  long long edges, decr, scanned, peeled;  // per-lane statistics
+  long long edges, decr, scanned, peeled, comb;  // per-lane statistics
   unsigned mymin;      // per-lane min over kept vertices
+  int32_t* ckey;       // LDS combining table (block-shared): target id or -1
+  uint32_t* ccnt;      //   decrements collected for it in this phase
+  bool precheck;       // phase-uniform: probe peeled bits and combine hub targets
 };
+
+__device__ __forceinline__ unsigned comb_hash(int32_t u) {
+  return ((unsigned)u * 2654435761u) >> (32 - kCombBits);
+}
+
+// Adds one decrement of hub target u to the block's LDS table; false when its probe window is
+// full (the caller then decrements in global memory directly).
+__device__ __forceinline__ bool comb_add(WaveCtx& c, int32_t u) {
+  const unsigned h = comb_hash(u);
+#pragma unroll
+  for (int p = 0; p < kCombProbe; ++p) {
+    const unsigned s = (h + p) & (kCombSlots - 1);
+    int32_t key = __hip_atomic_load(&c.ckey[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (key == -1) {
+      key = atomicCAS(&c.ckey[s], -1, u);
+      if (key == -1) key = u;
+    }
+    if (key == u) {
+      atomicAdd(&c.ccnt[s], 1u);
+      return true;
+    }
+  }
+  return false;
+}
 
 struct PhaseOut {
   PhaseSlot* slot;
@@ -237,35 +264,62 @@ __device__ __forceinline__ void push_vertices(const PeelArgs& a, WaveCtx& c, con
   }
 }
 
-// One adjacency entry per lane: the online decrement of Alg. 3. A neighbour already peeled is
-// skipped (its peeled bit is set when it is given a coreness); otherwise its induced degree is
-// decremented atomically and the lane whose decrement takes it from k+1 to k pushes it.
-__device__ __forceinline__ void edge_step(const PeelArgs& a, WaveCtx& c, const PhaseOut& o,
-                                          bool valid, int32_t u, uint32_t k) {
-  bool crossed = false;
-  bool hub = false;
-  if (valid) {
+// Up to kEdgeUnroll adjacency entries per lane: the online decrement of Alg. 3. All loads, and
+// then all atomics, of a lane are issued before any result is used, so one pass costs a few memory
+// round trips however many entries it covers. In large phases (c.precheck) a neighbour whose
+// peeled bit is already set is skipped and hub targets go to the LDS combining table; in small,
+// latency-bound phases the probe is skipped (decrementing a peeled vertex is harmless: it can
+// never cross k again, and each neighbour decrements it once, so it never drops below zero).
+// The lane whose decrement takes u from k+1 to k pushes it.
+__device__ __forceinline__ void edges_batch(const PeelArgs& a, WaveCtx& c, const PhaseOut& o,
+                                            const int32_t (&u)[kEdgeUnroll], unsigned valid, uint32_t k) {
+  uint32_t sw[kEdgeUnroll];
+#pragma unroll
+  for (int j = 0; j < kEdgeUnroll; ++j) sw[j] = 0u;
+  if (c.precheck) {
+#pragma unroll
+    for (int j = 0; j < kEdgeUnroll; ++j)
+      if ((valid >> j) & 1u) sw[j] = ald(&a.state[u[j] >> 4]);
+  }
+  uint32_t old[kEdgeUnroll];
+  unsigned did = 0u;
+#pragma unroll
+  for (int j = 0; j < kEdgeUnroll; ++j) {
+    old[j] = 0u;
+    if (!((valid >> j) & 1u)) continue;
     c.edges += 1;
-    const uint32_t sw = ald(&a.state[u >> 4]);
-    if (!((sw >> (u & 15)) & 1u)) {
-      const uint32_t old = asub(&a.dt[u], 1u);
-      c.decr += 1;
-      if ((old & DMASK) == k + 1u) {
-        crossed = true;
-        hub = (old & HUBBIT) != 0u;
+    if ((sw[j] >> (u[j] & 15)) & 1u) continue;  // already peeled
+    // hub targets collect their decrements in LDS for the rest of the phase (the flush applies
+    // them with one atomic per target); everything else is decremented right away
+    if (((sw[j] >> (16 + (u[j] & 15))) & 1u) && comb_add(c, u[j])) {
+      c.comb += 1;
+      continue;
+    }
+    old[j] = asub(&a.dt[u[j]], 1u);
+    c.decr += 1;
+    did |= 1u << j;
+  }
+#pragma unroll
+  for (int j = 0; j < kEdgeUnroll; ++j) {
+    bool crossed = ((did >> j) & 1u) && (old[j] & DMASK) == k + 1u;
+    const bool hub = (old[j] & HUBBIT) != 0u;
+    if (crossed) {
+      // the peeled bit decides ownership: in chained mode a scan may find u at the same time
+      const uint32_t bit = 1u << (u[j] & 15);
+      if (aor(&a.state[u[j] >> 4], bit) & bit) {
+        crossed = false;
+      } else {
+        a.core[u[j]] = (int32_t)k;
+        c.peeled += 1;
       }
     }
+    push_vertices(a, c, o, crossed, u[j], hub);
   }
-  if (crossed) {
-    a.core[u] = (int32_t)k;
-    aor(&a.state[u >> 4], 1u << (u & 15));
-    c.peeled += 1;
-  }
-  push_vertices(a, c, o, crossed, u, hub);
 }
 
 // Expands the rows of up to 64 vertices (one per lane, -1 = none) edge-balanced across the wave:
-// an exclusive scan of the degrees, then each lane finds the row of its edge by binary search.
+// an exclusive scan of the degrees, then each lane finds the row of each of its entries by binary
+// search over the scan.
 __device__ void expand_rows(const PeelArgs& a, WaveCtx& c, const PhaseOut& o, int32_t v, uint32_t k) {
   long long b = 0, d = 0;
   if (v >= 0) {
@@ -276,19 +330,27 @@ __device__ void expand_rows(const PeelArgs& a, WaveCtx& c, const PhaseOut& o, in
   const long long excl = incl - d;
   const long long total = __shfl(incl, 63, 64);
   const int l = lane_id();
-  for (long long e0 = 0; e0 < total; e0 += 64) {
-    const long long t = e0 + l;
-    const bool valid = t < total;
-    int j = 0;
+  for (long long e0 = 0; e0 < total; e0 += 64 * kEdgeUnroll) {
+    int32_t u[kEdgeUnroll];
+    unsigned valid = 0u;
 #pragma unroll
-    for (int step = 32; step >= 1; step >>= 1) {
-      const int cand = j + step;
-      const long long ex = __shfl(excl, cand & 63, 64);
-      if (cand < 64 && ex <= t) j = cand;
+    for (int q = 0; q < kEdgeUnroll; ++q) {
+      const long long t = e0 + 64 * q + l;
+      int j = 0;
+#pragma unroll
+      for (int step = 32; step >= 1; step >>= 1) {
+        const int cand = j + step;
+        const long long ex = __shfl(excl, cand & 63, 64);
+        if (cand < 64 && ex <= t) j = cand;
+      }
+      const long long pos = __shfl(b, j, 64) + (t - __shfl(excl, j, 64));
+      u[q] = 0;
+      if (t < total) {
+        u[q] = a.adj[pos];
+        valid |= 1u << q;
+      }
     }
-    const long long pos = __shfl(b, j, 64) + (t - __shfl(excl, j, 64));
-    const int32_t u = valid ? a.adj[pos] : 0;
-    edge_step(a, c, o, valid, u, k);
+    edges_batch(a, c, o, u, valid, k);
   }
 }
 
@@ -298,12 +360,51 @@ __device__ void expand_tile(const PeelArgs& a, WaveCtx& c, const PhaseOut& o, in
   const long long rb = a.off[v], re = a.off[v + 1];
   const long long b = rb + (long long)j * a.tile;
   const long long e = min(re, b + a.tile);
-  for (long long p0 = b; p0 < e; p0 += 64) {
-    const long long pos = p0 + lane_id();
-    const bool valid = pos < e;
-    const int32_t u = valid ? a.adj[pos] : 0;
-    edge_step(a, c, o, valid, u, k);
+  for (long long p0 = b; p0 < e; p0 += 64 * kEdgeUnroll) {
+    int32_t u[kEdgeUnroll];
+    unsigned valid = 0u;
+#pragma unroll
+    for (int q = 0; q < kEdgeUnroll; ++q) {
+      const long long pos = p0 + 64 * q + lane_id();
+      u[q] = 0;
+      if (pos < e) {
+        u[q] = a.adj[pos];
+        valid |= 1u << q;
+      }
+    }
+    edges_batch(a, c, o, u, valid, k);
   }
+}
+
+// Applies the block's combined decrements: one atomic subtraction of c per target; exactly one
+// subtraction takes a target from above k to k or below (old > k >= old - c), and that one pushes
+// it. Clears the table for the next phase. All threads of the block call.
+__device__ void comb_flush(const PeelArgs& a, WaveCtx& c, const PhaseOut& o, uint32_t k) {
+  __syncthreads();
+  for (int s0 = 0; s0 < kCombSlots; s0 += kPeelThreads) {
+    const int s = s0 + threadIdx.x;
+    const int32_t u = c.ckey[s];
+    bool crossed = false, hub = false;
+    if (u >= 0) {
+      const uint32_t cnt = c.ccnt[s];
+      c.ckey[s] = -1;
+      c.ccnt[s] = 0;
+      const uint32_t old = asub(&a.dt[u], cnt);
+      c.decr += 1;
+      const uint32_t ox = old & DMASK;
+      if (ox > k && ox - cnt <= k) {
+        const uint32_t bit = 1u << (u & 15);
+        if (!(aor(&a.state[u >> 4], bit) & bit)) {
+          crossed = true;
+          hub = (old & HUBBIT) != 0u;
+          a.core[u] = (int32_t)k;
+          c.peeled += 1;
+        }
+      }
+    }
+    push_vertices(a, c, o, crossed, u, hub);
+  }
+  __syncthreads();
 }
 
 // Chained mode: peel what the wave queued locally, in packets of up to 64 vertices, until the
@@ -337,6 +438,9 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
   __shared__ unsigned long long s_base;
   __shared__ unsigned s_red[kWaves];
   __shared__ long long s_red64[kWaves];
+  __shared__ long long s_out[8];
+  __shared__ int32_t s_ckey[kCombSlots];
+  __shared__ uint32_t s_ccnt[kCombSlots];
 
   const int w = threadIdx.x >> 6;
   const int l = lane_id();
@@ -356,8 +460,14 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
   c.lq_head = 0;
   c.lq_cnt = 0;
   c.lq_used = 0;
-  c.edges = c.decr = c.scanned = c.peeled = 0;
+  c.edges = c.decr = c.scanned = c.peeled = c.comb = 0;
   c.mymin = 0xffffffffu;
+  c.ckey = s_ckey;
+  c.ccnt = s_ccnt;
+  for (int i = threadIdx.x; i < kCombSlots; i += kPeelThreads) {
+    s_ckey[i] = -1;
+    s_ccnt[i] = 0;
+  }
 
   unsigned epoch = 0;
   long long st_rounds = 0, st_sub = 0, st_bar = 0;
@@ -392,8 +502,11 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
   if (!grid_sync(C, epoch)) return;
   st_bar++;
 
-  long long kprev = -1;                      // every vertex with induced degree <= kprev is peeled
-  long long kx = (long long)ald(&C->slot[0].minv);  // round being extracted or expanded
+  if (threadIdx.x == 0) s_out[0] = (long long)ald(&C->slot[0].minv);
+  __syncthreads();
+  long long kprev = -1;        // every vertex with induced degree <= kprev is peeled
+  long long kx = s_out[0];     // round being extracted or expanded
+  __syncthreads();
   int kind = PH_SCAN;
   bool dense = true, compact = false;
   long long asize = n;
@@ -422,6 +535,9 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
     }
     const uint32_t k = (uint32_t)kx;
     c.lq_used = 0;
+    // large phases are bandwidth bound: probe peeled bits and combine hub decrements; small ones
+    // are latency bound: skip the probe and spread the frontier over as many waves as possible
+    c.precheck = kind == PH_SCAN ? asize >= a.big_phase * 16 : (fs + ft * (a.tile / 16)) >= a.big_phase;
     long long peeled_before = c.peeled;
     if (kind == PH_SCAN) {
       // Alg. 1: F = {v in A : induced degree <= k}; survivors refine A.
@@ -439,14 +555,18 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
           c.scanned += 1;
         }
         const bool alive = valid && (long long)x > kprev;
-        const bool ext = alive && (long long)x <= kx;
+        bool ext = alive && (long long)x <= kx;
         const bool keep = alive && (long long)x > kx;
         if (keep) c.mymin = min(c.mymin, x);
         if (compact) stage_push(c.sa, keep, v, &o.slot->active, anext, n, &C->status);
         if (ext) {
-          a.core[v] = (int32_t)k;
-          aor(&a.state[v >> 4], 1u << (v & 15));
-          c.peeled += 1;
+          const uint32_t bit = 1u << (v & 15);
+          if (aor(&a.state[v >> 4], bit) & bit) {
+            ext = false;  // already peeled in this round by a chain (chained mode)
+          } else {
+            a.core[v] = (int32_t)k;
+            c.peeled += 1;
+          }
         }
         push_vertices(a, c, o, ext, v, (word & HUBBIT) != 0u);
       }
@@ -454,12 +574,14 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
       // Alg. 3 over the frontier: packets of 64 small vertices, then hub tiles.
       const int32_t* fcur = a.fr[(p - 1) & 1];
       const int2* tcur = a.tl[(p - 1) & 1];
-      const long long npk = (fs + 63) >> 6;
+      int per = 64;  // frontier vertices per wave item: fewer when the frontier is small
+      while (per > 1 && (fs + per - 1) / per < W) per >>= 1;
+      const long long npk = (fs + per - 1) / per;
       const long long items = npk + ft;
       for (long long it = gw; it < items; it += W) {
         if (it < npk) {
-          const long long i = it * 64 + l;
-          const int32_t v = i < fs ? ald(&fcur[i]) : -1;
+          const long long i = it * per + l;
+          const int32_t v = (l < per && i < fs) ? ald(&fcur[i]) : -1;
           expand_rows(a, c, o, v, k);
         } else {
           const int32_t* e = reinterpret_cast<const int32_t*>(&tcur[it - npk]);
@@ -469,6 +591,8 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
         }
       }
     }
+    if (a.chained) drain_local(a, c, o, k);
+    comb_flush(a, c, o, k);
     if (a.chained) drain_local(a, c, o, k);
 
     // ---- phase end: block-level flushes and reductions
@@ -499,12 +623,21 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
     if (!grid_sync(C, epoch)) break;
     st_bar++;
 
-    // ---- decide the next phase (identical in every workgroup)
-    const long long nfs = (long long)ald(&o.slot->small);
-    const long long nft = (long long)ald(&o.slot->tiles);
-    const long long nact = (long long)ald(&o.slot->active);
-    const unsigned mv = ald(&o.slot->minv);
-    const long long npeel = (long long)ald(&o.slot->peeled);
+    // ---- decide the next phase (identical in every workgroup); one thread reads the outcome
+    if (threadIdx.x == 0) {
+      s_out[0] = (long long)ald(&o.slot->small);
+      s_out[1] = (long long)ald(&o.slot->tiles);
+      s_out[2] = (long long)ald(&o.slot->active);
+      s_out[3] = (long long)ald(&o.slot->minv);
+      s_out[4] = (long long)ald(&o.slot->peeled);
+    }
+    __syncthreads();
+    const long long nfs = s_out[0];
+    const long long nft = s_out[1];
+    const long long nact = s_out[2];
+    const unsigned mv = (unsigned)s_out[3];
+    const long long npeel = s_out[4];
+    __syncthreads();
     if (nfs > a.fcap || nft > a.tcap || nact > n) {
       // a list overflowed (its entries were not written): stop before reading them
       if (threadIdx.x == 0) aor(&C->status, (unsigned)KC_ERR_OVERFLOW);
@@ -537,6 +670,12 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
         // no live vertex has induced degree <= kx: jump to the smallest one (next non-empty round)
         if (mv == 0xffffffffu) {
           if (threadIdx.x == 0) aor(&C->status, (unsigned)KC_ERR_PHASES);
+          if (blockIdx.x == 0 && threadIdx.x == 0) {
+            ast(&C->stats[12], (unsigned long long)total_peeled);
+            ast(&C->stats[13], (unsigned long long)kx);
+            ast(&C->stats[14], (unsigned long long)p);
+            ast(&C->stats[15], (unsigned long long)asize);
+          }
           break;
         }
         kx = (long long)mv;
@@ -559,8 +698,8 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
 
   // ---- statistics: per-lane counters reduced per block, one atomic each per block
   {
-    long long v4[4] = {c.edges, c.decr, c.scanned, c.peeled};
-    for (int q = 0; q < 4; ++q) {
+    long long v4[5] = {c.edges, c.decr, c.scanned, c.peeled, c.comb};
+    for (int q = 0; q < 5; ++q) {
       long long x = v4[q];
       for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
       if (l == 0) s_red64[w] = x;
@@ -568,7 +707,7 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
       if (threadIdx.x == 0) {
         long long t = 0;
         for (int i = 0; i < kWaves; ++i) t += s_red64[i];
-        const int idx = q == 0 ? ST_EDGES : q == 1 ? ST_DECR : q == 2 ? ST_SCANNED : ST_PEELED;
+        const int idx = q == 0 ? ST_EDGES : q == 1 ? ST_DECR : q == 2 ? ST_SCANNED : q == 3 ? ST_PEELED : ST_COMBINED;
         if (t) aadd(&C->stats[idx], (unsigned long long)t);
       }
       __syncthreads();

@@ -9,7 +9,10 @@ constexpr int kPeelThreads = 1024;   // threads per persistent workgroup (16 wav
 constexpr int kWaves = kPeelThreads / 64;
 constexpr int kStage = 256;          // per-wave LDS staging entries for frontier appends
 constexpr int kLocalQ = 512;         // per-wave local queue (chained mode)
-constexpr int kCombSlots = 2048;     // per-workgroup LDS combining table for hub targets
+constexpr int kCombBits = 12;
+constexpr int kCombSlots = 1 << kCombBits;  // per-workgroup LDS combining table for hub targets
+constexpr int kCombProbe = 4;               // linear-probe window of that table
+constexpr int kEdgeUnroll = 2;              // adjacency entries in flight per lane
 constexpr int kBarGroups = 32;       // arrival groups of the grid barrier
 constexpr int kBatchThreads = 512;   // threads per workgroup of the batched peel
 
@@ -60,6 +63,7 @@ struct PeelArgs {
   int32_t tile;        // edges per tile (multiple of 64)
   int32_t chained;     // 1: local queues (chained mode)
   int32_t lq_budget;   // max vertices a wave peels from its local queue per phase
+  int64_t big_phase;   // frontier size from which a phase probes peeled bits and combines hubs
 };
 
 struct BatchCtl {

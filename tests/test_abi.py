@@ -1,0 +1,88 @@
+"""C ABI checks that need no GPU: the library loads, exports every function kcore.h declares,
+and rejects bad arguments before touching the device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+HEADER = os.path.join(ROOT, "include", "kcore.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(kcore_[a-z_]+)\s*\(", src)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for need in ("kcore_decompose", "kcore_decompose_ex", "kcore_decompose_batched",
+                 "kcore_submit", "kcore_poll", "kcore_server_create", "kcore_server_destroy",
+                 "kcore_last_error"):
+        assert need in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2502_08042_amd as K
+    lib = ctypes.CDLL(K.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), f"{name} declared in kcore.h but not exported"
+        assert name in K.SIGNATURES, f"{name} has no binding signature"
+
+
+def test_struct_layouts_match_header_sizes():
+    import paper_2502_08042_amd as K
+    # sizes implied by the header's field lists (natural alignment on x86-64)
+    assert ctypes.sizeof(K.Options) == 48
+    assert ctypes.sizeof(K.Stats) == 8 * 8 + 4 * 3 + 4 * 5
+    assert ctypes.sizeof(K.ServerConfig) == 16 + 8 * 3 + 8 + 16
+    assert ctypes.sizeof(K.RequestStats) == 8 * 4 + 8 + 8
+
+
+def test_argument_errors_without_device_work():
+    import paper_2502_08042_amd as K
+    lib = K.lib()
+    one = np.zeros(2, dtype=np.int64)
+    # negative n, n beyond the int32 id range: rejected before any HIP call
+    assert lib.kcore_decompose(one.ctypes.data, None, -1, None, None) == -1
+    assert "negative" in K.last_error()
+    assert lib.kcore_decompose(one.ctypes.data, None, 1 << 31, None, None) == -1
+    # n == 0 is a no-op
+    assert lib.kcore_decompose(None, None, 0, None, None) == 0
+    # bad options
+    o = K.Options()
+    o.mode = 7
+    assert lib.kcore_decompose_ex(one.ctypes.data, None, 0, None, None, ctypes.byref(o), None) == -1
+    o = K.Options()
+    o.tile_edges = 100
+    assert lib.kcore_decompose_ex(one.ctypes.data, None, 0, None, None, ctypes.byref(o), None) == -1
+    o = K.Options()
+    o.reserved[2] = 1
+    assert lib.kcore_decompose_ex(one.ctypes.data, None, 0, None, None, ctypes.byref(o), None) == -1
+    # batched: negative sizes, empty batch
+    assert lib.kcore_decompose_batched(None, None, None, -1, 0, None, None) == -1
+    assert lib.kcore_decompose_batched(None, None, None, 0, 0, None, None) == 0
+    # server calls on a null handle
+    t = ctypes.c_uint64(0)
+    assert lib.kcore_submit(None, one.ctypes.data, None, 1, ctypes.byref(t)) == -1
+    assert lib.kcore_poll(None, 1, None, None) == -1
+    assert lib.kcore_cancel(None, 1) == -1
+    lib.kcore_server_destroy(None)
+    assert lib.kcore_version() >= 10000
+
+
+def test_missing_library_fails_loudly(tmp_path, monkeypatch):
+    import importlib.util
+    import shutil
+    pkg = tmp_path / "pkgcopy"
+    shutil.copytree(os.path.join(ROOT, "paper_2502_08042_amd"), pkg,
+                    ignore=shutil.ignore_patterns("*.so", "__pycache__"))
+    spec = importlib.util.spec_from_file_location("kcore_nolib", pkg / "__init__.py")
+    mod = importlib.util.module_from_spec(spec)
+    with pytest.raises(ImportError, match="no fallback"):
+        spec.loader.exec_module(mod)

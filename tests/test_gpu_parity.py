@@ -52,7 +52,7 @@ def test_small_graphs(mode):
 
 
 @pytest.mark.parametrize("mode", MODES)
-@pytest.mark.parametrize("which", ["rmat12", "er3000", "road128", "hcns200", "rmat16"])
+@pytest.mark.parametrize("which", ["rmat12", "er3000", "road128", "hcns200", "rmat16", "road1024"])
 def test_medium_graphs(mode, which):
     if which == "rmat12":
         g = gg.rmat(12, 16, 11)
@@ -65,6 +65,11 @@ def test_medium_graphs(mode, which):
         off, adj = g.offsets, g.adj
     elif which == "hcns200":
         off, adj = G.hcns(200)
+    elif which == "road1024":
+        # deep peel chains: in chained mode scans and chains race for the same vertices, and
+        # every vertex must still be peeled exactly once (peeled == n, edges == m)
+        g = gg.grid_road(1024, 0.05, 0.01, 2)
+        off, adj = g.offsets, g.adj
     else:
         g = gg.config_rmat16()
         off, adj = g.offsets, g.adj
