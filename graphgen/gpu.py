@@ -118,10 +118,9 @@ def chung_lu_device(n, gamma, pairs, max_deg, block_n, block_p, seed, device="cu
     src = uk // n
     adj = (uk - src * n).to(torch.int32)
     del uk
-    deg = torch.bincount(src, minlength=n)
+    # keys are sorted, so row starts are where the source id first reaches each vertex
+    offsets = torch.searchsorted(src, torch.arange(n + 1, dtype=torch.int64, device=device))
     del src
-    offsets = torch.zeros(n + 1, dtype=torch.int64, device=device)
-    offsets[1:] = torch.cumsum(deg, 0)
     return offsets, adj
 
 

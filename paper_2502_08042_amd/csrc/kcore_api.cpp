@@ -261,8 +261,8 @@ int kcore_decompose_ex(const int64_t* offsets, const int32_t* adj, int64_t n, in
   if (int rc = dev_info(dev, di)) return rc;
 
   const int mode = (opt && opt->mode) ? opt->mode : KCORE_MODE_CHAINED;
-  const uint32_t hub = (opt && opt->hub_degree) ? (uint32_t)opt->hub_degree : 1024u;
-  const int tile = (opt && opt->tile_edges) ? opt->tile_edges : 1024;
+  const uint32_t hub = (opt && opt->hub_degree) ? (uint32_t)opt->hub_degree : 128u;
+  const int tile = (opt && opt->tile_edges) ? opt->tile_edges : 256;
   const int budget = (opt && opt->local_budget) ? opt->local_budget : 4096;
   int64_t m = opt ? opt->num_entries : 0;
   if (m <= 0) {
@@ -312,6 +312,7 @@ int kcore_decompose_ex(const int64_t* offsets, const int32_t* adj, int64_t n, in
   a.tcap = w->t_cap;
   a.ctl = w->ctl;
   a.hub = hub;
+  a.comb_degree = hub > 1024u ? hub : 1024u;
   a.tile = tile;
   a.chained = mode == KCORE_MODE_CHAINED ? 1 : 0;
   a.lq_budget = budget;
@@ -335,6 +336,24 @@ int kcore_decompose_ex(const int64_t* offsets, const int32_t* adj, int64_t n, in
   if (status)
     return fail(KCORE_EDEVICE, "device reported failure bits 0x%x (diag %llu %llu %llu %llu)", status,
                 w->host_stats[12], w->host_stats[13], w->host_stats[14], w->host_stats[15]);
+  return KCORE_OK;
+}
+
+// Debugging aid, not part of kcore.h: copies the phase timeline of the last single-graph call on
+// `stream` (rows of start, work done, flushed, barrier passed; 100 MHz ticks). Synchronises.
+int kcore_debug_trace(hipStream_t stream, unsigned long long* out, int max_phases) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  PeelWs* w = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_peel.find(Key(dev, stream));
+    if (it == g_peel.end() || !it->second || !it->second->ctl) return fail(KCORE_ENOTFOUND, "no workspace");
+    w = it->second;
+  }
+  const int np = max_phases < kc::kTracePhases ? max_phases : kc::kTracePhases;
+  HIP_TRY(hipStreamSynchronize(stream));
+  HIP_TRY(hipMemcpy(out, w->ctl->trace, sizeof(unsigned long long) * 4 * np, hipMemcpyDeviceToHost));
   return KCORE_OK;
 }
 

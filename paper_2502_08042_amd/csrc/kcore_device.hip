@@ -483,9 +483,10 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
         const long long v = wd * 16 + j;
         if (v >= n) break;
         const long long d = a.off[v + 1] - a.off[v];
-        const bool hub = d >= (long long)a.hub;
+        const bool hub = d >= (long long)a.hub;        // rows split into tiles when peeled
+        const bool hot = d >= (long long)a.comb_degree;  // decrements combined in LDS
         ast(&a.dt[v], (uint32_t)d | (hub ? HUBBIT : 0u));
-        bits |= (hub ? 1u : 0u) << (16 + j);
+        bits |= (hot ? 1u : 0u) << (16 + j);
         mn = min(mn, (unsigned)d);
       }
       ast(&a.state[wd], bits);
@@ -504,7 +505,6 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
 
   if (threadIdx.x == 0) s_out[0] = (long long)ald(&C->slot[0].minv);
   __syncthreads();
-  long long kprev = -1;        // every vertex with induced degree <= kprev is peeled
   long long kx = s_out[0];     // round being extracted or expanded
   __syncthreads();
   int kind = PH_SCAN;
@@ -534,6 +534,8 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
       ast(&r->minv, 0xffffffffu);
     }
     const uint32_t k = (uint32_t)kx;
+    const bool tr = blockIdx.x == 0 && threadIdx.x == 0 && p < kTracePhases;
+    if (tr) C->trace[p][0] = wall_clock64();
     c.lq_used = 0;
     // large phases are bandwidth bound: probe peeled bits and combine hub decrements; small ones
     // are latency bound: skip the probe and spread the frontier over as many waves as possible
@@ -549,12 +551,16 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
         int32_t v = -1;
         if (valid) v = dense ? (int32_t)i : ald(&alist[i]);
         uint32_t word = 0, x = 0;
+        bool alive = false;
         if (valid) {
+          // liveness comes from the peeled bit, not from the induced degree: in chained mode a
+          // chain of this round may already have taken a vertex due for extraction below k
+          const uint32_t sw = ald(&a.state[v >> 4]);
           word = ald(&a.dt[v]);
           x = word & DMASK;
+          alive = !((sw >> (v & 15)) & 1u);
           c.scanned += 1;
         }
-        const bool alive = valid && (long long)x > kprev;
         bool ext = alive && (long long)x <= kx;
         const bool keep = alive && (long long)x > kx;
         if (keep) c.mymin = min(c.mymin, x);
@@ -594,6 +600,7 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
     if (a.chained) drain_local(a, c, o, k);
     comb_flush(a, c, o, k);
     if (a.chained) drain_local(a, c, o, k);
+    if (tr) C->trace[p][1] = wall_clock64();
 
     // ---- phase end: block-level flushes and reductions
     block_flush(c.sf, &o.slot->small, o.fr, a.fcap, &C->status, s_cnt, &s_base);
@@ -615,13 +622,15 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
           m = min(m, s_red[i]);
           tp += s_red64[i];
         }
-        if (m < ald(&o.slot->minv)) amin(&o.slot->minv, m);
+        if (m != 0xffffffffu && m < ald(&o.slot->minv)) amin(&o.slot->minv, m);
         if (tp) aadd(&o.slot->peeled, (unsigned long long)tp);
       }
       c.mymin = 0xffffffffu;
     }
+    if (tr) C->trace[p][2] = wall_clock64();
     if (!grid_sync(C, epoch)) break;
     st_bar++;
+    if (tr) C->trace[p][3] = wall_clock64();
 
     // ---- decide the next phase (identical in every workgroup); one thread reads the outcome
     if (threadIdx.x == 0) {
@@ -663,7 +672,6 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
         break;
       } else if (npeel > 0) {
         // the round completed inside the scan (chained mode)
-        kprev = kx;
         kx = kx + 1;
         compact = removed_since * 8 >= asize;
       } else {
@@ -688,7 +696,6 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
       } else if (total_peeled >= n) {
         break;
       } else {
-        kprev = kx;
         kx = kx + 1;
         kind = PH_SCAN;
         compact = removed_since * 8 >= asize;

@@ -15,6 +15,7 @@ constexpr int kCombProbe = 4;               // linear-probe window of that table
 constexpr int kEdgeUnroll = 2;              // adjacency entries in flight per lane
 constexpr int kBarGroups = 32;       // arrival groups of the grid barrier
 constexpr int kBatchThreads = 512;   // threads per workgroup of the batched peel
+constexpr int kTracePhases = 1024;   // phases whose timeline workgroup 0 records
 
 enum StatIdx {
   ST_ROUNDS = 0, ST_SUBROUNDS, ST_BARRIERS, ST_PEELED, ST_EDGES, ST_DECR, ST_COMBINED, ST_SCANNED,
@@ -42,6 +43,8 @@ struct alignas(128) PeelCtl {
   unsigned int status;        // error bits (KC_ERR_*)
   unsigned int pad2[31];
   unsigned long long stats[16];
+  // phase timeline of workgroup 0 (100 MHz wall clock): start, work done, flushed, barrier passed
+  unsigned long long trace[kTracePhases][4];
 };
 
 enum : unsigned { KC_ERR_TIMEOUT = 1u, KC_ERR_OVERFLOW = 2u, KC_ERR_PHASES = 4u, KC_ERR_BADGRAPH = 8u };
@@ -59,7 +62,8 @@ struct PeelArgs {
   int64_t fcap;        // frontier capacity (entries)
   int64_t tcap;        // tile list capacity
   PeelCtl* ctl;
-  uint32_t hub;        // hub degree threshold
+  uint32_t hub;        // rows of vertices with at least this degree are split into tiles
+  uint32_t comb_degree;// decrements to vertices with at least this degree are combined in LDS
   int32_t tile;        // edges per tile (multiple of 64)
   int32_t chained;     // 1: local queues (chained mode)
   int32_t lq_budget;   // max vertices a wave peels from its local queue per phase
