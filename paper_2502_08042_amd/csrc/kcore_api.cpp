@@ -73,6 +73,8 @@ struct PeelWs {
   int32_t* act[2] = {nullptr, nullptr};
   int32_t* fr[2] = {nullptr, nullptr};
   int2* tl[2] = {nullptr, nullptr};
+  long long* aq = nullptr;
+  int64_t q_cap = 0;
   kc::PeelCtl* ctl = nullptr;
   unsigned long long* host_stats = nullptr;  // pinned
   unsigned* vstat = nullptr;                 // validation status + xor sum (device)
@@ -85,6 +87,7 @@ struct BatchWs {
   void* block = nullptr;
   uint32_t* gdt = nullptr;
   int32_t* gq = nullptr;
+  int32_t* ga = nullptr;
   int32_t* order = nullptr;
   kc::BatchCtl* ctl = nullptr;
   unsigned long long* host_stats = nullptr;
@@ -125,6 +128,8 @@ int peel_ws(int dev, hipStream_t s, int64_t n, int64_t tcap, PeelWs*& out) {
     const size_t o_f1 = off; off = align_up(off + 4 * (size_t)nc);
     const size_t o_t0 = off; off = align_up(off + 8 * (size_t)tc);
     const size_t o_t1 = off; off = align_up(off + 8 * (size_t)tc);
+    const int64_t qc = nc + tc + 256 * 64 * 64;  // entries of one phase + one claim per wave
+    const size_t o_q = off; off = align_up(off + 8 * (size_t)qc);
     const size_t o_c = off; off = align_up(off + sizeof(kc::PeelCtl));
     const size_t o_v = off; off = align_up(off + 64);
     hipError_t e = hipMalloc(&w->block, off);
@@ -143,6 +148,8 @@ int peel_ws(int dev, hipStream_t s, int64_t n, int64_t tcap, PeelWs*& out) {
     w->fr[1] = (int32_t*)(b + o_f1);
     w->tl[0] = (int2*)(b + o_t0);
     w->tl[1] = (int2*)(b + o_t1);
+    w->aq = (long long*)(b + o_q);
+    w->q_cap = qc;
     w->ctl = (kc::PeelCtl*)(b + o_c);
     w->vstat = (unsigned*)(b + o_v);
     w->n_cap = nc;
@@ -172,6 +179,7 @@ int batch_ws(int dev, hipStream_t s, int64_t V, int32_t G, BatchWs*& out) {
     size_t off = 0;
     const size_t o_d = off; off = align_up(off + 4 * (size_t)vc);
     const size_t o_q = off; off = align_up(off + 4 * (size_t)vc);
+    const size_t o_a = off; off = align_up(off + 4 * (size_t)vc);
     const size_t o_o = off; off = align_up(off + 4 * (size_t)gc);
     const size_t o_c = off; off = align_up(off + sizeof(kc::BatchCtl));
     const size_t o_v = off; off = align_up(off + 64);
@@ -185,6 +193,7 @@ int batch_ws(int dev, hipStream_t s, int64_t V, int32_t G, BatchWs*& out) {
     char* b = static_cast<char*>(w->block);
     w->gdt = (uint32_t*)(b + o_d);
     w->gq = (int32_t*)(b + o_q);
+    w->ga = (int32_t*)(b + o_a);
     w->order = (int32_t*)(b + o_o);
     w->ctl = (kc::BatchCtl*)(b + o_c);
     w->vstat = (unsigned*)(b + o_v);
@@ -317,8 +326,14 @@ int kcore_decompose_ex(const int64_t* offsets, const int32_t* adj, int64_t n, in
   a.chained = mode == KCORE_MODE_CHAINED ? 1 : 0;
   a.lq_budget = budget;
   a.big_phase = 16384;
+  a.aq = w->aq;
+  a.qcap = w->q_cap;
+  a.async_small = 65536;
+  a.async_tiles = 65536;
+  a.async_scan_max = 1 << 21;
 
   HIP_TRY(kc::launch_init_ctl(w->ctl, stream));
+  if (a.chained) HIP_TRY(kc::launch_fill_u32(w->aq, 0xffffffffu, 2 * (size_t)w->q_cap, stream));
   if (stats_host) HIP_TRY(hipEventRecord(w->ev0, stream));
   HIP_TRY(kc::launch_peel(a, blocks, stream));
   if (!stats_host) return KCORE_OK;
@@ -362,9 +377,31 @@ int kcore_decompose(const int64_t* offsets, const int32_t* adj, int64_t n, int32
   return kcore_decompose_ex(offsets, adj, n, coreness_out, stream, nullptr, nullptr);
 }
 
+static int batched_impl(const int64_t* graph_vptr, const int64_t* offsets, const int32_t* adj,
+                        int32_t num_graphs, int64_t total_vertices, int32_t* coreness_out,
+                        hipStream_t stream, const kcore_options* opt, kcore_stats* stats_host,
+                        bool local_ids);
+
 int kcore_decompose_batched_ex(const int64_t* graph_vptr, const int64_t* offsets, const int32_t* adj,
                                int32_t num_graphs, int64_t total_vertices, int32_t* coreness_out,
                                hipStream_t stream, const kcore_options* opt, kcore_stats* stats_host) {
+  return batched_impl(graph_vptr, offsets, adj, num_graphs, total_vertices, coreness_out, stream, opt,
+                      stats_host, false);
+}
+
+}  // extern "C"
+
+int kc::decompose_batched_local(const int64_t* graph_vptr, const int64_t* offsets, const int32_t* adj,
+                                int32_t num_graphs, int64_t total_vertices, int32_t* coreness_out,
+                                hipStream_t stream) {
+  return batched_impl(graph_vptr, offsets, adj, num_graphs, total_vertices, coreness_out, stream, nullptr,
+                      nullptr, true);
+}
+
+static int batched_impl(const int64_t* graph_vptr, const int64_t* offsets, const int32_t* adj,
+                        int32_t num_graphs, int64_t total_vertices, int32_t* coreness_out,
+                        hipStream_t stream, const kcore_options* opt, kcore_stats* stats_host,
+                        bool local_ids) {
   g_err.clear();
   if (num_graphs < 0 || total_vertices < 0)
     return fail(KCORE_EINVAL, "negative num_graphs or total_vertices");
@@ -406,6 +443,8 @@ int kcore_decompose_batched_ex(const int64_t* graph_vptr, const int64_t* offsets
   a.order = w->order;
   a.gdt = w->gdt;
   a.gq = w->gq;
+  a.ga = w->ga;
+  a.local_ids = local_ids ? 1 : 0;
   a.ctl = w->ctl;
   a.lds_cap = cap;
   if (stats_host) HIP_TRY(hipEventRecord(w->ev0, stream));
@@ -422,6 +461,8 @@ int kcore_decompose_batched_ex(const int64_t* graph_vptr, const int64_t* offsets
   stats_host->barriers = 0;
   return KCORE_OK;
 }
+
+extern "C" {
 
 int kcore_decompose_batched(const int64_t* graph_vptr, const int64_t* offsets, const int32_t* adj,
                             int32_t num_graphs, int64_t total_vertices, int32_t* coreness_out,

@@ -142,7 +142,7 @@ __device__ __forceinline__ void stage_push(Stage& s, bool p, int32_t v, unsigned
 }
 
 // Block-level final flush of every wave's leftovers with one atomic per block.
-__device__ void block_flush(Stage& s, unsigned long long* tail, int32_t* dst, long long cap,
+__device__ __forceinline__ void block_flush(Stage& s, unsigned long long* tail, int32_t* dst, long long cap,
                             unsigned* status, unsigned long long* s_cnt, unsigned long long* s_base) {
   const int w = threadIdx.x >> 6;
   __syncthreads();
@@ -185,7 +185,10 @@ struct WaveCtx {
   unsigned mymin;      // per-lane min over kept vertices
   int32_t* ckey;       // LDS combining table (block-shared): target id or -1
   uint32_t* ccnt;      //   decrements collected for it in this phase
-  bool precheck;       // phase-uniform: probe peeled bits and combine hub targets
+  bool precheck;       // phase-uniform: probe peeled bits
+  bool combine;        // phase-uniform: collect decrements of hot targets in LDS
+  bool async;          // phase-uniform: pushes go to the async work queue
+  bool arbitrate;      // phase-uniform: crossings may race with a scan (chained scan phases)
 };
 
 __device__ __forceinline__ unsigned comb_hash(int32_t u) {
@@ -221,6 +224,35 @@ struct PhaseOut {
 // Pushes crossed/extracted vertices: hubs are split into tiles on the global tile list, small
 // vertices go to the wave's local queue (chained mode, while it has room) or the staged frontier.
 // All lanes call.
+// Async work queue entry: low word vertex, high word tile index, or kWholeRow for a whole row.
+constexpr uint32_t kWholeRow = 0xffffffffu;
+constexpr long long kQEmpty = -1ll;
+
+// Appends work for the lanes with cnt > 0 to the phase's async queue: a whole row (cnt == 1 and
+// !tiles) or cnt tiles of a hub row. The tail counter doubles as the count of created entries: it
+// grows before an entry becomes visible, which the quiescence test relies on. All lanes call.
+__device__ __forceinline__ void queue_push(const PeelArgs& a, const PhaseOut& o, int32_t v, long long cnt,
+                                           bool tiles) {
+  const long long incl = wave_incl_scan(cnt);
+  const long long tot = __shfl(incl, 63, 64);
+  if (tot == 0) return;
+  unsigned long long base = 0;
+  if (lane_id() == 0) base = aadd(&o.slot->qtail, (unsigned long long)tot);
+  base = __shfl(base, 0, 64);
+  if ((long long)base + tot > a.qcap) {
+    if (lane_id() == 0) aor(&a.ctl->status, (unsigned)KC_ERR_OVERFLOW);
+    return;
+  }
+  const long long s0 = (long long)base + incl - cnt;
+  for (long long j = 0; j < cnt; ++j) {
+    const unsigned long long hi = tiles ? (unsigned long long)j : (unsigned long long)kWholeRow;
+    ast(&a.aq[s0 + j], (long long)((hi << 32) | (unsigned)v));
+  }
+}
+
+// Pushes crossed/extracted vertices: hubs are split into tiles, small vertices go to the wave's
+// local queue (chained mode, while it has room). Outside async phases the rest goes to the next
+// frontier (staged) and the tile list; in async phases both go to the async queue. All lanes call.
 __device__ __forceinline__ void push_vertices(const PeelArgs& a, WaveCtx& c, const PhaseOut& o,
                                               bool p, int32_t v, bool hub) {
   const bool ps = p && !hub;
@@ -230,6 +262,8 @@ __device__ __forceinline__ void push_vertices(const PeelArgs& a, WaveCtx& c, con
     if (a.chained && c.lq_cnt + cnt <= kLocalQ) {
       if (ps) c.lq[(c.lq_head + c.lq_cnt + rank_in(ms)) & (kLocalQ - 1)] = v;
       c.lq_cnt += cnt;
+    } else if (c.async) {
+      queue_push(a, o, v, ps ? 1 : 0, false);
     } else {
       stage_push(c.sf, ps, v, &o.slot->small, o.fr, a.fcap, &a.ctl->status);
     }
@@ -238,18 +272,19 @@ __device__ __forceinline__ void push_vertices(const PeelArgs& a, WaveCtx& c, con
   const unsigned long long mh = __ballot(ph);
   if (mh) {
     long long nt = 0;
-    long long deg = 0;
     if (ph) {
-      deg = a.off[v + 1] - a.off[v];
+      const long long deg = a.off[v + 1] - a.off[v];
       nt = (deg + a.tile - 1) / a.tile;
+    }
+    if (lane_id() == 0) aadd(&o.slot->hubv, (unsigned long long)__popcll(mh));
+    if (c.async) {
+      queue_push(a, o, v, nt, true);
+      return;
     }
     const long long incl = wave_incl_scan(nt);
     const long long tot = __shfl(incl, 63, 64);
     unsigned long long base = 0;
-    if (lane_id() == 0) {
-      base = aadd(&o.slot->tiles, (unsigned long long)tot);
-      aadd(&o.slot->hubv, (unsigned long long)__popcll(mh));
-    }
+    if (lane_id() == 0) base = aadd(&o.slot->tiles, (unsigned long long)tot);
     base = __shfl(base, 0, 64);
     if ((long long)base + tot > a.tcap) {
       if (lane_id() == 0) aor(&a.ctl->status, (unsigned)KC_ERR_OVERFLOW);
@@ -291,7 +326,7 @@ __device__ __forceinline__ void edges_batch(const PeelArgs& a, WaveCtx& c, const
     if ((sw[j] >> (u[j] & 15)) & 1u) continue;  // already peeled
     // hub targets collect their decrements in LDS for the rest of the phase (the flush applies
     // them with one atomic per target); everything else is decremented right away
-    if (((sw[j] >> (16 + (u[j] & 15))) & 1u) && comb_add(c, u[j])) {
+    if (c.combine && ((sw[j] >> (16 + (u[j] & 15))) & 1u) && comb_add(c, u[j])) {
       c.comb += 1;
       continue;
     }
@@ -304,11 +339,15 @@ __device__ __forceinline__ void edges_batch(const PeelArgs& a, WaveCtx& c, const
     bool crossed = ((did >> j) & 1u) && (old[j] & DMASK) == k + 1u;
     const bool hub = (old[j] & HUBBIT) != 0u;
     if (crossed) {
-      // the peeled bit decides ownership: in chained mode a scan may find u at the same time
       const uint32_t bit = 1u << (u[j] & 15);
-      if (aor(&a.state[u[j] >> 4], bit) & bit) {
-        crossed = false;
+      if (c.arbitrate) {
+        // a scan of this phase may find u at the same time: the peeled bit decides ownership
+        if (aor(&a.state[u[j] >> 4], bit) & bit) crossed = false;
       } else {
+        // only one decrement crosses k, so the lane owns u: set the bit without waiting for it
+        __hip_atomic_fetch_or(&a.state[u[j] >> 4], bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      if (crossed) {
         a.core[u[j]] = (int32_t)k;
         c.peeled += 1;
       }
@@ -320,7 +359,7 @@ __device__ __forceinline__ void edges_batch(const PeelArgs& a, WaveCtx& c, const
 // Expands the rows of up to 64 vertices (one per lane, -1 = none) edge-balanced across the wave:
 // an exclusive scan of the degrees, then each lane finds the row of each of its entries by binary
 // search over the scan.
-__device__ void expand_rows(const PeelArgs& a, WaveCtx& c, const PhaseOut& o, int32_t v, uint32_t k) {
+__device__ __forceinline__ void expand_rows(const PeelArgs& a, WaveCtx& c, const PhaseOut& o, int32_t v, uint32_t k) {
   long long b = 0, d = 0;
   if (v >= 0) {
     b = a.off[v];
@@ -355,8 +394,11 @@ __device__ void expand_rows(const PeelArgs& a, WaveCtx& c, const PhaseOut& o, in
 }
 
 // A tile of a hub row: edges [off[v] + j*tile, min(off[v+1], off[v] + (j+1)*tile)).
-__device__ void expand_tile(const PeelArgs& a, WaveCtx& c, const PhaseOut& o, int32_t v, int32_t j,
+__device__ __forceinline__ void expand_tile(const PeelArgs& a, WaveCtx& c, const PhaseOut& o, int32_t v, int32_t j,
                             uint32_t k) {
+  // hub rows mostly point at vertices peeled long ago: always probe the peeled bits here
+  const bool saved = c.precheck;
+  c.precheck = true;
   const long long rb = a.off[v], re = a.off[v + 1];
   const long long b = rb + (long long)j * a.tile;
   const long long e = min(re, b + a.tile);
@@ -374,12 +416,13 @@ __device__ void expand_tile(const PeelArgs& a, WaveCtx& c, const PhaseOut& o, in
     }
     edges_batch(a, c, o, u, valid, k);
   }
+  c.precheck = saved;
 }
 
 // Applies the block's combined decrements: one atomic subtraction of c per target; exactly one
 // subtraction takes a target from above k to k or below (old > k >= old - c), and that one pushes
 // it. Clears the table for the next phase. All threads of the block call.
-__device__ void comb_flush(const PeelArgs& a, WaveCtx& c, const PhaseOut& o, uint32_t k) {
+__device__ __forceinline__ void comb_flush(const PeelArgs& a, WaveCtx& c, const PhaseOut& o, uint32_t k) {
   __syncthreads();
   for (int s0 = 0; s0 < kCombSlots; s0 += kPeelThreads) {
     const int s = s0 + threadIdx.x;
@@ -409,7 +452,7 @@ __device__ void comb_flush(const PeelArgs& a, WaveCtx& c, const PhaseOut& o, uin
 
 // Chained mode: peel what the wave queued locally, in packets of up to 64 vertices, until the
 // queue is empty or the wave's budget for this phase is spent; what is left joins the frontier.
-__device__ void drain_local(const PeelArgs& a, WaveCtx& c, const PhaseOut& o, uint32_t k) {
+__device__ __forceinline__ void drain_local(const PeelArgs& a, WaveCtx& c, const PhaseOut& o, uint32_t k) {
   while (c.lq_cnt > 0 && c.lq_used < a.lq_budget) {
     const int take = c.lq_cnt < 64 ? c.lq_cnt : 64;
     const int32_t v = lane_id() < take ? c.lq[(c.lq_head + lane_id()) & (kLocalQ - 1)] : -1;
@@ -424,11 +467,89 @@ __device__ void drain_local(const PeelArgs& a, WaveCtx& c, const PhaseOut& o, ui
     const int32_t v = p ? c.lq[(c.lq_head + lane_id()) & (kLocalQ - 1)] : 0;
     c.lq_head = (c.lq_head + take) & (kLocalQ - 1);
     c.lq_cnt -= take;
-    stage_push(c.sf, p, v, &o.slot->small, o.fr, a.fcap, &a.ctl->status);
+    if (c.async)
+      queue_push(a, o, v, p ? 1 : 0, false);
+    else
+      stage_push(c.sf, p, v, &o.slot->small, o.fr, a.fcap, &a.ctl->status);
   }
 }
 
-enum PhaseKind { PH_SCAN = 0, PH_EXPAND = 1 };
+// Async phase, dynamic part: each wave claims one queue slot at a time, waits until the slot is
+// filled or the phase is quiescent, and peels what it holds (a whole row or a hub tile), together
+// with the local chain it starts. Quiescent = every workgroup finished its static share and every
+// created entry is done; done is counted after an entry's pushes, so when done equals the tail
+// (read after done) nothing is left in flight and nothing more can be created. Only wave 0 of a
+// workgroup polls those shared counters (and publishes the outcome in LDS for its siblings), so
+// waiting waves do not slow down the atomics of working ones. Waits are bounded.
+__device__ __forceinline__ void async_loop(const PeelArgs& a, WaveCtx& c, const PhaseOut& o, uint32_t k,
+                                           volatile int* s_quiet) {
+  PhaseSlot* S = o.slot;
+  const unsigned nb = gridDim.x;
+  const bool watcher = (threadIdx.x >> 6) == 0;
+  for (;;) {
+    unsigned long long idx = 0;
+    if (lane_id() == 0) idx = aadd(&S->qhead, 1ull);
+    idx = __shfl(idx, 0, 64);
+    long long e = kQEmpty;
+    int state = 0;  // 0 waiting, 1 got entry, 2 quiescent, 3 error
+    if (lane_id() == 0) {
+      const unsigned long long t0 = wall_clock64();
+      for (int spin = 0;; ++spin) {
+        if ((long long)idx < a.qcap) {
+          e = ald(&a.aq[idx]);
+          if (e != kQEmpty) {
+            state = 1;
+            break;
+          }
+        }
+        const int q = *s_quiet;
+        if (q) {
+          state = q;
+          break;
+        }
+        if (watcher) {
+          if (ald(&S->bdone) >= nb) {
+            const unsigned long long dn = ald(&S->qdone);
+            const unsigned long long tl = ald(&S->qtail);
+            if (dn == tl && (long long)idx >= (long long)tl) {
+              *s_quiet = 2;
+              state = 2;
+              break;
+            }
+          }
+          if (ald(&a.ctl->status) != 0u) {
+            *s_quiet = 3;
+            state = 3;
+            break;
+          }
+        }
+        __builtin_amdgcn_s_sleep(2);
+        if ((spin & 255) == 255 && wall_clock64() - t0 > 400000000ull) {
+          aor(&a.ctl->status, (unsigned)KC_ERR_TIMEOUT);
+          *s_quiet = 3;
+          state = 3;
+          break;
+        }
+      }
+    }
+    state = __shfl(state, 0, 64);
+    if (state != 1) return;
+    e = __shfl(e, 0, 64);
+    if (lane_id() == 0) ast(&a.aq[idx], kQEmpty);  // slots start empty in every async phase
+    const int32_t v = (int32_t)(e & 0xffffffffll);
+    const uint32_t j = (uint32_t)((unsigned long long)e >> 32);
+    c.lq_used = 0;
+    if (j == kWholeRow)
+      expand_rows(a, c, o, lane_id() == 0 ? v : -1, k);
+    else
+      expand_tile(a, c, o, v, (int32_t)j, k);
+    if (a.chained) drain_local(a, c, o, k);
+    __builtin_amdgcn_s_waitcnt(0);
+    if (lane_id() == 0) aadd(&S->qdone, 1ull);
+  }
+}
+
+enum PhaseKind { PH_SCAN = 0, PH_EXPAND = 1, PH_ASYNC = 2 };
 
 __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
   __shared__ int32_t s_sf[kWaves][kStage];
@@ -439,6 +560,7 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
   __shared__ unsigned s_red[kWaves];
   __shared__ long long s_red64[kWaves];
   __shared__ long long s_out[8];
+  __shared__ int s_quiet;
   __shared__ int32_t s_ckey[kCombSlots];
   __shared__ uint32_t s_ccnt[kCombSlots];
 
@@ -531,6 +653,10 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
       ast(&r->hubv, 0ull);
       ast(&r->active, 0ull);
       ast(&r->peeled, 0ull);
+      ast(&r->qhead, 0ull);
+      ast(&r->qtail, 0ull);
+      ast(&r->qdone, 0ull);
+      ast(&r->bdone, 0u);
       ast(&r->minv, 0xffffffffu);
     }
     const uint32_t k = (uint32_t)kx;
@@ -540,6 +666,12 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
     // large phases are bandwidth bound: probe peeled bits and combine hub decrements; small ones
     // are latency bound: skip the probe and spread the frontier over as many waves as possible
     c.precheck = kind == PH_SCAN ? asize >= a.big_phase * 16 : (fs + ft * (a.tile / 16)) >= a.big_phase;
+    // chained mode folds the round's whole peel into its scan phase once the active set is small
+    const bool async_scan = kind == PH_SCAN && a.chained && asize <= a.async_scan_max;
+    // deferred (combined) decrements would hide work from the async quiescence test
+    c.async = kind == PH_ASYNC || async_scan;
+    c.combine = c.precheck && !c.async;
+    c.arbitrate = kind == PH_SCAN && a.chained;
     long long peeled_before = c.peeled;
     if (kind == PH_SCAN) {
       // Alg. 1: F = {v in A : induced degree <= k}; survivors refine A.
@@ -577,7 +709,8 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
         push_vertices(a, c, o, ext, v, (word & HUBBIT) != 0u);
       }
     } else {
-      // Alg. 3 over the frontier: packets of 64 small vertices, then hub tiles.
+      // Alg. 3 over the frontier: packets of small vertices, then hub tiles (the static share of
+      // an async phase is the same).
       const int32_t* fcur = a.fr[(p - 1) & 1];
       const int2* tcur = a.tl[(p - 1) & 1];
       int per = 64;  // frontier vertices per wave item: fewer when the frontier is small
@@ -598,6 +731,17 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
       }
     }
     if (a.chained) drain_local(a, c, o, k);
+    if (c.async) {
+      if (threadIdx.x == 0) s_quiet = 0;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        __builtin_amdgcn_s_waitcnt(0);
+        aadd(&o.slot->bdone, 1u);
+      }
+      // a few waves per workgroup take part in the dynamic part: every claim is an atomic on one
+      // shared counter, so thousands of claimers would serialise there
+      if ((threadIdx.x >> 6) < kAsyncWaves) async_loop(a, c, o, k, &s_quiet);
+    }
     comb_flush(a, c, o, k);
     if (a.chained) drain_local(a, c, o, k);
     if (tr) C->trace[p][1] = wall_clock64();
@@ -654,7 +798,9 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
     }
     total_peeled += npeel;
     removed_since += npeel;
-    if (kind == PH_EXPAND) st_sub++;
+    if (kind != PH_SCAN) st_sub++;
+    // small frontiers of chained mode are peeled by the async phase
+    const bool go_async = a.chained && nfs <= a.async_small && nft <= a.async_tiles;
     if (npeel > 0) kmax_seen = k;
     if (kind == PH_SCAN && compact) {
       asize = nact;
@@ -665,7 +811,7 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
     if (kind == PH_SCAN) {
       if (npeel > 0) st_rounds++;
       if (nfs + nft > 0) {
-        kind = PH_EXPAND;
+        kind = go_async ? PH_ASYNC : PH_EXPAND;
         fs = nfs;
         ft = nft;
       } else if (total_peeled >= n) {
@@ -691,6 +837,7 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
       }
     } else {
       if (nfs + nft > 0) {
+        kind = go_async ? PH_ASYNC : PH_EXPAND;
         fs = nfs;
         ft = nft;
       } else if (total_peeled >= n) {
@@ -825,23 +972,44 @@ __global__ __launch_bounds__(kBatchThreads) void batched_kernel(BatchArgs a) {
     __syncthreads();
 
     int head = 0;
-    bool scan_eq = true;  // extraction test: at round start every live vertex has d >= k
+    // Graphs held in global memory keep a compacted active list (Alg. 1 refine): each round's
+    // scan reads the survivors of the previous one and writes its own survivors in place (a
+    // survivor never moves forward, and a chunk is read before it is overwritten). LDS-resident
+    // graphs are small enough to scan whole.
+    int32_t* act = inl ? nullptr : a.ga + base;
+    long long asz = ng;
+    bool dense_b = true;
     for (;;) {
-      // extraction of round k's first frontier; also the min over the others for a jump
+      // extraction of round k's first frontier (at round start every live vertex has d >= k);
+      // also the min over the others for a jump
       unsigned nm = 0xffffffffu;
-      for (long long i0 = 0; i0 < ng; i0 += kBatchThreads) {
+      long long wpos = 0;
+      for (long long i0 = 0; i0 < asz; i0 += kBatchThreads) {
         const long long i = i0 + tid;
-        bool ext = false;
-        if (i < ng) {
-          const unsigned x = d[i];
+        bool ext = false, keep = false;
+        int32_t vi = 0;
+        if (i < asz) {
+          vi = dense_b ? (int32_t)i : act[i];
+          const unsigned x = d[vi];
           st_scanned++;
           ext = x == k;
-          if (x > k) nm = min(nm, x);
+          keep = x > k;
+          if (keep) nm = min(nm, x);
         }
-        team_push(ext, (int32_t)i, q, &s_tail);
-        if (ext) a.core[base + i] = (int32_t)k;
+        team_push(ext, vi, q, &s_tail);
+        if (ext) a.core[base + vi] = (int32_t)k;
+        if (!inl) {
+          long long kept;
+          const long long ex = block_excl_scan(keep ? 1 : 0, s_w, kept);
+          if (keep) act[wpos + ex] = vi;
+          wpos += kept;
+          __syncthreads();
+        }
       }
-      (void)scan_eq;
+      if (!inl) {
+        asz = wpos;
+        dense_b = false;
+      }
       nm = wave_min(nm);
       if (l == 0) s_min[w] = nm;
       __syncthreads();
@@ -884,7 +1052,7 @@ __global__ __launch_bounds__(kBatchThreads) void batched_kernel(BatchArgs a) {
                 if (s_pref[mid] <= t) lo = mid; else hi = mid - 1;
               }
               const long long pos = s_rb[lo] + (t - s_pref[lo]);
-              ul = a.adj[pos] - (int32_t)base;
+              ul = a.adj[pos] - (a.local_ids ? 0 : (int32_t)base);
               st_edges++;
               if (d[ul] > k) {
                 const unsigned old = inl ? atomicSub(&d[ul], 1u) : wsub(&d[ul], 1u);

@@ -13,6 +13,7 @@ constexpr int kCombBits = 12;
 constexpr int kCombSlots = 1 << kCombBits;  // per-workgroup LDS combining table for hub targets
 constexpr int kCombProbe = 4;               // linear-probe window of that table
 constexpr int kEdgeUnroll = 2;              // adjacency entries in flight per lane
+constexpr int kAsyncWaves = 2;              // waves per workgroup claiming async work
 constexpr int kBarGroups = 32;       // arrival groups of the grid barrier
 constexpr int kBatchThreads = 512;   // threads per workgroup of the batched peel
 constexpr int kTracePhases = 1024;   // phases whose timeline workgroup 0 records
@@ -29,8 +30,12 @@ struct alignas(128) PhaseSlot {
   unsigned long long hubv;    // hub vertices pushed
   unsigned long long active;  // compacted active-list tail
   unsigned long long peeled;  // vertices given a coreness in the phase
+  unsigned long long qhead;   // async queue: next slot to claim
+  unsigned long long qtail;   //   entries created (= slots filled or being filled)
+  unsigned long long qdone;   //   entries fully processed
+  unsigned int bdone;         //   workgroups done with their static share
   unsigned int minv;          // min induced degree over vertices kept by a scan
-  unsigned int pad[5];
+  unsigned int pad[6];
 };
 
 struct alignas(128) PeelCtl {
@@ -68,6 +73,11 @@ struct PeelArgs {
   int32_t chained;     // 1: local queues (chained mode)
   int32_t lq_budget;   // max vertices a wave peels from its local queue per phase
   int64_t big_phase;   // frontier size from which a phase probes peeled bits and combines hubs
+  long long* aq;       // async work queue (entries, -1 = empty), qcap slots
+  int64_t qcap;
+  int64_t async_small; // chained mode: frontiers up to this many small vertices ...
+  int64_t async_tiles; //   ... and tiles are peeled by an async phase
+  int64_t async_scan_max; // chained mode: active sets up to this size scan and peel in one phase
 };
 
 struct BatchCtl {
@@ -86,12 +96,20 @@ struct BatchArgs {
   const int32_t* order;   // processing order (largest first)
   uint32_t* gdt;          // global induced degrees for graphs beyond the LDS capacity
   int32_t* gq;            // global peel queues for those graphs
+  int32_t* ga;            // global active lists for those graphs
+  int32_t local_ids;      // adjacency holds per-graph local ids (serving) instead of global ids
   BatchCtl* ctl;
   int32_t lds_cap;        // vertices per graph held in LDS
 };
 
 // Error text returned by kcore_last_error (thread-local; defined in kcore_api.cpp).
 void set_error(const char* msg);
+
+// kcore_decompose_batched with per-graph local ids in adj (used by the serving runtime, which
+// then packs requests without rewriting their adjacency). Defined in kcore_api.cpp.
+int decompose_batched_local(const int64_t* graph_vptr, const int64_t* offsets, const int32_t* adj,
+                            int32_t num_graphs, int64_t total_vertices, int32_t* coreness_out,
+                            hipStream_t stream);
 
 // Launch helpers (defined in kcore_device.hip).
 hipError_t launch_peel(const PeelArgs& a, int blocks, hipStream_t s);

@@ -54,9 +54,37 @@ struct Slot {
   int64_t bytes = 0;
   int64_t batch_id = 0;
   int rc = 0;
+  bool large = false;
 };
 
 int64_t footprint(int64_t n, int64_t m) { return 8 * (n + 1) + 4 * m + 16 * n + 64; }
+
+// Requests at least this large run in batches of their own class, so that a large graph (peeled by
+// one workgroup) never holds up the completion of a batch of small ones.
+constexpr int64_t kLargeEntries = 1 << 21;
+bool is_large(int64_t n, int64_t m) { return m >= kLargeEntries || n >= (1 << 16); }
+
+// memcpy split over a few threads for large buffers (request intake and batch packing are the
+// host-side cost of serving large graphs).
+void par_copy(void* dst, const void* src, size_t bytes) {
+  const size_t kMin = 8u << 20;
+  if (bytes < kMin) {
+    memcpy(dst, src, bytes);
+    return;
+  }
+  unsigned t = std::thread::hardware_concurrency();
+  t = t < 2 ? 2 : (t > 8 ? 8 : t);
+  const size_t chunk = ((bytes + t - 1) / t + 63) & ~size_t(63);
+  std::vector<std::thread> th;
+  for (unsigned i = 1; i < t; ++i) {
+    const size_t o = chunk * i;
+    if (o >= bytes) break;
+    const size_t len = o + chunk > bytes ? bytes - o : chunk;
+    th.emplace_back([=] { memcpy(static_cast<char*>(dst) + o, static_cast<const char*>(src) + o, len); });
+  }
+  memcpy(dst, src, chunk < bytes ? chunk : bytes);
+  for (auto& x : th) x.join();
+}
 
 }  // namespace
 
@@ -138,10 +166,8 @@ int launch_slot(kcore_server* s, Slot* sl) {
   for (int64_t g = 0; g < G; ++g) {
     Request* r = sl->reqs[g];
     for (int64_t i = 0; i < r->n; ++i) sl->off_h[vb + i] = eb + r->off[i];
-    const int32_t base = (int32_t)vb;
-    const int32_t* src = r->adj.data();
-    int32_t* dst = sl->adj_h + eb;
-    for (int64_t i = 0; i < r->m; ++i) dst[i] = src[i] + base;
+    // adjacency keeps the request's own (local) ids: the peel is launched in local-id mode
+    if (r->m) par_copy(sl->adj_h + eb, r->adj.data(), sizeof(int32_t) * (size_t)r->m);
     vb += r->n;
     eb += r->m;
     sl->vptr_h[g + 1] = vb;
@@ -152,7 +178,7 @@ int launch_slot(kcore_server* s, Slot* sl) {
       hipMemcpyAsync(sl->off_d, sl->off_h, 8 * (V + 1), hipMemcpyHostToDevice, st) != hipSuccess ||
       (E > 0 && hipMemcpyAsync(sl->adj_d, sl->adj_h, 4 * E, hipMemcpyHostToDevice, st) != hipSuccess))
     return KCORE_EDEVICE;
-  int rc = kcore_decompose_batched(sl->vptr_d, sl->off_d, sl->adj_d, (int32_t)G, V, sl->core_d, st);
+  int rc = kc::decompose_batched_local(sl->vptr_d, sl->off_d, sl->adj_d, (int32_t)G, V, sl->core_d, st);
   if (rc) return rc;
   if (hipMemcpyAsync(sl->core_h, sl->core_d, 4 * V, hipMemcpyDeviceToHost, st) != hipSuccess)
     return KCORE_EDEVICE;
@@ -207,19 +233,31 @@ void dispatcher(kcore_server* s) {
     }
     if (s->stop && busy == 0) break;
     if (!s->stop && free_slot && !s->queue.empty()) {
-      // admit in arrival order while the budget and batch limits allow
+      // Admit in arrival order, one size class per batch: the class of the oldest request, then
+      // every queued request of that class while the budget and batch limits allow. Large
+      // batches may not take the last free slot, so small requests always have one.
+      int busy_large = 0;
+      for (Slot* sl : s->slots)
+        if (sl->busy && sl->large) ++busy_large;
+      const bool large_ok = s->slots.size() == 1 || busy_large + 1 < (int)s->slots.size();
+      const bool large = large_ok && is_large(s->queue.front()->n, s->queue.front()->m);
       int64_t V = 0, bytes = 0;
       std::vector<Request*> take;
-      while (!s->queue.empty()) {
-        Request* r = s->queue.front();
+      for (auto it = s->queue.begin(); it != s->queue.end();) {
+        Request* r = *it;
+        if (is_large(r->n, r->m) != large) {
+          ++it;
+          continue;
+        }
         if ((int64_t)take.size() >= s->cfg.max_batch_graphs) break;
         if (!take.empty() && V + r->n > s->cfg.max_batch_vertices) break;
         if (s->bytes_in_use + bytes + r->bytes > s->cfg.hbm_budget_bytes) break;
-        s->queue.pop_front();
+        it = s->queue.erase(it);
         take.push_back(r);
         V += r->n;
         bytes += r->bytes;
       }
+      free_slot->large = large;
       if (!take.empty()) {
         const double t = s->now_us();
         free_slot->busy = true;
@@ -314,7 +352,10 @@ int kcore_submit(kcore_server* s, const int64_t* offsets_host, const int32_t* ad
   r->m = m;
   r->bytes = bytes;
   r->off.assign(offsets_host, offsets_host + n + 1);
-  if (m) r->adj.assign(adj_host, adj_host + m);
+  if (m) {
+    r->adj.resize((size_t)m);
+    par_copy(r->adj.data(), adj_host, sizeof(int32_t) * (size_t)m);
+  }
   {
     std::lock_guard<std::mutex> lk(s->mu);
     r->ticket = s->next_ticket++;
