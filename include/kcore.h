@@ -72,7 +72,13 @@ typedef struct {
   int32_t local_budget;  /* chained mode: vertices one wavefront may peel from its local queue per
                             phase before handing the rest to the global frontier; 0 = default */
   int32_t tile_edges;    /* adjacency entries per hub tile (multiple of 64); 0 = default */
-  int32_t reserved[4];   /* must be zero */
+  int32_t async_frontier;/* chained mode: a frontier of at most this many vertices (and as many
+                            hub tiles) is peeled by one asynchronous phase with a shared work
+                            queue instead of barrier-separated subrounds; 0 = default, -1 = never */
+  int32_t async_scan;    /* chained mode: while the active set has at most this many vertices the
+                            round's scan and its whole peel run as one asynchronous phase (one
+                            barrier per round); 0 = default, -1 = never */
+  int32_t reserved[2];   /* must be zero */
 } kcore_options;
 
 /* Counters of one decomposition (filled when a kcore_stats* is passed; that call synchronises
@@ -144,7 +150,11 @@ typedef struct {
   int64_t max_request_vertices;/* larger requests are rejected with KCORE_ETOOBIG (0 = no limit) */
   double batch_wait_us;        /* how long the dispatcher waits to grow a batch while the device
                                   is busy (0 = 50 us) */
-  int32_t reserved[4];
+  int32_t borrow_inputs;       /* nonzero: kcore_submit does not copy; the caller keeps offsets and
+                                  adj unchanged and alive until kcore_poll/kcore_wait returns the
+                                  result (host-to-device copies then read them directly, at DMA
+                                  speed when the caller's memory is pinned) */
+  int32_t reserved[3];
 } kcore_server_config;
 
 typedef struct {
@@ -160,7 +170,8 @@ typedef struct {
 /* Returns null on failure (see kcore_last_error). */
 kcore_server* kcore_server_create(const kcore_server_config* cfg);
 
-/* Host CSR (offsets int64[n+1], adj int32[offsets[n]]), copied before return. */
+/* Host CSR (offsets int64[n+1], adj int32[offsets[n]]), copied before return unless the server
+ * borrows inputs (kcore_server_config.borrow_inputs). */
 int kcore_submit(kcore_server* s, const int64_t* offsets_host, const int32_t* adj_host, int64_t n,
                  uint64_t* ticket_out);
 

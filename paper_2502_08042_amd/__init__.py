@@ -46,7 +46,8 @@ class Options(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("validate", ctypes.c_int32),
                 ("blocks_per_cu", ctypes.c_int32), ("hub_degree", ctypes.c_int32),
                 ("num_entries", ctypes.c_int64), ("local_budget", ctypes.c_int32),
-                ("tile_edges", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+                ("tile_edges", ctypes.c_int32), ("async_frontier", ctypes.c_int32),
+                ("async_scan", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
 
 class Stats(ctypes.Structure):
@@ -66,7 +67,7 @@ class ServerConfig(ctypes.Structure):
                 ("max_batch_graphs", ctypes.c_int32), ("reserved0", ctypes.c_int32),
                 ("max_batch_vertices", ctypes.c_int64), ("hbm_budget_bytes", ctypes.c_int64),
                 ("max_request_vertices", ctypes.c_int64), ("batch_wait_us", ctypes.c_double),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("borrow_inputs", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class RequestStats(ctypes.Structure):
@@ -105,6 +106,10 @@ def _load():
         raise ImportError(f"{LIB_PATH} is missing: build it first with "
                           "`python -c 'import __graft_entry__ as g; g.build()'` "
                           "(hipcc --offload-arch=gfx950); there is no fallback path")
+    # PyTorch ships its own copy of the HIP runtime under the same soname. Loading PyTorch first
+    # makes the dynamic loader bind this library to that copy; the other order would put two HIP
+    # (and HSA) runtimes in one process, and the one initialised second finds no device.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     for name, (res, args) in SIGNATURES.items():
         f = getattr(lib, name)
@@ -136,7 +141,7 @@ def _stream_ptr(stream) -> int:
 
 
 def _options(mode, validate, num_entries, hub_degree=0, local_budget=0, tile_edges=0,
-             blocks_per_cu=0) -> Options:
+             blocks_per_cu=0, async_frontier=0, async_scan=0) -> Options:
     o = Options()
     o.mode = MODES[mode] if isinstance(mode, str) else int(mode)
     o.validate = 1 if validate else 0
@@ -145,6 +150,8 @@ def _options(mode, validate, num_entries, hub_degree=0, local_budget=0, tile_edg
     o.num_entries = num_entries
     o.local_budget = local_budget
     o.tile_edges = tile_edges
+    o.async_frontier = async_frontier
+    o.async_scan = async_scan
     return o
 
 
@@ -211,7 +218,8 @@ class Server:
 
     def __init__(self, device: int = 0, max_inflight: int = 0, max_batch_graphs: int = 0,
                  max_batch_vertices: int = 0, hbm_budget_bytes: int = 0,
-                 max_request_vertices: int = 0, batch_wait_us: float = 0.0):
+                 max_request_vertices: int = 0, batch_wait_us: float = 0.0,
+                 borrow_inputs: bool = False):
         cfg = ServerConfig()
         cfg.device = device
         cfg.max_inflight = max_inflight
@@ -220,12 +228,17 @@ class Server:
         cfg.hbm_budget_bytes = hbm_budget_bytes
         cfg.max_request_vertices = max_request_vertices
         cfg.batch_wait_us = batch_wait_us
+        cfg.borrow_inputs = 1 if borrow_inputs else 0
         self._h = _lib.kcore_server_create(ctypes.byref(cfg))
         if not self._h:
             raise KcoreError(-1, "kcore_server_create", last_error())
         self._n = {}
+        self._borrow = bool(borrow_inputs)
+        self._held = {}
 
     def submit(self, offsets: np.ndarray, adj: np.ndarray) -> int:
+        """Queues a host graph. With borrow_inputs the arrays must stay alive and unchanged until
+        the result is taken (this object keeps a reference until then)."""
         off = np.ascontiguousarray(offsets, dtype=np.int64)
         a = np.ascontiguousarray(adj, dtype=np.int32)
         n = off.shape[0] - 1
@@ -234,6 +247,8 @@ class Server:
                                ctypes.byref(t))
         _check(rc, "kcore_submit")
         self._n[t.value] = n
+        if self._borrow:
+            self._held[t.value] = (off, a)
         return t.value
 
     def poll(self, ticket: int):
@@ -245,6 +260,7 @@ class Server:
         if rc == KCORE_PENDING:
             return rc, None, None
         self._n.pop(ticket, None)
+        self._held.pop(ticket, None)
         _check(rc, "kcore_poll")
         return rc, out, st.as_dict()
 
@@ -257,6 +273,7 @@ class Server:
         if rc == KCORE_PENDING:
             raise TimeoutError(f"ticket {ticket} not done after {timeout_us} us")
         self._n.pop(ticket, None)
+        self._held.pop(ticket, None)
         _check(rc, "kcore_wait")
         return (out, st.as_dict()) if with_stats else out
 

@@ -210,8 +210,9 @@ int check_opts(const kcore_options* o) {
   if (o->blocks_per_cu < 0 || o->hub_degree < 0 || o->num_entries < 0 || o->local_budget < 0 ||
       o->tile_edges < 0 || (o->tile_edges % 64) != 0)
     return fail(KCORE_EINVAL, "negative option, or tile_edges not a multiple of 64");
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 2; ++i)
     if (o->reserved[i]) return fail(KCORE_EINVAL, "reserved option fields must be zero");
+  if (o->async_frontier < -1 || o->async_scan < -1) return fail(KCORE_EINVAL, "async thresholds must be >= -1");
   return KCORE_OK;
 }
 
@@ -270,7 +271,7 @@ int kcore_decompose_ex(const int64_t* offsets, const int32_t* adj, int64_t n, in
   if (int rc = dev_info(dev, di)) return rc;
 
   const int mode = (opt && opt->mode) ? opt->mode : KCORE_MODE_CHAINED;
-  const uint32_t hub = (opt && opt->hub_degree) ? (uint32_t)opt->hub_degree : 128u;
+  const uint32_t hub = (opt && opt->hub_degree) ? (uint32_t)opt->hub_degree : 256u;
   const int tile = (opt && opt->tile_edges) ? opt->tile_edges : 256;
   const int budget = (opt && opt->local_budget) ? opt->local_budget : 4096;
   int64_t m = opt ? opt->num_entries : 0;
@@ -328,9 +329,13 @@ int kcore_decompose_ex(const int64_t* offsets, const int32_t* adj, int64_t n, in
   a.big_phase = 16384;
   a.aq = w->aq;
   a.qcap = w->q_cap;
-  a.async_small = 65536;
-  a.async_tiles = 65536;
-  a.async_scan_max = 1 << 21;
+  const int32_t af = opt ? opt->async_frontier : 0;
+  const int32_t as = opt ? opt->async_scan : 0;
+  a.async_small = af < 0 ? -1 : (af ? af : 65536);
+  // hub tiles are better spread over every wave by a barrier-separated phase than claimed one
+  // by one from the shared queue: frontiers with more than a few tiles stay synchronous
+  a.async_tiles = af < 0 ? -1 : 64;
+  a.async_scan_max = as < 0 ? -1 : (as ? as : 0);
 
   HIP_TRY(kc::launch_init_ctl(w->ctl, stream));
   if (a.chained) HIP_TRY(kc::launch_fill_u32(w->aq, 0xffffffffu, 2 * (size_t)w->q_cap, stream));

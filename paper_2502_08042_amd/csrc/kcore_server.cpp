@@ -14,6 +14,7 @@
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
+#include <cstdio>
 #include <cstring>
 #include <deque>
 #include <mutex>
@@ -32,8 +33,10 @@ enum ReqState { RQ_QUEUED, RQ_RUNNING, RQ_DONE, RQ_CANCELED, RQ_FAILED };
 struct Request {
   uint64_t ticket = 0;
   int64_t n = 0, m = 0;
-  std::vector<int64_t> off;
+  std::vector<int64_t> off;  // owned copies (copying servers)
   std::vector<int32_t> adj;
+  const int64_t* offp = nullptr;  // what the dispatcher reads: the copies or the caller's arrays
+  const int32_t* adjp = nullptr;
   std::vector<int32_t> core;
   int state = RQ_QUEUED;
   int err = 0;
@@ -163,20 +166,31 @@ int launch_slot(kcore_server* s, Slot* sl) {
   if (int rc = grow(sl, V, E, G)) return rc;
   int64_t vb = 0, eb = 0;
   sl->vptr_h[0] = 0;
+  hipStream_t st = sl->stream;
+  // Borrowed large requests are copied to the device straight from the caller's arrays (one DMA
+  // each); everything else is packed into the slot's pinned buffer and copied in one piece.
+  const bool direct = s->cfg.borrow_inputs && sl->large;
   for (int64_t g = 0; g < G; ++g) {
     Request* r = sl->reqs[g];
-    for (int64_t i = 0; i < r->n; ++i) sl->off_h[vb + i] = eb + r->off[i];
+    for (int64_t i = 0; i < r->n; ++i) sl->off_h[vb + i] = eb + r->offp[i];
     // adjacency keeps the request's own (local) ids: the peel is launched in local-id mode
-    if (r->m) par_copy(sl->adj_h + eb, r->adj.data(), sizeof(int32_t) * (size_t)r->m);
+    if (r->m) {
+      if (direct) {
+        if (hipMemcpyAsync(sl->adj_d + eb, r->adjp, sizeof(int32_t) * (size_t)r->m, hipMemcpyHostToDevice,
+                           st) != hipSuccess)
+          return KCORE_EDEVICE;
+      } else {
+        par_copy(sl->adj_h + eb, r->adjp, sizeof(int32_t) * (size_t)r->m);
+      }
+    }
     vb += r->n;
     eb += r->m;
     sl->vptr_h[g + 1] = vb;
   }
   sl->off_h[V] = E;
-  hipStream_t st = sl->stream;
   if (hipMemcpyAsync(sl->vptr_d, sl->vptr_h, 8 * (G + 1), hipMemcpyHostToDevice, st) != hipSuccess ||
       hipMemcpyAsync(sl->off_d, sl->off_h, 8 * (V + 1), hipMemcpyHostToDevice, st) != hipSuccess ||
-      (E > 0 && hipMemcpyAsync(sl->adj_d, sl->adj_h, 4 * E, hipMemcpyHostToDevice, st) != hipSuccess))
+      (!direct && E > 0 && hipMemcpyAsync(sl->adj_d, sl->adj_h, 4 * E, hipMemcpyHostToDevice, st) != hipSuccess))
     return KCORE_EDEVICE;
   int rc = kc::decompose_batched_local(sl->vptr_d, sl->off_d, sl->adj_d, (int32_t)G, V, sl->core_d, st);
   if (rc) return rc;
@@ -206,6 +220,8 @@ void finish_slot(kcore_server* s, Slot* sl) {
     r->st.done_us = t;
     std::vector<int64_t>().swap(r->off);
     std::vector<int32_t>().swap(r->adj);
+    r->offp = nullptr;
+    r->adjp = nullptr;
   }
   s->bytes_in_use -= sl->bytes;
   sl->bytes = 0;
@@ -309,8 +325,12 @@ kcore_server* kcore_server_create(const kcore_server_config* cfg) {
   if (!c.hbm_budget_bytes) c.hbm_budget_bytes = 8ll << 30;
   if (!c.batch_wait_us) c.batch_wait_us = 50;
   int ndev = 0;
-  if (hipGetDeviceCount(&ndev) != hipSuccess || c.device < 0 || c.device >= ndev) {
-    kc::set_error("no such HIP device");
+  (void)hipGetLastError();  // an earlier, unrelated failure must not be reported as ours
+  const hipError_t de = hipGetDeviceCount(&ndev);
+  if (de != hipSuccess || c.device < 0 || c.device >= ndev) {
+    char msg[160];
+    snprintf(msg, sizeof msg, "no such HIP device (%d of %d: %s)", c.device, ndev, hipGetErrorString(de));
+    kc::set_error(msg);
     return nullptr;
   }
   if (hipSetDevice(c.device) != hipSuccess) {
@@ -351,10 +371,17 @@ int kcore_submit(kcore_server* s, const int64_t* offsets_host, const int32_t* ad
   r->n = n;
   r->m = m;
   r->bytes = bytes;
-  r->off.assign(offsets_host, offsets_host + n + 1);
-  if (m) {
-    r->adj.resize((size_t)m);
-    par_copy(r->adj.data(), adj_host, sizeof(int32_t) * (size_t)m);
+  if (s->cfg.borrow_inputs) {
+    r->offp = offsets_host;
+    r->adjp = adj_host;
+  } else {
+    r->off.assign(offsets_host, offsets_host + n + 1);
+    if (m) {
+      r->adj.resize((size_t)m);
+      par_copy(r->adj.data(), adj_host, sizeof(int32_t) * (size_t)m);
+    }
+    r->offp = r->off.data();
+    r->adjp = r->adj.data();
   }
   {
     std::lock_guard<std::mutex> lk(s->mu);

@@ -62,7 +62,7 @@ def test_argument_errors_without_device_work():
     o.tile_edges = 100
     assert lib.kcore_decompose_ex(one.ctypes.data, None, 0, None, None, ctypes.byref(o), None) == -1
     o = K.Options()
-    o.reserved[2] = 1
+    o.reserved[1] = 1
     assert lib.kcore_decompose_ex(one.ctypes.data, None, 0, None, None, ctypes.byref(o), None) == -1
     # batched: negative sizes, empty batch
     assert lib.kcore_decompose_batched(None, None, None, -1, 0, None, None) == -1
@@ -86,3 +86,17 @@ def test_missing_library_fails_loudly(tmp_path, monkeypatch):
     mod = importlib.util.module_from_spec(spec)
     with pytest.raises(ImportError, match="no fallback"):
         spec.loader.exec_module(mod)
+
+
+def test_one_hip_runtime_in_process():
+    """Importing the binding before PyTorch must still leave a single HIP runtime mapped: PyTorch's
+    copy and the system's share a soname, and two runtimes in one process see no device."""
+    import subprocess
+    import sys
+    code = ("import paper_2502_08042_amd, torch\n"
+            "paths = {l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}\n"
+            "print(len(paths))\n")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True,
+                         timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip().splitlines()[-1] == "1"
