@@ -78,7 +78,11 @@ typedef struct {
   int32_t async_scan;    /* chained mode: while the active set has at most this many vertices the
                             round's scan and its whole peel run as one asynchronous phase (one
                             barrier per round); 0 = default, -1 = never */
-  int32_t reserved[2];   /* must be zero */
+  int32_t block_tiles;   /* chained mode: a hub of at most this many tiles, pushed during a phase,
+                            is peeled in the same phase by the 16 wavefronts of the workgroup that
+                            pushed it (workgroup-local tile queue) instead of in the next phase by
+                            the whole grid; 0 = default, -1 = never */
+  int32_t reserved[1];   /* must be zero */
 } kcore_options;
 
 /* Counters of one decomposition (filled when a kcore_stats* is passed; that call synchronises

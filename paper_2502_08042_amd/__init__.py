@@ -47,7 +47,8 @@ class Options(ctypes.Structure):
                 ("blocks_per_cu", ctypes.c_int32), ("hub_degree", ctypes.c_int32),
                 ("num_entries", ctypes.c_int64), ("local_budget", ctypes.c_int32),
                 ("tile_edges", ctypes.c_int32), ("async_frontier", ctypes.c_int32),
-                ("async_scan", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+                ("async_scan", ctypes.c_int32), ("block_tiles", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 1)]
 
 
 class Stats(ctypes.Structure):
@@ -141,7 +142,7 @@ def _stream_ptr(stream) -> int:
 
 
 def _options(mode, validate, num_entries, hub_degree=0, local_budget=0, tile_edges=0,
-             blocks_per_cu=0, async_frontier=0, async_scan=0) -> Options:
+             blocks_per_cu=0, async_frontier=0, async_scan=0, block_tiles=0) -> Options:
     o = Options()
     o.mode = MODES[mode] if isinstance(mode, str) else int(mode)
     o.validate = 1 if validate else 0
@@ -152,6 +153,7 @@ def _options(mode, validate, num_entries, hub_degree=0, local_budget=0, tile_edg
     o.tile_edges = tile_edges
     o.async_frontier = async_frontier
     o.async_scan = async_scan
+    o.block_tiles = block_tiles
     return o
 
 

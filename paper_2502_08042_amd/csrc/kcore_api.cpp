@@ -210,9 +210,10 @@ int check_opts(const kcore_options* o) {
   if (o->blocks_per_cu < 0 || o->hub_degree < 0 || o->num_entries < 0 || o->local_budget < 0 ||
       o->tile_edges < 0 || (o->tile_edges % 64) != 0)
     return fail(KCORE_EINVAL, "negative option, or tile_edges not a multiple of 64");
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < 1; ++i)
     if (o->reserved[i]) return fail(KCORE_EINVAL, "reserved option fields must be zero");
-  if (o->async_frontier < -1 || o->async_scan < -1) return fail(KCORE_EINVAL, "async thresholds must be >= -1");
+  if (o->async_frontier < -1 || o->async_scan < -1 || o->block_tiles < -1)
+    return fail(KCORE_EINVAL, "async and block-tile thresholds must be >= -1");
   return KCORE_OK;
 }
 
@@ -336,6 +337,8 @@ int kcore_decompose_ex(const int64_t* offsets, const int32_t* adj, int64_t n, in
   // by one from the shared queue: frontiers with more than a few tiles stay synchronous
   a.async_tiles = af < 0 ? -1 : 64;
   a.async_scan_max = as < 0 ? -1 : (as ? as : 0);
+  const int32_t bt = opt ? opt->block_tiles : 0;
+  a.bq_max_tiles = bt < 0 ? 0 : (bt ? bt : 32);
 
   HIP_TRY(kc::launch_init_ctl(w->ctl, stream));
   if (a.chained) HIP_TRY(kc::launch_fill_u32(w->aq, 0xffffffffu, 2 * (size_t)w->q_cap, stream));
@@ -360,7 +363,8 @@ int kcore_decompose_ex(const int64_t* offsets, const int32_t* adj, int64_t n, in
 }
 
 // Debugging aid, not part of kcore.h: copies the phase timeline of the last single-graph call on
-// `stream` (rows of start, work done, flushed, barrier passed; 100 MHz ticks). Synchronises.
+// `stream` (rows of eight: start, work done, flushed, barrier passed in 100 MHz ticks, then the
+// phase kind word, frontier vertices, hub tiles and active-set size). Synchronises.
 int kcore_debug_trace(hipStream_t stream, unsigned long long* out, int max_phases) {
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
@@ -373,7 +377,7 @@ int kcore_debug_trace(hipStream_t stream, unsigned long long* out, int max_phase
   }
   const int np = max_phases < kc::kTracePhases ? max_phases : kc::kTracePhases;
   HIP_TRY(hipStreamSynchronize(stream));
-  HIP_TRY(hipMemcpy(out, w->ctl->trace, sizeof(unsigned long long) * 4 * np, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(out, w->ctl->trace, sizeof(unsigned long long) * 8 * np, hipMemcpyDeviceToHost));
   return KCORE_OK;
 }
 

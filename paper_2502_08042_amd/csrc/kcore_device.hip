@@ -189,6 +189,9 @@ struct WaveCtx {
   bool combine;        // phase-uniform: collect decrements of hot targets in LDS
   bool async;          // phase-uniform: pushes go to the async work queue
   bool arbitrate;      // phase-uniform: crossings may race with a scan (chained scan phases)
+  bool bq_open;        // phase-uniform: small hubs go to the workgroup's tile queue
+  unsigned long long* bq;  // LDS, kBlockQ entries: (tile << 32) | vertex, kQEmpty or kQSkip
+  int* bqc;            // LDS: claimed, reserved, busy waves
 };
 
 __device__ __forceinline__ unsigned comb_hash(int32_t u) {
@@ -227,6 +230,37 @@ struct PhaseOut {
 // Async work queue entry: low word vertex, high word tile index, or kWholeRow for a whole row.
 constexpr uint32_t kWholeRow = 0xffffffffu;
 constexpr long long kQEmpty = -1ll;
+constexpr long long kQSkip = -2ll;  // a reserved workgroup-queue slot that holds no work
+
+template <class T>
+__device__ __forceinline__ T lds_ld(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+template <class T>
+__device__ __forceinline__ void lds_st(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Chained mode: appends the tiles of the lanes with cnt > 0 to the workgroup's tile queue. Either
+// the whole wave's request fits, or none of it does (its reserved slots are then marked empty of
+// work and the caller sends the tiles to the global list). All lanes call; true for lanes whose
+// tiles were queued.
+__device__ __forceinline__ bool block_push(WaveCtx& c, int32_t v, long long cnt) {
+  const long long incl = wave_incl_scan(cnt);
+  const long long tot = __shfl(incl, 63, 64);
+  if (tot == 0) return false;
+  int base = 0;
+  if (lane_id() == 0) base = atomicAdd(&c.bqc[1], (int)tot);
+  base = __shfl(base, 0, 64);
+  const bool fits = (long long)base + tot <= kBlockQ;
+  const long long s0 = (long long)base + incl - cnt;
+  for (long long j = 0; j < cnt; ++j) {
+    const long long sl = s0 + j;
+    if (sl < kBlockQ)
+      lds_st(&c.bq[sl], fits ? (((unsigned long long)j << 32) | (unsigned)v) : (unsigned long long)kQSkip);
+  }
+  return fits && cnt > 0;
+}
 
 // Appends work for the lanes with cnt > 0 to the phase's async queue: a whole row (cnt == 1 and
 // !tiles) or cnt tiles of a hub row. The tail counter doubles as the count of created entries: it
@@ -281,6 +315,10 @@ __device__ __forceinline__ void push_vertices(const PeelArgs& a, WaveCtx& c, con
       queue_push(a, o, v, nt, true);
       return;
     }
+    bool pg = ph;
+    if (c.bq_open && block_push(c, v, (ph && nt <= a.bq_max_tiles) ? nt : 0)) pg = false;
+    if (!pg) nt = 0;
+    if (__ballot(pg) == 0) return;
     const long long incl = wave_incl_scan(nt);
     const long long tot = __shfl(incl, 63, 64);
     unsigned long long base = 0;
@@ -288,7 +326,7 @@ __device__ __forceinline__ void push_vertices(const PeelArgs& a, WaveCtx& c, con
     base = __shfl(base, 0, 64);
     if ((long long)base + tot > a.tcap) {
       if (lane_id() == 0) aor(&a.ctl->status, (unsigned)KC_ERR_OVERFLOW);
-    } else if (ph) {
+    } else if (pg) {
       const long long s0 = (long long)base + incl - nt;
       for (long long j = 0; j < nt; ++j) {
         int32_t* e = reinterpret_cast<int32_t*>(&o.tl[s0 + j]);
@@ -474,6 +512,73 @@ __device__ __forceinline__ void drain_local(const PeelArgs& a, WaveCtx& c, const
   }
 }
 
+// Chained mode, after a wave's static share: the workgroup's 16 waves peel the small hubs pushed
+// into its tile queue in this phase, and whatever those tiles push in turn, so a chain through hubs
+// continues inside the phase instead of waiting for the next one. A wave leaves once it sees no
+// busy wave (busy first) and then no unclaimed slot: entries are only reserved by busy waves, and a
+// wave that reserved entries stays until it sees them claimed, so no entry is left behind. Waits
+// are bounded.
+__device__ __forceinline__ void block_loop(const PeelArgs& a, WaveCtx& c, const PhaseOut& o, uint32_t k) {
+  int* head = &c.bqc[0];
+  int* tail = &c.bqc[1];
+  int* busy = &c.bqc[2];
+  for (;;) {
+    int state = 0;  // 1 got an entry, 2 done, 3 error
+    long long e = kQEmpty;
+    if (lane_id() == 0) {
+      bool counted = true;  // every wave starts the phase counted as busy
+      const unsigned long long t0 = wall_clock64();
+      for (int spin = 0;; ++spin) {
+        const int h = lds_ld(head);
+        const int t = min(lds_ld(tail), kBlockQ);
+        if (h < t) {
+          if (!counted) {
+            atomicAdd(busy, 1);
+            counted = true;
+          }
+          if (atomicCAS(head, h, h + 1) == h) {
+            // the producer reserved the slot before writing it: wait for the entry
+            for (int s2 = 0;; ++s2) {
+              e = (long long)lds_ld(&c.bq[h]);
+              if (e != kQEmpty) break;
+              if ((s2 & 255) == 255 && wall_clock64() - t0 > 400000000ull) break;
+            }
+            state = e == kQEmpty ? 3 : 1;
+            break;
+          }
+          continue;
+        }
+        if (counted) {
+          atomicSub(busy, 1);
+          counted = false;
+          continue;
+        }
+        if (lds_ld(busy) == 0) {
+          if (lds_ld(head) >= min(lds_ld(tail), kBlockQ)) {
+            state = 2;
+            break;
+          }
+          continue;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        if ((spin & 255) == 255 && wall_clock64() - t0 > 400000000ull) {
+          state = 3;
+          break;
+        }
+      }
+      if (state == 3) aor(&a.ctl->status, (unsigned)KC_ERR_TIMEOUT);
+    }
+    state = __shfl(state, 0, 64);
+    if (state != 1) return;
+    e = __shfl(e, 0, 64);
+    if (e == kQSkip) continue;
+    const int32_t v = (int32_t)(e & 0xffffffffll);
+    const int32_t j = (int32_t)((unsigned long long)e >> 32);
+    expand_tile(a, c, o, v, j, k);
+    drain_local(a, c, o, k);
+  }
+}
+
 // Async phase, dynamic part: each wave claims one queue slot at a time, waits until the slot is
 // filled or the phase is quiescent, and peels what it holds (a whole row or a hub tile), together
 // with the local chain it starts. Quiescent = every workgroup finished its static share and every
@@ -563,6 +668,8 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
   __shared__ int s_quiet;
   __shared__ int32_t s_ckey[kCombSlots];
   __shared__ uint32_t s_ccnt[kCombSlots];
+  __shared__ unsigned long long s_bq[kBlockQ];
+  __shared__ int s_bqc[4];
 
   const int w = threadIdx.x >> 6;
   const int l = lane_id();
@@ -590,6 +697,11 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
     s_ckey[i] = -1;
     s_ccnt[i] = 0;
   }
+  c.bq = s_bq;
+  c.bqc = s_bqc;
+  c.bq_open = false;
+  for (int i = threadIdx.x; i < kBlockQ; i += kPeelThreads) s_bq[i] = (unsigned long long)kQEmpty;
+  if (threadIdx.x < 4) s_bqc[threadIdx.x] = threadIdx.x == 2 ? kWaves : 0;
 
   unsigned epoch = 0;
   long long st_rounds = 0, st_sub = 0, st_bar = 0;
@@ -672,6 +784,14 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
     c.async = kind == PH_ASYNC || async_scan;
     c.combine = c.precheck && !c.async;
     c.arbitrate = kind == PH_SCAN && a.chained;
+    c.bq_open = a.chained && a.bq_max_tiles > 0 && !c.async;
+    if (tr) {
+      C->trace[p][4] = (unsigned long long)kind | (c.precheck ? 4ull : 0ull) | (c.async ? 8ull : 0ull) |
+                       ((unsigned long long)k << 8);
+      C->trace[p][5] = (unsigned long long)fs;
+      C->trace[p][6] = (unsigned long long)ft;
+      C->trace[p][7] = (unsigned long long)asize;
+    }
     long long peeled_before = c.peeled;
     if (kind == PH_SCAN) {
       // Alg. 1: F = {v in A : induced degree <= k}; survivors refine A.
@@ -731,6 +851,10 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
       }
     }
     if (a.chained) drain_local(a, c, o, k);
+    if (c.bq_open) {
+      block_loop(a, c, o, k);
+      c.bq_open = false;
+    }
     if (c.async) {
       if (threadIdx.x == 0) s_quiet = 0;
       __syncthreads();
@@ -743,6 +867,10 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
       if ((threadIdx.x >> 6) < kAsyncWaves) async_loop(a, c, o, k, &s_quiet);
     }
     comb_flush(a, c, o, k);
+    // every wave has left the tile queue (comb_flush starts with a workgroup barrier): reset it for
+    // the next phase; the barriers of the flushes below order this before its next use
+    for (int i = threadIdx.x; i < kBlockQ; i += kPeelThreads) s_bq[i] = (unsigned long long)kQEmpty;
+    if (threadIdx.x < 4) s_bqc[threadIdx.x] = threadIdx.x == 2 ? kWaves : 0;
     if (a.chained) drain_local(a, c, o, k);
     if (tr) C->trace[p][1] = wall_clock64();
 
@@ -1140,7 +1268,7 @@ __global__ void fill_u32_kernel(uint32_t* p, uint32_t v, size_t count) {
 
 __global__ void init_ctl_kernel(PeelCtl* c) {
   uint32_t* w = reinterpret_cast<uint32_t*>(c);
-  for (size_t i = threadIdx.x; i < sizeof(PeelCtl) / 4; i += blockDim.x) w[i] = 0u;
+  for (size_t i = threadIdx.x; i < offsetof(PeelCtl, trace) / 4; i += blockDim.x) w[i] = 0u;
   __syncthreads();
   if (threadIdx.x < 3) c->slot[threadIdx.x].minv = 0xffffffffu;
 }

@@ -13,10 +13,11 @@ constexpr int kCombBits = 12;
 constexpr int kCombSlots = 1 << kCombBits;  // per-workgroup LDS combining table for hub targets
 constexpr int kCombProbe = 4;               // linear-probe window of that table
 constexpr int kEdgeUnroll = 2;              // adjacency entries in flight per lane
+constexpr int kBlockQ = 1024;              // workgroup-local hub tile queue (chained mode)
 constexpr int kAsyncWaves = 2;              // waves per workgroup claiming async work
 constexpr int kBarGroups = 32;       // arrival groups of the grid barrier
 constexpr int kBatchThreads = 512;   // threads per workgroup of the batched peel
-constexpr int kTracePhases = 1024;   // phases whose timeline workgroup 0 records
+constexpr int kTracePhases = 16384;   // phases whose timeline workgroup 0 records
 
 enum StatIdx {
   ST_ROUNDS = 0, ST_SUBROUNDS, ST_BARRIERS, ST_PEELED, ST_EDGES, ST_DECR, ST_COMBINED, ST_SCANNED,
@@ -48,8 +49,10 @@ struct alignas(128) PeelCtl {
   unsigned int status;        // error bits (KC_ERR_*)
   unsigned int pad2[31];
   unsigned long long stats[16];
-  // phase timeline of workgroup 0 (100 MHz wall clock): start, work done, flushed, barrier passed
-  unsigned long long trace[kTracePhases][4];
+  // phase timeline of workgroup 0, not cleared between launches: 100 MHz wall clock at start,
+  // work done, flushed and barrier passed; then kind | precheck << 2 | async << 3 | k << 8, the
+  // frontier's vertices, its hub tiles and the active-set size
+  unsigned long long trace[kTracePhases][8];
 };
 
 enum : unsigned { KC_ERR_TIMEOUT = 1u, KC_ERR_OVERFLOW = 2u, KC_ERR_PHASES = 4u, KC_ERR_BADGRAPH = 8u };
@@ -78,6 +81,7 @@ struct PeelArgs {
   int64_t async_small; // chained mode: frontiers up to this many small vertices ...
   int64_t async_tiles; //   ... and tiles are peeled by an async phase
   int64_t async_scan_max; // chained mode: active sets up to this size scan and peel in one phase
+  int32_t bq_max_tiles;   // chained mode: hubs of at most this many tiles stay in the workgroup (0 = off)
 };
 
 struct BatchCtl {

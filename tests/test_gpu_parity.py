@@ -99,6 +99,22 @@ def test_tuning_knobs_do_not_change_results(mode):
         assert not first_mismatch(got, want), first_mismatch(got, want)
 
 
+def test_chained_work_queues_do_not_change_results():
+    """Chained mode's in-phase work sharing: the workgroup tile queue (off, one tile, a few tiles,
+    more tiles than the queue holds, which spills to the global list) and the asynchronous phases
+    (never, default, scan folded in) must all give the oracle's coreness, every vertex peeled once."""
+    cases = [("rmat13", gg.rmat(13, 16, 7)), ("road256", gg.grid_road(256, 0.05, 0.01, 3))]
+    for name, g in cases:
+        want = oracle.bz(g.offsets, g.adj)
+        for bt, af, asc in ((-1, -1, -1), (1, -1, -1), (4, 0, 0), (2000, -1, -1), (0, 0, 1 << 30),
+                            (0, 0, 0)):
+            say(f"[gpu] queues {name} block_tiles={bt} async_frontier={af} async_scan={asc}")
+            got, st = run_single(g.offsets, g.adj, mode="chained", hub_degree=16, tile_edges=64,
+                                 block_tiles=bt, async_frontier=af, async_scan=asc)
+            assert not first_mismatch(got, want), first_mismatch(got, want)
+            assert st["peeled"] == g.n and st["edges"] == g.m and st["device_status"] == 0
+
+
 def test_batched_small():
     b = gg.batch(64, 4, hi=20000)
     say(f"[gpu] batched 64 graphs V={b.n} m={b.m}")
