@@ -82,7 +82,10 @@ typedef struct {
                             is peeled in the same phase by the 16 wavefronts of the workgroup that
                             pushed it (workgroup-local tile queue) instead of in the next phase by
                             the whole grid; 0 = default, -1 = never */
-  int32_t reserved[1];   /* must be zero */
+  int32_t block_queue;   /* chained mode: tiles one workgroup may take into its own queue per phase
+                            (at most 1024); the rest go to the next phase's global list, so one
+                            workgroup's chain cannot hold up the grid; 0 = default */
+  int32_t reserved[3];   /* must be zero */
 } kcore_options;
 
 /* Counters of one decomposition (filled when a kcore_stats* is passed; that call synchronises
@@ -135,8 +138,8 @@ int kcore_release_workspaces(void);
 /* ------------------------------------------------------------------------------------------------
  * Serving: continuous batching of independent graph requests on one device.
  *
- * kcore_submit copies a HOST graph into pinned staging before it returns (the caller may free its
- * buffers immediately) and hands back a ticket. A dispatcher thread admits queued requests while
+ * kcore_submit copies a HOST graph before it returns (the caller may free its buffers at once)
+ * unless borrow_inputs is set, and hands back a ticket. A dispatcher thread admits queued requests while
  * their device footprint fits the HBM budget and a batch slot is free, packs them into a segmented
  * CSR and launches the batched peel; up to max_inflight batches run concurrently on separate
  * streams, so requests that arrive while others are on the GPU start as soon as a slot and memory
@@ -158,13 +161,19 @@ typedef struct {
                                   adj unchanged and alive until kcore_poll/kcore_wait returns the
                                   result (host-to-device copies then read them directly, at DMA
                                   speed when the caller's memory is pinned) */
-  int32_t reserved[3];
+  int32_t reserved1;
+  int64_t reserve_vertices;    /* nonzero: every slot allocates, at creation, device and pinned
+                                  buffers for batches of this many vertices and reserve_entries
+                                  adjacency entries, and a peel workspace for max_batch_vertices,
+                                  so that serving rarely stops to allocate or pin memory (buffers
+                                  a slot outgrows are kept until kcore_server_destroy) */
+  int64_t reserve_entries;
 } kcore_server_config;
 
 typedef struct {
   double submit_us;   /* submit time, microseconds on the server's steady clock */
   double admit_us;    /* admitted into a batch */
-  double launch_us;   /* batch launched */
+  double launch_us;   /* batch packed and enqueued on its stream */
   double done_us;     /* result visible to kcore_poll */
   int64_t batch_id;   /* batch the request ran in */
   int32_t batch_graphs;

@@ -48,7 +48,7 @@ class Options(ctypes.Structure):
                 ("num_entries", ctypes.c_int64), ("local_budget", ctypes.c_int32),
                 ("tile_edges", ctypes.c_int32), ("async_frontier", ctypes.c_int32),
                 ("async_scan", ctypes.c_int32), ("block_tiles", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 1)]
+                ("block_queue", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class Stats(ctypes.Structure):
@@ -68,7 +68,8 @@ class ServerConfig(ctypes.Structure):
                 ("max_batch_graphs", ctypes.c_int32), ("reserved0", ctypes.c_int32),
                 ("max_batch_vertices", ctypes.c_int64), ("hbm_budget_bytes", ctypes.c_int64),
                 ("max_request_vertices", ctypes.c_int64), ("batch_wait_us", ctypes.c_double),
-                ("borrow_inputs", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("borrow_inputs", ctypes.c_int32), ("reserved1", ctypes.c_int32),
+                ("reserve_vertices", ctypes.c_int64), ("reserve_entries", ctypes.c_int64)]
 
 
 class RequestStats(ctypes.Structure):
@@ -142,7 +143,8 @@ def _stream_ptr(stream) -> int:
 
 
 def _options(mode, validate, num_entries, hub_degree=0, local_budget=0, tile_edges=0,
-             blocks_per_cu=0, async_frontier=0, async_scan=0, block_tiles=0) -> Options:
+             blocks_per_cu=0, async_frontier=0, async_scan=0, block_tiles=0,
+             block_queue=0) -> Options:
     o = Options()
     o.mode = MODES[mode] if isinstance(mode, str) else int(mode)
     o.validate = 1 if validate else 0
@@ -154,6 +156,7 @@ def _options(mode, validate, num_entries, hub_degree=0, local_budget=0, tile_edg
     o.async_frontier = async_frontier
     o.async_scan = async_scan
     o.block_tiles = block_tiles
+    o.block_queue = block_queue
     return o
 
 
@@ -221,7 +224,7 @@ class Server:
     def __init__(self, device: int = 0, max_inflight: int = 0, max_batch_graphs: int = 0,
                  max_batch_vertices: int = 0, hbm_budget_bytes: int = 0,
                  max_request_vertices: int = 0, batch_wait_us: float = 0.0,
-                 borrow_inputs: bool = False):
+                 borrow_inputs: bool = False, reserve_vertices: int = 0, reserve_entries: int = 0):
         cfg = ServerConfig()
         cfg.device = device
         cfg.max_inflight = max_inflight
@@ -231,6 +234,8 @@ class Server:
         cfg.max_request_vertices = max_request_vertices
         cfg.batch_wait_us = batch_wait_us
         cfg.borrow_inputs = 1 if borrow_inputs else 0
+        cfg.reserve_vertices = reserve_vertices
+        cfg.reserve_entries = reserve_entries
         self._h = _lib.kcore_server_create(ctypes.byref(cfg))
         if not self._h:
             raise KcoreError(-1, "kcore_server_create", last_error())

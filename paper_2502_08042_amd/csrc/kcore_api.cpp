@@ -174,8 +174,9 @@ int batch_ws(int dev, hipStream_t s, int64_t V, int32_t G, BatchWs*& out) {
       HIP_TRY(hipFree(w->block));
       w->block = nullptr;
     }
-    const int64_t vc = V > w->v_cap ? V + V / 8 : w->v_cap;
-    const int64_t gc = G > w->g_cap ? (int64_t)G + G / 8 + 16 : w->g_cap;
+    // headroom: regrowing waits for the stream and frees device memory (a device-wide wait)
+    const int64_t vc = V > w->v_cap ? std::max<int64_t>(V, w->v_cap * 3 / 2) : w->v_cap;
+    const int64_t gc = G > w->g_cap ? std::max<int64_t>((int64_t)G + 16, (int64_t)w->g_cap * 3 / 2) : w->g_cap;
     size_t off = 0;
     const size_t o_d = off; off = align_up(off + 4 * (size_t)vc);
     const size_t o_q = off; off = align_up(off + 4 * (size_t)vc);
@@ -210,8 +211,10 @@ int check_opts(const kcore_options* o) {
   if (o->blocks_per_cu < 0 || o->hub_degree < 0 || o->num_entries < 0 || o->local_budget < 0 ||
       o->tile_edges < 0 || (o->tile_edges % 64) != 0)
     return fail(KCORE_EINVAL, "negative option, or tile_edges not a multiple of 64");
-  for (int i = 0; i < 1; ++i)
+  for (int i = 0; i < 3; ++i)
     if (o->reserved[i]) return fail(KCORE_EINVAL, "reserved option fields must be zero");
+  if (o->block_queue < 0 || o->block_queue > kc::kBlockQ)
+    return fail(KCORE_EINVAL, "block_queue must be in [0, %d]", kc::kBlockQ);
   if (o->async_frontier < -1 || o->async_scan < -1 || o->block_tiles < -1)
     return fail(KCORE_EINVAL, "async and block-tile thresholds must be >= -1");
   return KCORE_OK;
@@ -339,6 +342,7 @@ int kcore_decompose_ex(const int64_t* offsets, const int32_t* adj, int64_t n, in
   a.async_scan_max = as < 0 ? -1 : (as ? as : 0);
   const int32_t bt = opt ? opt->block_tiles : 0;
   a.bq_max_tiles = bt < 0 ? 0 : (bt ? bt : 32);
+  a.bq_cap = (opt && opt->block_queue) ? opt->block_queue : kc::kBlockQ;
 
   HIP_TRY(kc::launch_init_ctl(w->ctl, stream));
   if (a.chained) HIP_TRY(kc::launch_fill_u32(w->aq, 0xffffffffu, 2 * (size_t)w->q_cap, stream));
@@ -399,6 +403,30 @@ int kcore_decompose_batched_ex(const int64_t* graph_vptr, const int64_t* offsets
 }
 
 }  // extern "C"
+
+int kc::reserve_batched(hipStream_t stream, int64_t V, int32_t G) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  BatchWs* w = nullptr;
+  return batch_ws(dev, stream, V, G, w);
+}
+
+void kc::release_batched(hipStream_t stream) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return;
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_batch.find(Key(dev, stream));
+  if (it == g_batch.end()) return;
+  BatchWs* w = it->second;
+  g_batch.erase(it);
+  if (!w) return;
+  hipStreamSynchronize(stream);
+  if (w->block) hipFree(w->block);
+  if (w->host_stats) hipHostFree(w->host_stats);
+  if (w->ev0) hipEventDestroy(w->ev0);
+  if (w->ev1) hipEventDestroy(w->ev1);
+  delete w;
+}
 
 int kc::decompose_batched_local(const int64_t* graph_vptr, const int64_t* offsets, const int32_t* adj,
                                 int32_t num_graphs, int64_t total_vertices, int32_t* coreness_out,

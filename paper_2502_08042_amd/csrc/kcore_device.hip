@@ -245,18 +245,18 @@ __device__ __forceinline__ void lds_st(T* p, T v) {
 // the whole wave's request fits, or none of it does (its reserved slots are then marked empty of
 // work and the caller sends the tiles to the global list). All lanes call; true for lanes whose
 // tiles were queued.
-__device__ __forceinline__ bool block_push(WaveCtx& c, int32_t v, long long cnt) {
+__device__ __forceinline__ bool block_push(WaveCtx& c, int32_t v, long long cnt, int cap) {
   const long long incl = wave_incl_scan(cnt);
   const long long tot = __shfl(incl, 63, 64);
   if (tot == 0) return false;
   int base = 0;
   if (lane_id() == 0) base = atomicAdd(&c.bqc[1], (int)tot);
   base = __shfl(base, 0, 64);
-  const bool fits = (long long)base + tot <= kBlockQ;
+  const bool fits = (long long)base + tot <= cap;
   const long long s0 = (long long)base + incl - cnt;
   for (long long j = 0; j < cnt; ++j) {
     const long long sl = s0 + j;
-    if (sl < kBlockQ)
+    if (sl < cap)
       lds_st(&c.bq[sl], fits ? (((unsigned long long)j << 32) | (unsigned)v) : (unsigned long long)kQSkip);
   }
   return fits && cnt > 0;
@@ -316,7 +316,7 @@ __device__ __forceinline__ void push_vertices(const PeelArgs& a, WaveCtx& c, con
       return;
     }
     bool pg = ph;
-    if (c.bq_open && block_push(c, v, (ph && nt <= a.bq_max_tiles) ? nt : 0)) pg = false;
+    if (c.bq_open && block_push(c, v, (ph && nt <= a.bq_max_tiles) ? nt : 0, a.bq_cap)) pg = false;
     if (!pg) nt = 0;
     if (__ballot(pg) == 0) return;
     const long long incl = wave_incl_scan(nt);
@@ -530,7 +530,7 @@ __device__ __forceinline__ void block_loop(const PeelArgs& a, WaveCtx& c, const 
       const unsigned long long t0 = wall_clock64();
       for (int spin = 0;; ++spin) {
         const int h = lds_ld(head);
-        const int t = min(lds_ld(tail), kBlockQ);
+        const int t = min(lds_ld(tail), a.bq_cap);
         if (h < t) {
           if (!counted) {
             atomicAdd(busy, 1);
@@ -554,7 +554,7 @@ __device__ __forceinline__ void block_loop(const PeelArgs& a, WaveCtx& c, const 
           continue;
         }
         if (lds_ld(busy) == 0) {
-          if (lds_ld(head) >= min(lds_ld(tail), kBlockQ)) {
+          if (lds_ld(head) >= min(lds_ld(tail), a.bq_cap)) {
             state = 2;
             break;
           }
@@ -673,7 +673,9 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
 
   const int w = threadIdx.x >> 6;
   const int l = lane_id();
-  const long long gw = (long long)blockIdx.x * kWaves + w;
+  // wave order interleaves workgroups, so a short list (a small active set or frontier) is spread
+  // over every workgroup, and with it the hub tiles their workgroup queues take
+  const long long gw = (long long)w * gridDim.x + blockIdx.x;
   const long long W = (long long)gridDim.x * kWaves;
   const long long gt = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long GT = (long long)gridDim.x * blockDim.x;

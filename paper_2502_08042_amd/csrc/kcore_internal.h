@@ -82,6 +82,7 @@ struct PeelArgs {
   int64_t async_tiles; //   ... and tiles are peeled by an async phase
   int64_t async_scan_max; // chained mode: active sets up to this size scan and peel in one phase
   int32_t bq_max_tiles;   // chained mode: hubs of at most this many tiles stay in the workgroup (0 = off)
+  int32_t bq_cap;         //   and the workgroup takes at most this many tiles per phase (<= kBlockQ)
 };
 
 struct BatchCtl {
@@ -111,6 +112,10 @@ void set_error(const char* msg);
 
 // kcore_decompose_batched with per-graph local ids in adj (used by the serving runtime, which
 // then packs requests without rewriting their adjacency). Defined in kcore_api.cpp.
+// Grows the batched-peel workspace of (current device, stream) to V vertices and G graphs now.
+int reserve_batched(hipStream_t stream, int64_t V, int32_t G);
+// Frees the batched-peel workspace of (current device, stream), if any (before the stream goes).
+void release_batched(hipStream_t stream);
 int decompose_batched_local(const int64_t* graph_vptr, const int64_t* offsets, const int32_t* adj,
                             int32_t num_graphs, int64_t total_vertices, int32_t* coreness_out,
                             hipStream_t stream);

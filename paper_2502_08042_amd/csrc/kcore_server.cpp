@@ -15,6 +15,7 @@
 #include <chrono>
 #include <condition_variable>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <mutex>
@@ -48,7 +49,9 @@ struct Slot {
   hipStream_t stream = nullptr;
   bool busy = false;
   std::atomic<int> finished{0};
-  int64_t v_cap = 0, e_cap = 0, g_cap = 0;
+  int64_t v_cap = 0, e_cap = 0, g_cap = 0, c_cap = 0;      // device buffers (elements)
+  int64_t vh_cap = 0, eh_cap = 0, gh_cap = 0, ch_cap = 0;  // pinned staging buffers
+  std::vector<void*> retired_dev, retired_host;             // outgrown, freed at destroy
   int64_t *vptr_d = nullptr, *off_d = nullptr;
   int32_t *adj_d = nullptr, *core_d = nullptr;
   int64_t *vptr_h = nullptr, *off_h = nullptr;
@@ -104,6 +107,7 @@ struct kcore_server {
   uint64_t next_ticket = 1;
   int64_t next_batch = 1;
   bool stop = false;
+  bool log = false;  // KCORE_SERVER_LOG set: one line per batch on stderr
   std::thread th;
 
   double now_us() const {
@@ -125,33 +129,42 @@ void host_done(void* p) {
   s->cv.notify_all();
 }
 
-int grow(Slot* sl, int64_t V, int64_t E, int64_t G) {
-  if (V <= sl->v_cap && E <= sl->e_cap && G <= sl->g_cap) return 0;
-  const int64_t v = std::max(V, sl->v_cap) * 5 / 4 + 1024;
-  const int64_t e = std::max(E, sl->e_cap) * 5 / 4 + 4096;
-  const int64_t g = std::max(G, sl->g_cap) * 5 / 4 + 64;
-  hipFree(sl->vptr_d);
-  hipFree(sl->off_d);
-  hipFree(sl->adj_d);
-  hipFree(sl->core_d);
-  hipHostFree(sl->vptr_h);
-  hipHostFree(sl->off_h);
-  hipHostFree(sl->adj_h);
-  hipHostFree(sl->core_h);
-  sl->vptr_d = sl->off_d = sl->vptr_h = sl->off_h = nullptr;
-  sl->adj_d = sl->core_d = sl->adj_h = sl->core_h = nullptr;
-  sl->v_cap = sl->e_cap = sl->g_cap = 0;
-  if (hipMalloc(&sl->vptr_d, 8 * (g + 1)) != hipSuccess || hipMalloc(&sl->off_d, 8 * (v + 1)) != hipSuccess ||
-      hipMalloc(&sl->adj_d, 4 * e) != hipSuccess || hipMalloc(&sl->core_d, 4 * v) != hipSuccess ||
-      hipHostMalloc((void**)&sl->vptr_h, 8 * (g + 1), hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&sl->off_h, 8 * (v + 1), hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&sl->adj_h, 4 * e, hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&sl->core_h, 4 * v, hipHostMallocDefault) != hipSuccess)
-    return KCORE_ENOMEM;
-  sl->v_cap = v;
-  sl->e_cap = e;
-  sl->g_cap = g;
+// Grows a device buffer and, when wanted, its pinned staging twin to hold `need` elements, with
+// headroom so that later batches rarely grow them again (freeing device memory waits for the whole
+// device). The two grow independently: batches copied from borrowed memory need no staging.
+// Outgrown buffers are kept until the server is destroyed instead of being freed on the spot:
+// freeing waits for the whole device, and the dispatcher must not stall behind running batches.
+template <class T>
+int grow_buf(Slot* sl, T*& dev, T*& host, int64_t& dcap, int64_t& hcap, int64_t need, int64_t floor,
+             bool want_host) {
+  if (need > dcap) {
+    const int64_t c = std::max(std::max(need, floor), dcap * 3 / 2);
+    if (dev) sl->retired_dev.push_back(dev);
+    dev = nullptr;
+    dcap = 0;
+    if (hipMalloc(&dev, sizeof(T) * (size_t)c) != hipSuccess) return KCORE_ENOMEM;
+    dcap = c;
+  }
+  if (want_host && need > hcap) {
+    if (host) sl->retired_host.push_back(host);
+    host = nullptr;
+    const int64_t c = std::max(std::max(need, floor), hcap * 3 / 2);
+    hcap = 0;
+    if (hipHostMalloc((void**)&host, sizeof(T) * (size_t)c, hipHostMallocDefault) != hipSuccess)
+      return KCORE_ENOMEM;
+    hcap = c;
+  }
   return 0;
+}
+
+// Device and pinned staging buffers of a slot; a batch whose adjacency is copied straight from
+// borrowed caller memory needs no pinned adjacency buffer.
+int grow(Slot* sl, int64_t V, int64_t E, int64_t G, bool host_adj) {
+  int rc = grow_buf(sl, sl->vptr_d, sl->vptr_h, sl->g_cap, sl->gh_cap, G + 1, 4096, true);
+  if (!rc) rc = grow_buf(sl, sl->off_d, sl->off_h, sl->v_cap, sl->vh_cap, V + 1, 1 << 20, true);
+  if (!rc) rc = grow_buf(sl, sl->adj_d, sl->adj_h, sl->e_cap, sl->eh_cap, E, 16 << 20, host_adj);
+  if (!rc) rc = grow_buf(sl, sl->core_d, sl->core_h, sl->c_cap, sl->ch_cap, V, 1 << 20, true);
+  return rc;
 }
 
 // Packs the slot's requests into its pinned buffers and enqueues copy-in, peel, copy-out and the
@@ -163,31 +176,68 @@ int launch_slot(kcore_server* s, Slot* sl) {
     E += r->m;
   }
   const int64_t G = (int64_t)sl->reqs.size();
-  if (int rc = grow(sl, V, E, G)) return rc;
-  int64_t vb = 0, eb = 0;
-  sl->vptr_h[0] = 0;
   hipStream_t st = sl->stream;
   // Borrowed large requests are copied to the device straight from the caller's arrays (one DMA
   // each); everything else is packed into the slot's pinned buffer and copied in one piece.
   const bool direct = s->cfg.borrow_inputs && sl->large;
+  const double t_start = s->now_us();
+  if (int rc = grow(sl, V, E, G, !direct)) return rc;
+  const double t_grown = s->now_us();
+  std::vector<int64_t> vbs((size_t)G + 1, 0), ebs((size_t)G + 1, 0);
   for (int64_t g = 0; g < G; ++g) {
-    Request* r = sl->reqs[g];
-    for (int64_t i = 0; i < r->n; ++i) sl->off_h[vb + i] = eb + r->offp[i];
-    // adjacency keeps the request's own (local) ids: the peel is launched in local-id mode
-    if (r->m) {
-      if (direct) {
-        if (hipMemcpyAsync(sl->adj_d + eb, r->adjp, sizeof(int32_t) * (size_t)r->m, hipMemcpyHostToDevice,
-                           st) != hipSuccess)
-          return KCORE_EDEVICE;
-      } else {
-        par_copy(sl->adj_h + eb, r->adjp, sizeof(int32_t) * (size_t)r->m);
-      }
+    vbs[g + 1] = vbs[g] + sl->reqs[g]->n;
+    ebs[g + 1] = ebs[g] + sl->reqs[g]->m;
+  }
+  // Offsets are rebased onto the batch's entry range; adjacency keeps the request's own (local)
+  // ids, since the peel is launched in local-id mode. Packing is host memory bandwidth, so the
+  // batch is cut into pieces of about 4 MiB (parts of one big request, or runs of small ones) that
+  // a few threads take from a shared counter.
+  struct Piece {
+    int64_t g, v0, v1;  // request and vertex range (offsets); v0 == 0 also copies its adjacency
+    int64_t e0, e1;     // adjacency range (entries) copied by this piece
+  };
+  std::vector<Piece> pieces;
+  const int64_t kPiece = 1 << 20;  // elements (4-8 MiB)
+  for (int64_t g = 0; g < G; ++g) {
+    const Request* r = sl->reqs[g];
+    const int64_t nv = r->n, ne = direct ? 0 : r->m;
+    const int64_t np = std::max<int64_t>(1, std::max((nv + kPiece - 1) / kPiece, (ne + kPiece - 1) / kPiece));
+    for (int64_t q = 0; q < np; ++q)
+      pieces.push_back({g, nv * q / np, nv * (q + 1) / np, ne * q / np, ne * (q + 1) / np});
+  }
+  std::atomic<size_t> next{0};
+  auto work = [&] {
+    for (size_t i = next.fetch_add(1); i < pieces.size(); i = next.fetch_add(1)) {
+      const Piece& pc = pieces[i];
+      const Request* r = sl->reqs[pc.g];
+      const int64_t vb = vbs[pc.g], eb = ebs[pc.g];
+      for (int64_t v = pc.v0; v < pc.v1; ++v) sl->off_h[vb + v] = eb + r->offp[v];
+      if (pc.e1 > pc.e0)
+        memcpy(sl->adj_h + eb + pc.e0, r->adjp + pc.e0, sizeof(int32_t) * (size_t)(pc.e1 - pc.e0));
+      if (pc.v1 == r->n) sl->vptr_h[pc.g + 1] = vbs[pc.g + 1];
     }
-    vb += r->n;
-    eb += r->m;
-    sl->vptr_h[g + 1] = vb;
+  };
+  sl->vptr_h[0] = 0;
+  const int64_t total_bytes = 8 * V + (direct ? 0 : 4 * E);
+  unsigned nt = std::thread::hardware_concurrency();
+  nt = nt < 2 ? 2 : (nt > 8 ? 8 : nt);
+  if (total_bytes < (4 << 20)) nt = 1;
+  {
+    std::vector<std::thread> th;
+    for (unsigned t = 1; t < nt; ++t) th.emplace_back(work);
+    work();
+    for (auto& x : th) x.join();
+  }
+  if (direct) {
+    for (int64_t g = 0; g < G; ++g) {
+      const Request* r = sl->reqs[g];
+      if (r->m && hipMemcpyAsync(sl->adj_d + ebs[g], r->adjp, sizeof(int32_t) * (size_t)r->m,
+                                 hipMemcpyHostToDevice, st) != hipSuccess)
+        return KCORE_EDEVICE;
+    }
   }
   sl->off_h[V] = E;
+  const double t_packed = s->now_us();
   if (hipMemcpyAsync(sl->vptr_d, sl->vptr_h, 8 * (G + 1), hipMemcpyHostToDevice, st) != hipSuccess ||
       hipMemcpyAsync(sl->off_d, sl->off_h, 8 * (V + 1), hipMemcpyHostToDevice, st) != hipSuccess ||
       (!direct && E > 0 && hipMemcpyAsync(sl->adj_d, sl->adj_h, 4 * E, hipMemcpyHostToDevice, st) != hipSuccess))
@@ -201,6 +251,11 @@ int launch_slot(kcore_server* s, Slot* sl) {
     delete pr;
     return KCORE_EDEVICE;
   }
+  if (s->log)
+    fprintf(stderr, "[kcore server] batch %lld %s: %lld graphs, %lld vertices, %lld entries; grow %.2f ms, "
+            "pack %.2f ms, enqueue %.2f ms\n", (long long)sl->batch_id, sl->large ? "large" : "small",
+            (long long)G, (long long)V, (long long)E, (t_grown - t_start) / 1000, (t_packed - t_grown) / 1000,
+            (s->now_us() - t_packed) / 1000);
   return 0;
 }
 
@@ -248,6 +303,16 @@ void dispatcher(kcore_server* s) {
       else if (!free_slot) free_slot = sl;
     }
     if (s->stop && busy == 0) break;
+    if (!s->stop && free_slot && !s->queue.empty() && busy > 0 &&
+        (int64_t)s->queue.size() < s->cfg.max_batch_graphs) {
+      // the device is busy anyway: give the batch up to batch_wait_us (from its oldest request's
+      // arrival) to fill up
+      const double age = s->now_us() - s->queue.front()->st.submit_us;
+      if (age < s->cfg.batch_wait_us) {
+        s->cv.wait_for(lk, std::chrono::microseconds((int64_t)(s->cfg.batch_wait_us - age) + 1));
+        continue;
+      }
+    }
     if (!s->stop && free_slot && !s->queue.empty()) {
       // Admit in arrival order, one size class per batch: the class of the oldest request, then
       // every queued request of that class while the budget and batch limits allow. Large
@@ -288,8 +353,8 @@ void dispatcher(kcore_server* s) {
           r->st.batch_graphs = (int32_t)take.size();
         }
         lk.unlock();
-        const double tl = s->now_us();
         int rc = launch_slot(s, free_slot);
+        const double tl = s->now_us();
         lk.lock();
         for (Request* r : take) r->st.launch_us = tl;
         if (rc) {
@@ -315,7 +380,8 @@ kcore_server* kcore_server_create(const kcore_server_config* cfg) {
   kcore_server_config c{};
   if (cfg) c = *cfg;
   if (c.max_inflight < 0 || c.max_batch_graphs < 0 || c.max_batch_vertices < 0 || c.hbm_budget_bytes < 0 ||
-      c.max_request_vertices < 0 || c.batch_wait_us < 0) {
+      c.max_request_vertices < 0 || c.batch_wait_us < 0 || c.reserve_vertices < 0 || c.reserve_entries < 0 ||
+      c.reserved0 || c.reserved1) {
     kc::set_error("negative server configuration field");
     return nullptr;
   }
@@ -340,6 +406,7 @@ kcore_server* kcore_server_create(const kcore_server_config* cfg) {
   auto* s = new kcore_server;
   s->cfg = c;
   s->t0 = std::chrono::steady_clock::now();
+  s->log = getenv("KCORE_SERVER_LOG") != nullptr;
   for (int i = 0; i < c.max_inflight; ++i) {
     Slot* sl = new Slot;
     if (hipStreamCreateWithFlags(&sl->stream, hipStreamNonBlocking) != hipSuccess) {
@@ -353,6 +420,18 @@ kcore_server* kcore_server_create(const kcore_server_config* cfg) {
       return nullptr;
     }
     s->slots.push_back(sl);
+  }
+  if (c.reserve_vertices || c.reserve_entries) {
+    for (Slot* sl : s->slots) {
+      const int32_t g = c.max_batch_graphs;
+      // the batched workspace is sized for the largest batch admission allows
+      if (grow(sl, c.reserve_vertices, c.reserve_entries, g, true) ||
+          kc::reserve_batched(sl->stream, std::max(c.reserve_vertices, c.max_batch_vertices), g)) {
+        kcore_server_destroy(s);
+        kc::set_error("could not reserve the slot buffers asked for");
+        return nullptr;
+      }
+    }
   }
   s->th = std::thread(dispatcher, s);
   return s;
@@ -482,6 +561,9 @@ void kcore_server_destroy(kcore_server* s) {
     hipHostFree(sl->off_h);
     hipHostFree(sl->adj_h);
     hipHostFree(sl->core_h);
+    for (void* p : sl->retired_dev) hipFree(p);
+    for (void* p : sl->retired_host) hipHostFree(p);
+    kc::release_batched(sl->stream);
     hipStreamDestroy(sl->stream);
     delete sl;
   }

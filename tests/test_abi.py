@@ -38,9 +38,9 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layouts_match_header_sizes():
     import paper_2502_08042_amd as K
     # sizes implied by the header's field lists (natural alignment on x86-64)
-    assert ctypes.sizeof(K.Options) == 48
+    assert ctypes.sizeof(K.Options) == 64
     assert ctypes.sizeof(K.Stats) == 8 * 8 + 4 * 3 + 4 * 5
-    assert ctypes.sizeof(K.ServerConfig) == 16 + 8 * 3 + 8 + 16
+    assert ctypes.sizeof(K.ServerConfig) == 16 + 8 * 3 + 8 + 8 + 16
     assert ctypes.sizeof(K.RequestStats) == 8 * 4 + 8 + 8
 
 
@@ -62,7 +62,10 @@ def test_argument_errors_without_device_work():
     o.tile_edges = 100
     assert lib.kcore_decompose_ex(one.ctypes.data, None, 0, None, None, ctypes.byref(o), None) == -1
     o = K.Options()
-    o.reserved[0] = 1
+    o.block_queue = 2000
+    assert lib.kcore_decompose_ex(one.ctypes.data, None, 0, None, None, ctypes.byref(o), None) == -1
+    o = K.Options()
+    o.reserved[2] = 1
     assert lib.kcore_decompose_ex(one.ctypes.data, None, 0, None, None, ctypes.byref(o), None) == -1
     # batched: negative sizes, empty batch
     assert lib.kcore_decompose_batched(None, None, None, -1, 0, None, None) == -1

@@ -106,11 +106,12 @@ def test_chained_work_queues_do_not_change_results():
     cases = [("rmat13", gg.rmat(13, 16, 7)), ("road256", gg.grid_road(256, 0.05, 0.01, 3))]
     for name, g in cases:
         want = oracle.bz(g.offsets, g.adj)
-        for bt, af, asc in ((-1, -1, -1), (1, -1, -1), (4, 0, 0), (2000, -1, -1), (0, 0, 1 << 30),
-                            (0, 0, 0)):
-            say(f"[gpu] queues {name} block_tiles={bt} async_frontier={af} async_scan={asc}")
+        for bt, bq, af, asc in ((-1, 0, -1, -1), (1, 0, -1, -1), (4, 0, 0, 0), (2000, 0, -1, -1),
+                                (4, 8, -1, -1), (0, 0, 0, 1 << 30), (0, 0, 0, 0)):
+            say(f"[gpu] queues {name} block_tiles={bt} block_queue={bq} async_frontier={af} "
+                f"async_scan={asc}")
             got, st = run_single(g.offsets, g.adj, mode="chained", hub_degree=16, tile_edges=64,
-                                 block_tiles=bt, async_frontier=af, async_scan=asc)
+                                 block_tiles=bt, block_queue=bq, async_frontier=af, async_scan=asc)
             assert not first_mismatch(got, want), first_mismatch(got, want)
             assert st["peeled"] == g.n and st["edges"] == g.m and st["device_status"] == 0
 
