@@ -71,7 +71,8 @@ typedef struct {
                             to size the tile lists */
   int32_t local_budget;  /* chained mode: vertices one wavefront may peel from its local queue per
                             phase before handing the rest to the global frontier; 0 = default */
-  int32_t tile_edges;    /* adjacency entries per hub tile (multiple of 64); 0 = default */
+  int32_t tile_edges;    /* adjacency entries per hub tile (multiple of 64, at most 32768);
+                            0 = default */
   int32_t async_frontier;/* chained mode: a frontier of at most this many vertices (and as many
                             hub tiles) is peeled by one asynchronous phase with a shared work
                             queue instead of barrier-separated subrounds; 0 = default, -1 = never */
@@ -82,10 +83,19 @@ typedef struct {
                             is peeled in the same phase by the 16 wavefronts of the workgroup that
                             pushed it (workgroup-local tile queue) instead of in the next phase by
                             the whole grid; 0 = default, -1 = never */
-  int32_t block_queue;   /* chained mode: tiles one workgroup may take into its own queue per phase
-                            (at most 1024); the rest go to the next phase's global list, so one
-                            workgroup's chain cannot hold up the grid; 0 = default */
-  int32_t reserved[3];   /* must be zero */
+  int32_t block_queue;   /* chained mode: a workgroup queues a hub's tiles only while at most this
+                            many tiles wait unclaimed in its queue (at most 1024); otherwise they
+                            go to the next phase's global list, so a burst of hubs is spread over
+                            the grid instead of holding one workgroup up; 0 = default */
+  int32_t tile_probe;    /* 0 = default: hub tiles skip neighbours already peeled (one probe of a
+                            bitmap per entry, fewer atomics); -1 = only in large phases, so small
+                            latency-bound phases save a memory round trip per tile */
+  int32_t residual;      /* chained and level-sync modes: once the active set has at most this many
+                            vertices (at a round boundary), the rows of the live vertices are
+                            rewritten once without their peeled neighbours, so later rounds stop
+                            reading dead entries; costs 16 bytes per vertex and half the adjacency
+                            in workspace; 0 = default (n / 256, at least 4096), -1 = never */
+  int32_t reserved[1];   /* must be zero */
 } kcore_options;
 
 /* Counters of one decomposition (filled when a kcore_stats* is passed; that call synchronises
@@ -95,7 +105,8 @@ typedef struct {
   int64_t subrounds;       /* peel passes over a non-empty frontier (rho in level-sync mode) */
   int64_t barriers;        /* grid-wide synchronisations executed */
   int64_t peeled;          /* vertices given a coreness (= n) */
-  int64_t edges;           /* adjacency entries expanded (= m) */
+  int64_t edges;           /* adjacency entries expanded (= m; entries dropped when rows are
+                              rewritten without peeled neighbours count as expanded there) */
   int64_t decrements;      /* global atomic decrements issued */
   int64_t combined;        /* decrements absorbed by LDS combining */
   int64_t scanned;         /* active-set slots scanned (Thm. 3.1 bounds this by n + m) */
@@ -105,7 +116,8 @@ typedef struct {
   int32_t reserved[5];
 } kcore_stats;
 
-/* Single graph. n == 0 is a no-op; adj may be null when offsets[n] == 0. */
+/* Single graph. n == 0 is a no-op; adj may be null when offsets[n] == 0; KCORE_ETOOBIG when
+ * offsets[n] >= 2^47. */
 int kcore_decompose(const int64_t* offsets, const int32_t* adj, int64_t n, int32_t* coreness_out,
                     hipStream_t stream);
 

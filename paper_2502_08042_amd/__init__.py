@@ -48,7 +48,8 @@ class Options(ctypes.Structure):
                 ("num_entries", ctypes.c_int64), ("local_budget", ctypes.c_int32),
                 ("tile_edges", ctypes.c_int32), ("async_frontier", ctypes.c_int32),
                 ("async_scan", ctypes.c_int32), ("block_tiles", ctypes.c_int32),
-                ("block_queue", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("block_queue", ctypes.c_int32), ("tile_probe", ctypes.c_int32),
+                ("residual", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
 
 
 class Stats(ctypes.Structure):
@@ -144,7 +145,7 @@ def _stream_ptr(stream) -> int:
 
 def _options(mode, validate, num_entries, hub_degree=0, local_budget=0, tile_edges=0,
              blocks_per_cu=0, async_frontier=0, async_scan=0, block_tiles=0,
-             block_queue=0) -> Options:
+             block_queue=0, tile_probe=0, residual=0) -> Options:
     o = Options()
     o.mode = MODES[mode] if isinstance(mode, str) else int(mode)
     o.validate = 1 if validate else 0
@@ -157,6 +158,8 @@ def _options(mode, validate, num_entries, hub_degree=0, local_budget=0, tile_edg
     o.async_scan = async_scan
     o.block_tiles = block_tiles
     o.block_queue = block_queue
+    o.tile_probe = tile_probe
+    o.residual = residual
     return o
 
 

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -65,16 +66,18 @@ int dev_info(int dev, DevInfo& out) {
 
 // ---- single-graph workspace ---------------------------------------------------------------
 struct PeelWs {
-  int64_t n_cap = -1, t_cap = -1;
+  int64_t n_cap = -1, t_cap = -1, r_cap = -1;
   void* block = nullptr;  // one allocation for everything
   size_t bytes = 0;
   uint32_t* dt = nullptr;
   uint32_t* state = nullptr;
   int32_t* act[2] = {nullptr, nullptr};
   int32_t* fr[2] = {nullptr, nullptr};
-  int2* tl[2] = {nullptr, nullptr};
+  unsigned long long* tl[2] = {nullptr, nullptr};
   long long* aq = nullptr;
   int64_t q_cap = 0;
+  long long* rrow = nullptr;
+  int32_t* radj = nullptr;
   kc::PeelCtl* ctl = nullptr;
   unsigned long long* host_stats = nullptr;  // pinned
   unsigned* vstat = nullptr;                 // validation status + xor sum (device)
@@ -101,7 +104,7 @@ std::map<Key, BatchWs*> g_batch;
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
-int peel_ws(int dev, hipStream_t s, int64_t n, int64_t tcap, PeelWs*& out) {
+int peel_ws(int dev, hipStream_t s, int64_t n, int64_t tcap, int64_t rcap, PeelWs*& out) {
   std::lock_guard<std::mutex> lk(g_mu);
   PeelWs*& w = g_peel[Key(dev, s)];
   if (!w) {
@@ -110,7 +113,7 @@ int peel_ws(int dev, hipStream_t s, int64_t n, int64_t tcap, PeelWs*& out) {
     HIP_TRY(hipEventCreate(&w->ev0));
     HIP_TRY(hipEventCreate(&w->ev1));
   }
-  if (w->n_cap < n || w->t_cap < tcap) {
+  if (w->n_cap < n || w->t_cap < tcap || w->r_cap < rcap) {
     if (w->block) {
       HIP_TRY(hipStreamSynchronize(s));
       HIP_TRY(hipFree(w->block));
@@ -118,6 +121,7 @@ int peel_ws(int dev, hipStream_t s, int64_t n, int64_t tcap, PeelWs*& out) {
     }
     const int64_t nc = n > w->n_cap ? n + n / 8 : w->n_cap;
     const int64_t tc = tcap > w->t_cap ? tcap + tcap / 8 + 64 : w->t_cap;
+    const int64_t rc = rcap > w->r_cap ? rcap : std::max<int64_t>(w->r_cap, 0);
     const size_t nw = (size_t)((nc + 15) / 16);
     size_t off = 0;
     const size_t o_dt = off; off = align_up(off + 4 * (size_t)nc);
@@ -130,12 +134,14 @@ int peel_ws(int dev, hipStream_t s, int64_t n, int64_t tcap, PeelWs*& out) {
     const size_t o_t1 = off; off = align_up(off + 8 * (size_t)tc);
     const int64_t qc = nc + tc + 256 * 64 * 64;  // entries of one phase + one claim per wave
     const size_t o_q = off; off = align_up(off + 8 * (size_t)qc);
+    const size_t o_rr = off; off = align_up(off + (rc > 0 ? 16 * (size_t)nc : 0));
+    const size_t o_ra = off; off = align_up(off + 4 * (size_t)rc);
     const size_t o_c = off; off = align_up(off + sizeof(kc::PeelCtl));
     const size_t o_v = off; off = align_up(off + 64);
     hipError_t e = hipMalloc(&w->block, off);
     if (e != hipSuccess) {
       w->block = nullptr;
-      w->n_cap = w->t_cap = -1;
+      w->n_cap = w->t_cap = w->r_cap = -1;
       return fail(KCORE_ENOMEM, "workspace of %zu bytes: %s", off, hipGetErrorString(e));
     }
     char* b = static_cast<char*>(w->block);
@@ -146,10 +152,13 @@ int peel_ws(int dev, hipStream_t s, int64_t n, int64_t tcap, PeelWs*& out) {
     w->act[1] = (int32_t*)(b + o_a1);
     w->fr[0] = (int32_t*)(b + o_f0);
     w->fr[1] = (int32_t*)(b + o_f1);
-    w->tl[0] = (int2*)(b + o_t0);
-    w->tl[1] = (int2*)(b + o_t1);
+    w->tl[0] = (unsigned long long*)(b + o_t0);
+    w->tl[1] = (unsigned long long*)(b + o_t1);
     w->aq = (long long*)(b + o_q);
     w->q_cap = qc;
+    w->rrow = rc > 0 ? (long long*)(b + o_rr) : nullptr;
+    w->radj = rc > 0 ? (int32_t*)(b + o_ra) : nullptr;
+    w->r_cap = rc;
     w->ctl = (kc::PeelCtl*)(b + o_c);
     w->vstat = (unsigned*)(b + o_v);
     w->n_cap = nc;
@@ -209,10 +218,12 @@ int check_opts(const kcore_options* o) {
   if (!o) return KCORE_OK;
   if (o->mode < 0 || o->mode > 2) return fail(KCORE_EINVAL, "mode %d unknown", o->mode);
   if (o->blocks_per_cu < 0 || o->hub_degree < 0 || o->num_entries < 0 || o->local_budget < 0 ||
-      o->tile_edges < 0 || (o->tile_edges % 64) != 0)
-    return fail(KCORE_EINVAL, "negative option, or tile_edges not a multiple of 64");
-  for (int i = 0; i < 3; ++i)
+      o->tile_edges < 0 || (o->tile_edges % 64) != 0 || o->tile_edges > 32768)
+    return fail(KCORE_EINVAL, "negative option, or tile_edges not a multiple of 64 up to 32768");
+  for (int i = 0; i < 2; ++i)
     if (o->reserved[i]) return fail(KCORE_EINVAL, "reserved option fields must be zero");
+  if (o->tile_probe < -1 || o->tile_probe > 0) return fail(KCORE_EINVAL, "tile_probe must be 0 or -1");
+  if (o->residual < -1) return fail(KCORE_EINVAL, "residual must be >= -1");
   if (o->block_queue < 0 || o->block_queue > kc::kBlockQ)
     return fail(KCORE_EINVAL, "block_queue must be in [0, %d]", kc::kBlockQ);
   if (o->async_frontier < -1 || o->async_scan < -1 || o->block_tiles < -1)
@@ -290,13 +301,21 @@ int kcore_decompose_ex(const int64_t* offsets, const int32_t* adj, int64_t n, in
   }
   if (m < 0) return fail(KCORE_EINVAL, "offsets[n] = %lld is negative", (long long)m);
   if (m > 0 && !adj) return fail(KCORE_EINVAL, "adj is null but the graph has %lld entries", (long long)m);
+  // hub tiles address entries with 48 bits
+  if (m >= (1ll << 47)) return fail(KCORE_ETOOBIG, "%lld entries exceed the 2^47 limit", (long long)m);
   // tiles pushed over the whole run: sum over hubs of ceil(deg / tile) <= m / tile + #hubs,
   // #hubs <= min(n, m / hub)
   const int64_t hubs = std::min<int64_t>(n, m / (int64_t)hub + 1);
   const int64_t tcap = m / tile + hubs + 64;
 
+  // residual rows (rewritten without peeled neighbours once the active set is small): room for
+  // half the adjacency; the rewrite happens only if the live rows fit
+  const int32_t ro = opt ? opt->residual : 0;
+  const int64_t resid_vmax = ro < 0 ? -1 : (ro ? ro : std::max<int64_t>(n / 256, 4096));
+  const int64_t rcap = resid_vmax < 0 ? 0 : m / 2 + 64;
+
   PeelWs* w = nullptr;
-  if (int rc = peel_ws(dev, stream, n, tcap, w)) return rc;
+  if (int rc = peel_ws(dev, stream, n, tcap, rcap, w)) return rc;
   if (opt && opt->validate) {
     if (int rc = run_validate(offsets, adj, n, nullptr, 0, w->vstat, stream)) return rc;
   }
@@ -342,7 +361,16 @@ int kcore_decompose_ex(const int64_t* offsets, const int32_t* adj, int64_t n, in
   a.async_scan_max = as < 0 ? -1 : (as ? as : 0);
   const int32_t bt = opt ? opt->block_tiles : 0;
   a.bq_max_tiles = bt < 0 ? 0 : (bt ? bt : 32);
-  a.bq_cap = (opt && opt->block_queue) ? opt->block_queue : kc::kBlockQ;
+  a.bq_backlog = (opt && opt->block_queue) ? opt->block_queue : 64;
+  a.tile_probe_always = !(opt && opt->tile_probe < 0);
+  a.rrow = w->rrow;
+  a.radj = w->radj;
+  a.rcap = rcap;
+  a.resid_vmax = w->rrow ? resid_vmax : -1;
+  // debugging aid: KCORE_DEBUG_PHASE=p records every workgroup's timing in phases [p, p + 64)
+  const char* dp = getenv("KCORE_DEBUG_PHASE");
+  a.dbg_lo = dp ? atoll(dp) : -1;
+  if (a.dbg_lo < 0) a.dbg_lo = -(1ll << 40);
 
   HIP_TRY(kc::launch_init_ctl(w->ctl, stream));
   if (a.chained) HIP_TRY(kc::launch_fill_u32(w->aq, 0xffffffffu, 2 * (size_t)w->q_cap, stream));
@@ -382,6 +410,24 @@ int kcore_debug_trace(hipStream_t stream, unsigned long long* out, int max_phase
   const int np = max_phases < kc::kTracePhases ? max_phases : kc::kTracePhases;
   HIP_TRY(hipStreamSynchronize(stream));
   HIP_TRY(hipMemcpy(out, w->ctl->trace, sizeof(unsigned long long) * 8 * np, hipMemcpyDeviceToHost));
+  return KCORE_OK;
+}
+
+// Debugging aid, not part of kcore.h: copies the per-workgroup record (kDbgPhases x kDbgBlocks
+// rows of start, work done, workgroup-queue tiles, local-queue vertices) of the last single-graph
+// call on `stream`. Synchronises.
+int kcore_debug_blocks(hipStream_t stream, unsigned long long* out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  PeelWs* w = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_peel.find(Key(dev, stream));
+    if (it == g_peel.end() || !it->second || !it->second->ctl) return fail(KCORE_ENOTFOUND, "no workspace");
+    w = it->second;
+  }
+  HIP_TRY(hipStreamSynchronize(stream));
+  HIP_TRY(hipMemcpy(out, w->ctl->dbg, sizeof(w->ctl->dbg), hipMemcpyDeviceToHost));
   return KCORE_OK;
 }
 

@@ -191,8 +191,20 @@ struct WaveCtx {
   bool arbitrate;      // phase-uniform: crossings may race with a scan (chained scan phases)
   bool bq_open;        // phase-uniform: small hubs go to the workgroup's tile queue
   unsigned long long* bq;  // LDS, kBlockQ entries: (tile << 32) | vertex, kQEmpty or kQSkip
-  int* bqc;            // LDS: claimed, reserved, busy waves
+  int* bqc;            // LDS: claimed, reserved, busy waves, [4..5] debug counts
+  const int32_t* adj;  // adjacency the rows point into: the input, or the residual rows
+  const long long* rows;  // row bounds: offsets (stride 1) or residual (start, end) pairs (stride 2)
+  int rstride;
+  bool resid;          // rows come from the residual rows
 };
+
+// Row of v: [b, b + d) in c.adj.
+__device__ __forceinline__ void row_of(const PeelArgs& a, const WaveCtx& c, int32_t v, long long& b,
+                                       long long& d) {
+  const long long* r = c.rows + (long long)v * c.rstride;
+  b = r[0];
+  d = r[1] - b;
+}
 
 __device__ __forceinline__ unsigned comb_hash(int32_t u) {
   return ((unsigned)u * 2654435761u) >> (32 - kCombBits);
@@ -221,7 +233,7 @@ __device__ __forceinline__ bool comb_add(WaveCtx& c, int32_t u) {
 struct PhaseOut {
   PhaseSlot* slot;
   int32_t* fr;  // frontier list written in this phase
-  int2* tl;     // tile list written in this phase
+  unsigned long long* tl;  // tile list written in this phase (span words)
 };
 
 // Pushes crossed/extracted vertices: hubs are split into tiles on the global tile list, small
@@ -232,6 +244,13 @@ constexpr uint32_t kWholeRow = 0xffffffffu;
 constexpr long long kQEmpty = -1ll;
 constexpr long long kQSkip = -2ll;  // a reserved workgroup-queue slot that holds no work
 
+// A hub tile as one word: position of its first adjacency entry (high 48 bits) and its length (low
+// 16 bits), so that peeling it needs no lookup of the row's offsets. Lengths never reach 0xfffe,
+// so a span never equals kQEmpty or kQSkip.
+__device__ __forceinline__ unsigned long long span_word(long long pos, long long len) {
+  return ((unsigned long long)pos << 16) | (unsigned long long)len;
+}
+
 template <class T>
 __device__ __forceinline__ T lds_ld(const T* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -241,23 +260,32 @@ __device__ __forceinline__ void lds_st(T* p, T v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// Chained mode: appends the tiles of the lanes with cnt > 0 to the workgroup's tile queue. Either
+// Chained mode: appends the cnt tiles of row [rb, rb + deg) of each lane with cnt > 0 to the
+// workgroup's tile queue. Either
 // the whole wave's request fits, or none of it does (its reserved slots are then marked empty of
 // work and the caller sends the tiles to the global list). All lanes call; true for lanes whose
 // tiles were queued.
-__device__ __forceinline__ bool block_push(WaveCtx& c, int32_t v, long long cnt, int cap) {
+__device__ __forceinline__ bool block_push(WaveCtx& c, long long rb, long long deg, long long tile, long long cnt,
+                                           int backlog_max) {
   const long long incl = wave_incl_scan(cnt);
   const long long tot = __shfl(incl, 63, 64);
   if (tot == 0) return false;
-  int base = 0;
-  if (lane_id() == 0) base = atomicAdd(&c.bqc[1], (int)tot);
+  int base = -1;
+  if (lane_id() == 0) {
+    // a burst of hubs (more than backlog_max tiles waiting) is better spread over the whole grid
+    // by the next phase than worked off by this workgroup's 16 waves
+    const int waiting = lds_ld(&c.bqc[1]) - lds_ld(&c.bqc[0]);
+    if ((long long)waiting + tot <= backlog_max) base = atomicAdd(&c.bqc[1], (int)tot);
+  }
   base = __shfl(base, 0, 64);
+  if (base < 0) return false;
+  const int cap = kBlockQ;
   const bool fits = (long long)base + tot <= cap;
   const long long s0 = (long long)base + incl - cnt;
   for (long long j = 0; j < cnt; ++j) {
     const long long sl = s0 + j;
     if (sl < cap)
-      lds_st(&c.bq[sl], fits ? (((unsigned long long)j << 32) | (unsigned)v) : (unsigned long long)kQSkip);
+      lds_st(&c.bq[sl], fits ? span_word(rb + j * tile, min(tile, deg - j * tile)) : (unsigned long long)kQSkip);
   }
   return fits && cnt > 0;
 }
@@ -305,9 +333,9 @@ __device__ __forceinline__ void push_vertices(const PeelArgs& a, WaveCtx& c, con
   const bool ph = p && hub;
   const unsigned long long mh = __ballot(ph);
   if (mh) {
-    long long nt = 0;
+    long long nt = 0, rb = 0, deg = 0;
     if (ph) {
-      const long long deg = a.off[v + 1] - a.off[v];
+      row_of(a, c, v, rb, deg);
       nt = (deg + a.tile - 1) / a.tile;
     }
     if (lane_id() == 0) aadd(&o.slot->hubv, (unsigned long long)__popcll(mh));
@@ -316,7 +344,8 @@ __device__ __forceinline__ void push_vertices(const PeelArgs& a, WaveCtx& c, con
       return;
     }
     bool pg = ph;
-    if (c.bq_open && block_push(c, v, (ph && nt <= a.bq_max_tiles) ? nt : 0, a.bq_cap)) pg = false;
+    if (c.bq_open && block_push(c, rb, deg, a.tile, (ph && nt <= a.bq_max_tiles) ? nt : 0, a.bq_backlog))
+      pg = false;
     if (!pg) nt = 0;
     if (__ballot(pg) == 0) return;
     const long long incl = wave_incl_scan(nt);
@@ -328,36 +357,33 @@ __device__ __forceinline__ void push_vertices(const PeelArgs& a, WaveCtx& c, con
       if (lane_id() == 0) aor(&a.ctl->status, (unsigned)KC_ERR_OVERFLOW);
     } else if (pg) {
       const long long s0 = (long long)base + incl - nt;
-      for (long long j = 0; j < nt; ++j) {
-        int32_t* e = reinterpret_cast<int32_t*>(&o.tl[s0 + j]);
-        ast(&e[0], v);
-        ast(&e[1], (int32_t)j);
-      }
+      for (long long j = 0; j < nt; ++j) ast(&o.tl[s0 + j], span_word(rb + j * a.tile, min((long long)a.tile, deg - j * a.tile)));
     }
   }
 }
 
-// Up to kEdgeUnroll adjacency entries per lane: the online decrement of Alg. 3. All loads, and
+// Up to U adjacency entries per lane: the online decrement of Alg. 3. All loads, and
 // then all atomics, of a lane are issued before any result is used, so one pass costs a few memory
 // round trips however many entries it covers. In large phases (c.precheck) a neighbour whose
 // peeled bit is already set is skipped and hub targets go to the LDS combining table; in small,
 // latency-bound phases the probe is skipped (decrementing a peeled vertex is harmless: it can
 // never cross k again, and each neighbour decrements it once, so it never drops below zero).
 // The lane whose decrement takes u from k+1 to k pushes it.
+template <int U>
 __device__ __forceinline__ void edges_batch(const PeelArgs& a, WaveCtx& c, const PhaseOut& o,
-                                            const int32_t (&u)[kEdgeUnroll], unsigned valid, uint32_t k) {
-  uint32_t sw[kEdgeUnroll];
+                                            const int32_t (&u)[U], unsigned valid, uint32_t k) {
+  uint32_t sw[U];
 #pragma unroll
-  for (int j = 0; j < kEdgeUnroll; ++j) sw[j] = 0u;
+  for (int j = 0; j < U; ++j) sw[j] = 0u;
   if (c.precheck) {
 #pragma unroll
-    for (int j = 0; j < kEdgeUnroll; ++j)
+    for (int j = 0; j < U; ++j)
       if ((valid >> j) & 1u) sw[j] = ald(&a.state[u[j] >> 4]);
   }
-  uint32_t old[kEdgeUnroll];
+  uint32_t old[U];
   unsigned did = 0u;
 #pragma unroll
-  for (int j = 0; j < kEdgeUnroll; ++j) {
+  for (int j = 0; j < U; ++j) {
     old[j] = 0u;
     if (!((valid >> j) & 1u)) continue;
     c.edges += 1;
@@ -373,7 +399,7 @@ __device__ __forceinline__ void edges_batch(const PeelArgs& a, WaveCtx& c, const
     did |= 1u << j;
   }
 #pragma unroll
-  for (int j = 0; j < kEdgeUnroll; ++j) {
+  for (int j = 0; j < U; ++j) {
     bool crossed = ((did >> j) & 1u) && (old[j] & DMASK) == k + 1u;
     const bool hub = (old[j] & HUBBIT) != 0u;
     if (crossed) {
@@ -399,10 +425,7 @@ __device__ __forceinline__ void edges_batch(const PeelArgs& a, WaveCtx& c, const
 // search over the scan.
 __device__ __forceinline__ void expand_rows(const PeelArgs& a, WaveCtx& c, const PhaseOut& o, int32_t v, uint32_t k) {
   long long b = 0, d = 0;
-  if (v >= 0) {
-    b = a.off[v];
-    d = a.off[v + 1] - b;
-  }
+  if (v >= 0) row_of(a, c, v, b, d);
   const long long incl = wave_incl_scan(d);
   const long long excl = incl - d;
   const long long total = __shfl(incl, 63, 64);
@@ -423,7 +446,7 @@ __device__ __forceinline__ void expand_rows(const PeelArgs& a, WaveCtx& c, const
       const long long pos = __shfl(b, j, 64) + (t - __shfl(excl, j, 64));
       u[q] = 0;
       if (t < total) {
-        u[q] = a.adj[pos];
+        u[q] = c.adj[pos];
         valid |= 1u << q;
       }
     }
@@ -431,30 +454,38 @@ __device__ __forceinline__ void expand_rows(const PeelArgs& a, WaveCtx& c, const
   }
 }
 
-// A tile of a hub row: edges [off[v] + j*tile, min(off[v+1], off[v] + (j+1)*tile)).
-__device__ __forceinline__ void expand_tile(const PeelArgs& a, WaveCtx& c, const PhaseOut& o, int32_t v, int32_t j,
-                            uint32_t k) {
-  // hub rows mostly point at vertices peeled long ago: always probe the peeled bits here
+// A hub tile: adjacency entries [pos, pos + len), len <= 64 * kTileUnroll for default tiles.
+__device__ __forceinline__ void expand_span(const PeelArgs& a, WaveCtx& c, const PhaseOut& o, long long pos,
+                                            long long len, uint32_t k) {
+  // hub rows mostly point at vertices peeled long ago: probe the peeled bits here (in every phase
+  // unless only large phases are asked for)
   const bool saved = c.precheck;
-  c.precheck = true;
-  const long long rb = a.off[v], re = a.off[v + 1];
-  const long long b = rb + (long long)j * a.tile;
-  const long long e = min(re, b + a.tile);
-  for (long long p0 = b; p0 < e; p0 += 64 * kEdgeUnroll) {
-    int32_t u[kEdgeUnroll];
+  c.precheck = saved || a.tile_probe_always;
+  const long long e = pos + len;
+  for (long long p0 = pos; p0 < e; p0 += 64 * kTileUnroll) {
+    int32_t u[kTileUnroll];
     unsigned valid = 0u;
 #pragma unroll
-    for (int q = 0; q < kEdgeUnroll; ++q) {
-      const long long pos = p0 + 64 * q + lane_id();
+    for (int q = 0; q < kTileUnroll; ++q) {
+      const long long i = p0 + 64 * q + lane_id();
       u[q] = 0;
-      if (pos < e) {
-        u[q] = a.adj[pos];
+      if (i < e) {
+        u[q] = c.adj[i];
         valid |= 1u << q;
       }
     }
     edges_batch(a, c, o, u, valid, k);
   }
   c.precheck = saved;
+}
+
+// Tile j of the row of v (async queue entries name the vertex).
+__device__ __forceinline__ void expand_tile(const PeelArgs& a, WaveCtx& c, const PhaseOut& o, int32_t v, int32_t j,
+                                            uint32_t k) {
+  long long rb = 0, d = 0;
+  row_of(a, c, v, rb, d);
+  const long long b = rb + (long long)j * a.tile;
+  expand_span(a, c, o, b, min(rb + d, b + a.tile) - b, k);
 }
 
 // Applies the block's combined decrements: one atomic subtraction of c per target; exactly one
@@ -497,6 +528,7 @@ __device__ __forceinline__ void drain_local(const PeelArgs& a, WaveCtx& c, const
     c.lq_head = (c.lq_head + take) & (kLocalQ - 1);
     c.lq_cnt -= take;
     c.lq_used += take;
+    if (lane_id() == 0) atomicAdd(&c.bqc[5], take);
     expand_rows(a, c, o, v, k);
   }
   while (c.lq_cnt > 0) {
@@ -530,7 +562,7 @@ __device__ __forceinline__ void block_loop(const PeelArgs& a, WaveCtx& c, const 
       const unsigned long long t0 = wall_clock64();
       for (int spin = 0;; ++spin) {
         const int h = lds_ld(head);
-        const int t = min(lds_ld(tail), a.bq_cap);
+        const int t = min(lds_ld(tail), kBlockQ);
         if (h < t) {
           if (!counted) {
             atomicAdd(busy, 1);
@@ -544,6 +576,7 @@ __device__ __forceinline__ void block_loop(const PeelArgs& a, WaveCtx& c, const 
               if ((s2 & 255) == 255 && wall_clock64() - t0 > 400000000ull) break;
             }
             state = e == kQEmpty ? 3 : 1;
+            atomicAdd(&c.bqc[4], 1);
             break;
           }
           continue;
@@ -554,7 +587,7 @@ __device__ __forceinline__ void block_loop(const PeelArgs& a, WaveCtx& c, const 
           continue;
         }
         if (lds_ld(busy) == 0) {
-          if (lds_ld(head) >= min(lds_ld(tail), a.bq_cap)) {
+          if (lds_ld(head) >= min(lds_ld(tail), kBlockQ)) {
             state = 2;
             break;
           }
@@ -572,9 +605,7 @@ __device__ __forceinline__ void block_loop(const PeelArgs& a, WaveCtx& c, const 
     if (state != 1) return;
     e = __shfl(e, 0, 64);
     if (e == kQSkip) continue;
-    const int32_t v = (int32_t)(e & 0xffffffffll);
-    const int32_t j = (int32_t)((unsigned long long)e >> 32);
-    expand_tile(a, c, o, v, j, k);
+    expand_span(a, c, o, (long long)((unsigned long long)e >> 16), e & 0xffff, k);
     drain_local(a, c, o, k);
   }
 }
@@ -654,7 +685,7 @@ __device__ __forceinline__ void async_loop(const PeelArgs& a, WaveCtx& c, const 
   }
 }
 
-enum PhaseKind { PH_SCAN = 0, PH_EXPAND = 1, PH_ASYNC = 2 };
+enum PhaseKind { PH_SCAN = 0, PH_EXPAND = 1, PH_ASYNC = 2, PH_RESIDUAL = 3 };
 
 __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
   __shared__ int32_t s_sf[kWaves][kStage];
@@ -669,7 +700,7 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
   __shared__ int32_t s_ckey[kCombSlots];
   __shared__ uint32_t s_ccnt[kCombSlots];
   __shared__ unsigned long long s_bq[kBlockQ];
-  __shared__ int s_bqc[4];
+  __shared__ int s_bqc[8];
 
   const int w = threadIdx.x >> 6;
   const int l = lane_id();
@@ -702,8 +733,12 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
   c.bq = s_bq;
   c.bqc = s_bqc;
   c.bq_open = false;
+  c.adj = a.adj;
+  c.rows = reinterpret_cast<const long long*>(a.off);
+  c.rstride = 1;
+  c.resid = false;
   for (int i = threadIdx.x; i < kBlockQ; i += kPeelThreads) s_bq[i] = (unsigned long long)kQEmpty;
-  if (threadIdx.x < 4) s_bqc[threadIdx.x] = threadIdx.x == 2 ? kWaves : 0;
+  if (threadIdx.x < 8) s_bqc[threadIdx.x] = threadIdx.x == 2 ? kWaves : 0;
 
   unsigned epoch = 0;
   long long st_rounds = 0, st_sub = 0, st_bar = 0;
@@ -749,6 +784,9 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
   int acur = 0;
   long long removed_since = 0, total_peeled = 0;
   long long fs = 0, ft = 0;
+  // the rows are rewritten once the active set is at most this large (-1: done, or never); a
+  // rewrite called off for lack of room is tried again when the active set has halved
+  long long resid_limit = a.resid_vmax;
   const long long max_phases = 4 * n + 64;
 
   for (long long p = 1;; ++p) {
@@ -776,6 +814,140 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
     const uint32_t k = (uint32_t)kx;
     const bool tr = blockIdx.x == 0 && threadIdx.x == 0 && p < kTracePhases;
     if (tr) C->trace[p][0] = wall_clock64();
+    const bool dbg = threadIdx.x == 0 && blockIdx.x < kDbgBlocks && p >= a.dbg_lo && p < a.dbg_lo + kDbgPhases;
+    if (dbg) C->dbg[p - a.dbg_lo][blockIdx.x][0] = wall_clock64();
+    if (kind == PH_RESIDUAL) {
+      // Rewrites the rows of the live vertices without their peeled neighbours, once. It runs at a
+      // round boundary: every decrement has landed, so a live vertex's induced degree is its number
+      // of live neighbours and sizes its new row exactly. (1) Reserve the new rows, list the tiles
+      // of the old ones; (2) copy the live neighbours of each old tile to the new row (order within
+      // a row is free) and refresh the hub flags for the new row lengths. When the live rows do not
+      // fit the residual buffer the rewrite is called off after (1) and nothing changes.
+      PhaseSlot* slot = o.slot;
+      const int32_t* alist = a.act[acur];
+      for (long long i0 = gw * 64; i0 < asize; i0 += W * 64) {
+        const long long i = i0 + l;
+        int32_t v = -1;
+        if (i < asize) v = dense ? (int32_t)i : ald(&alist[i]);
+        bool live = false;
+        long long len = 0, ob = 0, od = 0, nt = 0;
+        if (v >= 0) {
+          live = !((ald(&a.state[v >> 4]) >> (v & 15)) & 1u);
+          if (live) {
+            len = ald(&a.dt[v]) & DMASK;
+            ob = a.off[v];
+            od = a.off[v + 1] - ob;
+            nt = (od + a.tile - 1) / a.tile;
+          }
+        }
+        const long long incl = wave_incl_scan(len);
+        const long long tot = __shfl(incl, 63, 64);
+        unsigned long long base = 0;
+        if (l == 0 && tot) base = aadd(&slot->small, (unsigned long long)tot);
+        base = __shfl(base, 0, 64);
+        const long long tincl = wave_incl_scan(nt);
+        const long long ttot = __shfl(tincl, 63, 64);
+        unsigned long long tbase = 0;
+        if (l == 0 && ttot) tbase = aadd(&slot->tiles, (unsigned long long)ttot);
+        tbase = __shfl(tbase, 0, 64);
+        if ((long long)base + tot > a.rcap || (long long)tbase + ttot > a.qcap) {
+          // the live rows do not fit the residual buffer: the rewrite is called off
+          if (l == 0) ast(&slot->hubv, 1ull);
+        } else if (live) {
+          const long long rb = (long long)base + incl - len;
+          ast(&a.rrow[2 * (long long)v], rb);      // first entry
+          ast(&a.rrow[2 * (long long)v + 1], rb);  // fill cursor, the row's end once filled
+          const long long t0 = (long long)tbase + tincl - nt;
+          for (long long j = 0; j < nt; ++j)
+            ast(&a.aq[t0 + j], (long long)(((unsigned long long)j << 32) | (unsigned)v));
+        }
+      }
+      if (!grid_sync(C, epoch)) break;
+      st_bar++;
+      // (2) Copy the live neighbours of each old tile to the new row (order within a row is free).
+      if (threadIdx.x == 0) {
+        s_out[0] = (long long)ald(&slot->tiles);
+        s_out[1] = (long long)ald(&slot->hubv);
+      }
+      __syncthreads();
+      const long long ntl = s_out[0] <= a.qcap ? s_out[0] : a.qcap;
+      const bool called_off = s_out[1] != 0;
+      __syncthreads();
+      for (long long it = gw; it < ntl; it += W) {
+        const long long e = ald(&a.aq[it]);
+        if (called_off) {
+          // entries past a refused reservation were never written: clear every slot
+          if (l == 0) ast(&a.aq[it], kQEmpty);
+          continue;
+        }
+        const int32_t v = (int32_t)(e & 0xffffffffll);
+        const long long j = (long long)((unsigned long long)e >> 32);
+        const long long ob = a.off[v], oe = a.off[v + 1];
+        const long long b = ob + j * a.tile, en = min(oe, b + a.tile);
+        const long long len = (long long)(ald(&a.dt[v]) & DMASK);
+        const long long lim = ald(&a.rrow[2 * (long long)v]) + len;
+        // hub flag for the new row length (only the flag bit changes)
+        if (j == 0 && l == 0) ast(&a.dt[v], (uint32_t)len | (len >= (long long)a.hub ? HUBBIT : 0u));
+        // 256 entries per pass: all loads, then all probes, then one reservation for the pass
+        for (long long p0 = b; p0 < en; p0 += 64 * kTileUnroll) {
+          int32_t u[kTileUnroll];
+          uint32_t sw[kTileUnroll];
+#pragma unroll
+          for (int r = 0; r < kTileUnroll; ++r) {
+            const long long q = p0 + 64 * r + l;
+            u[r] = q < en ? a.adj[q] : -1;
+          }
+#pragma unroll
+          for (int r = 0; r < kTileUnroll; ++r) sw[r] = u[r] >= 0 ? ald(&a.state[u[r] >> 4]) : 1u;
+          unsigned long long mk[kTileUnroll];
+          int cnt = 0;
+#pragma unroll
+          for (int r = 0; r < kTileUnroll; ++r) {
+            const bool lv = u[r] >= 0 && !((sw[r] >> (u[r] & 15)) & 1u);
+            // entries to peeled neighbours are done with here (they count as expanded)
+            c.edges += (u[r] >= 0 && !lv) ? 1 : 0;
+            mk[r] = __ballot(lv);
+            cnt += __popcll(mk[r]);
+          }
+          if (cnt == 0) continue;
+          long long pos = 0;
+          if (l == 0)
+            pos = (long long)aadd(reinterpret_cast<unsigned long long*>(&a.rrow[2 * (long long)v + 1]),
+                                  (unsigned long long)cnt);
+          pos = __shfl(pos, 0, 64);
+          if (pos + cnt > lim) {
+            if (l == 0) aor(&C->status, (unsigned)KC_ERR_OVERFLOW);
+            continue;
+          }
+#pragma unroll
+          for (int r = 0; r < kTileUnroll; ++r) {
+            if ((mk[r] >> l) & 1ull) ast(&a.radj[pos + rank_in(mk[r])], u[r]);
+            pos += __popcll(mk[r]);
+          }
+        }
+        if (l == 0) ast(&a.aq[it], kQEmpty);  // the async queue starts every phase empty
+      }
+      if (tr) {
+        C->trace[p][1] = C->trace[p][2] = wall_clock64();
+        C->trace[p][4] = (unsigned long long)PH_RESIDUAL | ((unsigned long long)k << 8);
+        C->trace[p][5] = C->trace[p][6] = 0;
+        C->trace[p][7] = (unsigned long long)asize;
+      }
+      if (!grid_sync(C, epoch)) break;
+      st_bar++;
+      if (tr) C->trace[p][3] = wall_clock64();
+      if (!called_off) {
+        c.resid = true;
+        c.adj = a.radj;
+        c.rows = a.rrow;
+        c.rstride = 2;
+        resid_limit = -1;
+      } else {
+        resid_limit = asize / 2 > 0 ? asize / 2 : -1;
+      }
+      kind = PH_SCAN;
+      continue;
+    }
     c.lq_used = 0;
     // large phases are bandwidth bound: probe peeled bits and combine hub decrements; small ones
     // are latency bound: skip the probe and spread the frontier over as many waves as possible
@@ -834,7 +1006,7 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
       // Alg. 3 over the frontier: packets of small vertices, then hub tiles (the static share of
       // an async phase is the same).
       const int32_t* fcur = a.fr[(p - 1) & 1];
-      const int2* tcur = a.tl[(p - 1) & 1];
+      const unsigned long long* tcur = a.tl[(p - 1) & 1];
       int per = 64;  // frontier vertices per wave item: fewer when the frontier is small
       while (per > 1 && (fs + per - 1) / per < W) per >>= 1;
       const long long npk = (fs + per - 1) / per;
@@ -845,10 +1017,8 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
           const int32_t v = (l < per && i < fs) ? ald(&fcur[i]) : -1;
           expand_rows(a, c, o, v, k);
         } else {
-          const int32_t* e = reinterpret_cast<const int32_t*>(&tcur[it - npk]);
-          const int32_t v = ald(&e[0]);
-          const int32_t j = ald(&e[1]);
-          expand_tile(a, c, o, v, j, k);
+          const unsigned long long sw = ald(&tcur[it - npk]);
+          expand_span(a, c, o, (long long)(sw >> 16), (long long)(sw & 0xffff), k);
         }
       }
     }
@@ -875,6 +1045,7 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
     if (threadIdx.x < 4) s_bqc[threadIdx.x] = threadIdx.x == 2 ? kWaves : 0;
     if (a.chained) drain_local(a, c, o, k);
     if (tr) C->trace[p][1] = wall_clock64();
+    if (dbg) C->dbg[p - a.dbg_lo][blockIdx.x][1] = wall_clock64();
 
     // ---- phase end: block-level flushes and reductions
     block_flush(c.sf, &o.slot->small, o.fr, a.fcap, &C->status, s_cnt, &s_base);
@@ -902,6 +1073,15 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
       c.mymin = 0xffffffffu;
     }
     if (tr) C->trace[p][2] = wall_clock64();
+    if (threadIdx.x == 0) {
+      // the flushes above end with a workgroup barrier: the phase's counts are complete
+      if (dbg) {
+        C->dbg[p - a.dbg_lo][blockIdx.x][2] = (unsigned long long)s_bqc[4];
+        C->dbg[p - a.dbg_lo][blockIdx.x][3] = (unsigned long long)s_bqc[5];
+      }
+      s_bqc[4] = 0;
+      s_bqc[5] = 0;
+    }
     if (!grid_sync(C, epoch)) break;
     st_bar++;
     if (tr) C->trace[p][3] = wall_clock64();
@@ -978,6 +1158,8 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
         compact = removed_since * 8 >= asize;
       }
     }
+    // at a round boundary with a small active set whose live rows fit: rewrite the rows once
+    if (kind == PH_SCAN && resid_limit >= 0 && asize <= resid_limit) kind = PH_RESIDUAL;
   }
 
   // ---- statistics: per-lane counters reduced per block, one atomic each per block

@@ -12,7 +12,10 @@ constexpr int kLocalQ = 512;         // per-wave local queue (chained mode)
 constexpr int kCombBits = 12;
 constexpr int kCombSlots = 1 << kCombBits;  // per-workgroup LDS combining table for hub targets
 constexpr int kCombProbe = 4;               // linear-probe window of that table
-constexpr int kEdgeUnroll = 2;              // adjacency entries in flight per lane
+constexpr int kEdgeUnroll = 2;              // adjacency entries in flight per lane (rows)
+constexpr int kTileUnroll = 4;              //   (hub tiles: a default tile is one pass)
+constexpr int kDbgPhases = 64;             // phases of the per-workgroup debug record
+constexpr int kDbgBlocks = 256;
 constexpr int kBlockQ = 1024;              // workgroup-local hub tile queue (chained mode)
 constexpr int kAsyncWaves = 2;              // waves per workgroup claiming async work
 constexpr int kBarGroups = 32;       // arrival groups of the grid barrier
@@ -53,6 +56,9 @@ struct alignas(128) PeelCtl {
   // work done, flushed and barrier passed; then kind | precheck << 2 | async << 3 | k << 8, the
   // frontier's vertices, its hub tiles and the active-set size
   unsigned long long trace[kTracePhases][8];
+  // per-workgroup record of the phases [dbg_lo, dbg_lo + kDbgPhases) when asked for: start, work
+  // done, tiles taken from the workgroup queue, vertices peeled from local queues
+  unsigned long long dbg[kDbgPhases][kDbgBlocks][4];
 };
 
 enum : unsigned { KC_ERR_TIMEOUT = 1u, KC_ERR_OVERFLOW = 2u, KC_ERR_PHASES = 4u, KC_ERR_BADGRAPH = 8u };
@@ -66,7 +72,7 @@ struct PeelArgs {
   uint32_t* state;     // per 16 vertices: bits 0..15 peeled, 16..31 hub
   int32_t* act[2];     // compacted active lists
   int32_t* fr[2];      // small-vertex frontiers
-  int2* tl[2];         // hub tiles (vertex, tile index)
+  unsigned long long* tl[2];  // hub tiles: first entry << 16 | length
   int64_t fcap;        // frontier capacity (entries)
   int64_t tcap;        // tile list capacity
   PeelCtl* ctl;
@@ -82,7 +88,13 @@ struct PeelArgs {
   int64_t async_tiles; //   ... and tiles are peeled by an async phase
   int64_t async_scan_max; // chained mode: active sets up to this size scan and peel in one phase
   int32_t bq_max_tiles;   // chained mode: hubs of at most this many tiles stay in the workgroup (0 = off)
-  int32_t bq_cap;         //   and the workgroup takes at most this many tiles per phase (<= kBlockQ)
+  int32_t bq_backlog;     //   while at most this many tiles wait unclaimed in the workgroup's queue
+  int64_t dbg_lo;         // first phase of the per-workgroup debug record (-1 = none)
+  int32_t tile_probe_always; // hub tiles probe peeled bits in every phase (else in large ones only)
+  long long* rrow;        // residual rows: [2v] first entry, [2v + 1] end, in radj
+  int32_t* radj;          // residual adjacency (live neighbours only), rcap entries
+  int64_t rcap;
+  int64_t resid_vmax;     // rewrite the rows once the active set is at most this large (-1 = never)
 };
 
 struct BatchCtl {

@@ -65,7 +65,7 @@ def test_argument_errors_without_device_work():
     o.block_queue = 2000
     assert lib.kcore_decompose_ex(one.ctypes.data, None, 0, None, None, ctypes.byref(o), None) == -1
     o = K.Options()
-    o.reserved[2] = 1
+    o.reserved[0] = 1
     assert lib.kcore_decompose_ex(one.ctypes.data, None, 0, None, None, ctypes.byref(o), None) == -1
     # batched: negative sizes, empty batch
     assert lib.kcore_decompose_batched(None, None, None, -1, 0, None, None) == -1

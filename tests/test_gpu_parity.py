@@ -106,14 +106,35 @@ def test_chained_work_queues_do_not_change_results():
     cases = [("rmat13", gg.rmat(13, 16, 7)), ("road256", gg.grid_road(256, 0.05, 0.01, 3))]
     for name, g in cases:
         want = oracle.bz(g.offsets, g.adj)
-        for bt, bq, af, asc in ((-1, 0, -1, -1), (1, 0, -1, -1), (4, 0, 0, 0), (2000, 0, -1, -1),
-                                (4, 8, -1, -1), (0, 0, 0, 1 << 30), (0, 0, 0, 0)):
+        for bt, bq, af, asc, tp in ((-1, 0, -1, -1, 0), (1, 0, -1, -1, 0), (4, 0, 0, 0, -1),
+                                    (2000, 0, -1, -1, 0), (4, 8, -1, -1, -1), (0, 0, 0, 1 << 30, 0),
+                                    (0, 0, 0, 0, 0), (0, 0, 0, 0, -1)):
             say(f"[gpu] queues {name} block_tiles={bt} block_queue={bq} async_frontier={af} "
-                f"async_scan={asc}")
+                f"async_scan={asc} tile_probe={tp}")
             got, st = run_single(g.offsets, g.adj, mode="chained", hub_degree=16, tile_edges=64,
-                                 block_tiles=bt, block_queue=bq, async_frontier=af, async_scan=asc)
+                                 block_tiles=bt, block_queue=bq, async_frontier=af, async_scan=asc,
+                                 tile_probe=tp)
             assert not first_mismatch(got, want), first_mismatch(got, want)
             assert st["peeled"] == g.n and st["edges"] == g.m and st["device_status"] == 0
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_residual_rows_do_not_change_results(mode):
+    """Rows rewritten without peeled neighbours (at the first round boundary the threshold allows,
+    from a small and from a large threshold) must give the oracle's coreness, and so must runs
+    that never rewrite them."""
+    cases = [("rmat13", gg.rmat(13, 16, 7)), ("road256", gg.grid_road(256, 0.05, 0.01, 3)),
+             ("hcns120", None)]
+    for name, g in cases:
+        off, adj = (g.offsets, g.adj) if g is not None else G.hcns(120)
+        want = oracle.bz(off, adj)
+        for resid in (-1, 1, 64, 1 << 30):
+            for hub in (0, 16):
+                say(f"[gpu] residual {name} mode={mode} residual={resid} hub={hub}")
+                got, st = run_single(off, adj, mode=mode, residual=resid, hub_degree=hub,
+                                     tile_edges=64 if hub else 0)
+                assert not first_mismatch(got, want), first_mismatch(got, want)
+                assert st["peeled"] == len(off) - 1 and st["device_status"] == 0
 
 
 def test_batched_small():
