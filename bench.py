@@ -93,12 +93,14 @@ def bench_single(args):
     value = m / (ms_step / 1000.0) / 1e9
     B = alg_bytes(n, m, st)
     achieved = B / (avg_ms / 1000.0) / 1e9
+    # HBM bytes per launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs (calibrated against a
+    # plain copy), valid only for the kernel source they were taken on
     traffic = None
-    tfile = os.path.join(ROOT, "profiles", f"traffic_{args.workload}_{args.mode}.json")
+    tfile = os.path.join(ROOT, "profiles", f"peel_kernel_{args.workload}_traffic.txt")
     if os.path.exists(tfile):
         with open(tfile) as f:
             tj = json.load(f)
-        if tj.get("kernel_source_sha") == kernel_sha():
+        if tj.get("kernel_source_sha") == kernel_sha() and tj.get("mode") == args.mode:
             traffic = tj.get("bytes_per_launch")
     res = {
         "metric": METRIC, "value": round(value, 4), "unit": "GTEPS", "n_gpus": 1,
