@@ -1,0 +1,59 @@
+"""GPU parity at the benchmark sizes, in the configuration bench.py times (default options, one
+call on the current stream), against the oracle over every vertex: the 16.8M-vertex Chung-Lu graph
+(~1B entries) and the 4096 x 4096 road grid. Also checks that the device-side Chung-Lu generator
+used by bench.py draws exactly the graph of the host generator.
+"""
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+from gpu_util import say, first_mismatch
+
+pytestmark = pytest.mark.gpu
+
+
+def test_device_chung_lu_generator_matches_host():
+    import graphgen.gpu as gp
+    n = 1 << 15
+    say(f"[gpu] chung-lu generator n={n} device vs host")
+    off_d, adj_d = gp.chung_lu_device(n, 2.1, 32 * n, 1_000_000, 300, 0.8, 3)
+    host = gg.chung_lu(n, 2.1, 32 * n, 1_000_000, 300, 0.8, 3)
+    assert np.array_equal(off_d.cpu().numpy(), host.offsets)
+    assert np.array_equal(adj_d.cpu().numpy(), host.adj)
+
+
+def _decompose_like_bench(off, adj):
+    import torch
+    import paper_2502_08042_amd as K
+    out = torch.empty(off.numel() - 1, dtype=torch.int32, device=off.device)
+    K.decompose(off, adj, out)  # default options, as bench.py times it
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def test_full_size_chung_lu_parity():
+    import torch
+    import graphgen.gpu as gp
+    say("[gpu] full-size Chung-Lu n=2^24: generate, decompose, oracle")
+    off, adj = gp.config_chung_lu_device()
+    torch.cuda.synchronize()
+    got = _decompose_like_bench(off, adj)
+    h_off, h_adj = off.cpu().numpy(), adj.cpu().numpy()
+    del off, adj
+    torch.cuda.empty_cache()
+    want = oracle.bz(h_off, h_adj)
+    assert not first_mismatch(got, want), first_mismatch(got, want)
+    assert int(want.max()) == 3911
+
+
+def test_full_size_road_grid_parity():
+    import torch
+    g = gg.config_grid4096()
+    say(f"[gpu] full-size road grid n={g.n} m={g.m}")
+    off = torch.from_numpy(g.offsets).cuda()
+    adj = torch.from_numpy(g.adj).cuda()
+    got = _decompose_like_bench(off, adj)
+    want = oracle.bz(g.offsets, g.adj)
+    assert not first_mismatch(got, want), first_mismatch(got, want)
+    assert int(want.max()) <= 3
