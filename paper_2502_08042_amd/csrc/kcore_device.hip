@@ -458,9 +458,10 @@ __device__ __forceinline__ void expand_rows(const PeelArgs& a, WaveCtx& c, const
 __device__ __forceinline__ void expand_span(const PeelArgs& a, WaveCtx& c, const PhaseOut& o, long long pos,
                                             long long len, uint32_t k) {
   // hub rows mostly point at vertices peeled long ago: probe the peeled bits here (in every phase
-  // unless only large phases are asked for)
+  // unless only large phases are asked for). Rewritten rows hold live neighbours only, so small
+  // phases save the probe's round trip there.
   const bool saved = c.precheck;
-  c.precheck = saved || a.tile_probe_always;
+  c.precheck = saved || (a.tile_probe_always && !c.resid);
   const long long e = pos + len;
   for (long long p0 = pos; p0 < e; p0 += 64 * kTileUnroll) {
     int32_t u[kTileUnroll];
@@ -1267,6 +1268,9 @@ __global__ __launch_bounds__(kBatchThreads) void batched_kernel(BatchArgs a) {
     uint32_t* d = inl ? s_dyn : a.gdt + base;
     int32_t* q = inl ? reinterpret_cast<int32_t*>(s_dyn + a.lds_cap) : a.gq + base;
     const int64_t* off = a.off + base;
+    // a graph held in global memory keeps a peeled bitmap in the (then unused) LDS, so that the
+    // liveness test before a decrement costs no global load
+    uint32_t* pb = (!inl && ng <= 64ll * a.lds_cap) ? s_dyn : nullptr;
 
     // induced degree = degree; k = min degree
     unsigned mn = 0xffffffffu;
@@ -1275,6 +1279,8 @@ __global__ __launch_bounds__(kBatchThreads) void batched_kernel(BatchArgs a) {
       d[i] = dg;
       mn = min(mn, dg);
     }
+    if (pb)
+      for (long long i = tid; i < (ng + 31) / 32; i += kBatchThreads) pb[i] = 0u;
     mn = wave_min(mn);
     if (l == 0) s_min[w] = mn;
     if (tid == 0) s_tail = 0;
@@ -1296,24 +1302,41 @@ __global__ __launch_bounds__(kBatchThreads) void batched_kernel(BatchArgs a) {
       // also the min over the others for a jump
       unsigned nm = 0xffffffffu;
       long long wpos = 0;
-      for (long long i0 = 0; i0 < asz; i0 += kBatchThreads) {
-        const long long i = i0 + tid;
-        bool ext = false, keep = false;
-        int32_t vi = 0;
-        if (i < asz) {
-          vi = dense_b ? (int32_t)i : act[i];
-          const unsigned x = d[vi];
-          st_scanned++;
-          ext = x == k;
-          keep = x > k;
-          if (keep) nm = min(nm, x);
+      // four consecutive slots per thread: independent loads, and one compaction scan per 2048
+      // slots (order preserving, so the in-place compaction never overwrites an unread slot)
+      for (long long i0 = 0; i0 < asz; i0 += 4 * kBatchThreads) {
+        int32_t vi[4];
+        unsigned x[4];
+        bool ext[4], keep[4];
+        int nk = 0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const long long i = i0 + 4 * tid + r;
+          vi[r] = (i < asz) ? (dense_b ? (int32_t)i : act[i]) : -1;
         }
-        team_push(ext, vi, q, &s_tail);
-        if (ext) a.core[base + vi] = (int32_t)k;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) x[r] = vi[r] >= 0 ? d[vi[r]] : 0u;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          ext[r] = vi[r] >= 0 && x[r] == k;
+          keep[r] = vi[r] >= 0 && x[r] > k;
+          if (vi[r] >= 0) st_scanned++;
+          if (keep[r]) {
+            nm = min(nm, x[r]);
+            ++nk;
+          }
+          if (ext[r]) {
+            a.core[base + vi[r]] = (int32_t)k;
+            if (pb) atomicOr(&pb[vi[r] >> 5], 1u << (vi[r] & 31));
+          }
+          team_push(ext[r], vi[r], q, &s_tail);
+        }
         if (!inl) {
           long long kept;
-          const long long ex = block_excl_scan(keep ? 1 : 0, s_w, kept);
-          if (keep) act[wpos + ex] = vi;
+          long long ex = block_excl_scan(nk, s_w, kept);
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            if (keep[r]) act[wpos + ex++] = vi[r];
           wpos += kept;
           __syncthreads();
         }
@@ -1366,12 +1389,14 @@ __global__ __launch_bounds__(kBatchThreads) void batched_kernel(BatchArgs a) {
               const long long pos = s_rb[lo] + (t - s_pref[lo]);
               ul = a.adj[pos] - (a.local_ids ? 0 : (int32_t)base);
               st_edges++;
-              if (d[ul] > k) {
+              const bool live = pb ? !((pb[ul >> 5] >> (ul & 31)) & 1u) : d[ul] > k;
+              if (live) {
                 const unsigned old = inl ? atomicSub(&d[ul], 1u) : wsub(&d[ul], 1u);
                 st_decr++;
                 crossed = old == k + 1;
               }
             }
+            if (crossed && pb) atomicOr(&pb[ul >> 5], 1u << (ul & 31));
             team_push(crossed, ul, q, &s_tail);
             if (crossed) a.core[base + ul] = (int32_t)k;
           }
