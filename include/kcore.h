@@ -134,7 +134,11 @@ int kcore_decompose_ex(const int64_t* offsets, const int32_t* adj, int64_t n, in
  *               graph_vptr[num_graphs] = total_vertices, non-decreasing
  *   offsets     int64[total_vertices+1], adj int32[offsets[total_vertices]] (global ids; must be
  *               non-null even when the batch has no edges)
- *   coreness_out int32[total_vertices] */
+ *   coreness_out int32[total_vertices]
+ * Options of the _ex form: mode LEVELSYNC (= AUTO) peels each round in barrier-separated
+ * subrounds inside the graph's workgroup; CHAINED works each round off through a dynamic
+ * workgroup queue. validate and blocks_per_cu apply; the other fields are ignored. A device failure
+ * is reported only when stats_host is given. */
 int kcore_decompose_batched(const int64_t* graph_vptr, const int64_t* offsets, const int32_t* adj,
                             int32_t num_graphs, int64_t total_vertices, int32_t* coreness_out,
                             hipStream_t stream);

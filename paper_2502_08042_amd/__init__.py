@@ -194,8 +194,11 @@ def decompose(offsets, adj, out=None, *, mode="auto", stats=False, validate=Fals
     return (out, st.as_dict()) if stats else out
 
 
-def decompose_batched(vptr, offsets, adj, out=None, *, stats=False, validate=False, stream=None):
-    """Coreness for a segmented batch of independent graphs (device tensors, global ids)."""
+def decompose_batched(vptr, offsets, adj, out=None, *, mode="auto", stats=False, validate=False,
+                      stream=None):
+    """Coreness for a segmented batch of independent graphs (device tensors, global ids).
+    ``mode``: "auto"/"levelsync" (barrier-separated subrounds inside each graph's workgroup) or
+    "chained" (each round peeled through a dynamic workgroup queue)."""
     import torch
     _dev_tensor(vptr, torch.int64, "vptr")
     _dev_tensor(offsets, torch.int64, "offsets")
@@ -207,7 +210,7 @@ def decompose_batched(vptr, offsets, adj, out=None, *, stats=False, validate=Fal
     if out is None:
         out = torch.empty(max(V, 0), dtype=torch.int32, device=offsets.device)
     _dev_tensor(out, torch.int32, "out")
-    opt = _options("auto", validate, adj.numel())
+    opt = _options(mode, validate, adj.numel())
     st = Stats() if stats else None
     rc = _lib.kcore_decompose_batched_ex(vptr.data_ptr(), offsets.data_ptr(), adj.data_ptr(), G, V,
                                          out.data_ptr() if V else None, _stream_ptr(stream),

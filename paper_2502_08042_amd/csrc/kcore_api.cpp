@@ -439,7 +439,7 @@ int kcore_decompose(const int64_t* offsets, const int32_t* adj, int64_t n, int32
 static int batched_impl(const int64_t* graph_vptr, const int64_t* offsets, const int32_t* adj,
                         int32_t num_graphs, int64_t total_vertices, int32_t* coreness_out,
                         hipStream_t stream, const kcore_options* opt, kcore_stats* stats_host,
-                        bool local_ids);
+                        bool local_ids, unsigned* status_out = nullptr);
 
 int kcore_decompose_batched_ex(const int64_t* graph_vptr, const int64_t* offsets, const int32_t* adj,
                                int32_t num_graphs, int64_t total_vertices, int32_t* coreness_out,
@@ -476,15 +476,15 @@ void kc::release_batched(hipStream_t stream) {
 
 int kc::decompose_batched_local(const int64_t* graph_vptr, const int64_t* offsets, const int32_t* adj,
                                 int32_t num_graphs, int64_t total_vertices, int32_t* coreness_out,
-                                hipStream_t stream) {
+                                hipStream_t stream, unsigned* status_out) {
   return batched_impl(graph_vptr, offsets, adj, num_graphs, total_vertices, coreness_out, stream, nullptr,
-                      nullptr, true);
+                      nullptr, true, status_out);
 }
 
 static int batched_impl(const int64_t* graph_vptr, const int64_t* offsets, const int32_t* adj,
                         int32_t num_graphs, int64_t total_vertices, int32_t* coreness_out,
                         hipStream_t stream, const kcore_options* opt, kcore_stats* stats_host,
-                        bool local_ids) {
+                        bool local_ids, unsigned* status_out) {
   g_err.clear();
   if (num_graphs < 0 || total_vertices < 0)
     return fail(KCORE_EINVAL, "negative num_graphs or total_vertices");
@@ -530,18 +530,29 @@ static int batched_impl(const int64_t* graph_vptr, const int64_t* offsets, const
   a.local_ids = local_ids ? 1 : 0;
   a.ctl = w->ctl;
   a.lds_cap = cap;
+  // barrier-separated subrounds by default: inside one workgroup a barrier is cheap, and peeling a
+  // whole frontier edge-balanced over all 512 threads beats 64-vertex packets claimed per wave
+  a.chained = (opt && opt->mode == KCORE_MODE_CHAINED) ? 1 : 0;
   if (stats_host) HIP_TRY(hipEventRecord(w->ev0, stream));
   HIP_TRY(kc::launch_batched(a, blocks, lds, stream));
+  // the device status word (failure bits), for callers that check it after the stream
+  if (status_out)
+    HIP_TRY(hipMemcpyAsync(status_out, &w->ctl->status, sizeof(unsigned), hipMemcpyDeviceToHost, stream));
   if (!stats_host) return KCORE_OK;
   HIP_TRY(hipEventRecord(w->ev1, stream));
   HIP_TRY(hipMemcpyAsync(w->host_stats, w->ctl->stats, 16 * sizeof(unsigned long long),
                          hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipMemcpyAsync(w->host_stats + 16, &w->ctl->status, sizeof(unsigned), hipMemcpyDeviceToHost,
+                         stream));
   HIP_TRY(hipStreamSynchronize(stream));
+  unsigned status = 0;
+  memcpy(&status, w->host_stats + 16, sizeof status);
   float ms = 0;
   HIP_TRY(hipEventElapsedTime(&ms, w->ev0, w->ev1));
-  fill_stats(stats_host, w->host_stats, 0u, ms);
+  fill_stats(stats_host, w->host_stats, status, ms);
   stats_host->peeled = total_vertices;
   stats_host->barriers = 0;
+  if (status) return fail(KCORE_EDEVICE, "device reported failure bits 0x%x", status);
   return KCORE_OK;
 }
 

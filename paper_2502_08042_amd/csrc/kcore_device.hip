@@ -1241,6 +1241,116 @@ __device__ __forceinline__ void team_push(bool p, int32_t v, int32_t* q, int* s_
   if (p) q[base + rank_in(m)] = v;
 }
 
+// Chained round of one graph (VGC, Sec. 4.2, at workgroup level): the round's queue segment grows
+// while it is worked off; each wave claims up to 64 queued vertices at a time, expands their rows
+// edge-balanced across its lanes and appends the vertices it takes to k to the same queue. A wave
+// leaves when it sees no busy wave (busy first) and then no unclaimed entry; entries are reserved
+// before they are written, so claimed entries are read once they are no longer -1. False on a
+// timeout. All threads call.
+__device__ __forceinline__ bool batch_chain(const BatchArgs& a, uint32_t* d, int32_t* q, uint32_t* pb,
+                                            const int64_t* off, int64_t base, bool inl, uint32_t k,
+                                            int* s_claim, int* s_tail, int* s_busy, long long& st_edges,
+                                            long long& st_decr) {
+  const int l = lane_id();
+  const unsigned long long t_start = wall_clock64();
+  for (;;) {
+    int state = 0, h = 0, cnt = 0;  // state: 1 claimed, 2 done, 3 timeout
+    if (l == 0) {
+      bool counted = true;
+      for (int spin = 0;; ++spin) {
+        const int hh = lds_ld(s_claim);
+        const int tt = lds_ld(s_tail);
+        if (hh < tt) {
+          if (!counted) {
+            atomicAdd(s_busy, 1);
+            counted = true;
+          }
+          const int n = min(64, tt - hh);
+          if (atomicCAS(s_claim, hh, hh + n) == hh) {
+            h = hh;
+            cnt = n;
+            state = 1;
+            break;
+          }
+          continue;
+        }
+        if (counted) {
+          atomicSub(s_busy, 1);
+          counted = false;
+          continue;
+        }
+        if (lds_ld(s_busy) == 0) {
+          if (lds_ld(s_claim) >= lds_ld(s_tail)) {
+            state = 2;
+            break;
+          }
+          continue;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        if ((spin & 255) == 255 && wall_clock64() - t_start > 400000000ull) {
+          state = 3;
+          break;
+        }
+      }
+    }
+    state = __shfl(state, 0, 64);
+    if (state != 1) return state == 2;
+    h = __shfl(h, 0, 64);
+    cnt = __shfl(cnt, 0, 64);
+    int32_t v = -1;
+    if (l < cnt) {
+      for (int spin = 0;; ++spin) {
+        v = lds_ld(&q[h + l]);
+        if (v >= 0) break;
+        if ((spin & 255) == 255 && wall_clock64() - t_start > 400000000ull) break;
+      }
+    }
+    if (__ballot(l < cnt && v < 0)) return false;
+    long long rb = 0, dg = 0;
+    if (v >= 0) {
+      rb = off[v];
+      dg = off[v + 1] - rb;
+    }
+    const long long incl = wave_incl_scan(dg);
+    const long long excl = incl - dg;
+    const long long total = __shfl(incl, 63, 64);
+    for (long long e0 = 0; e0 < total; e0 += 64) {
+      const long long t = e0 + l;
+      int j = 0;
+#pragma unroll
+      for (int step = 32; step >= 1; step >>= 1) {
+        const int cand = j + step;
+        const long long ex = __shfl(excl, cand & 63, 64);
+        if (cand < 64 && ex <= t) j = cand;
+      }
+      const long long pos = __shfl(rb, j, 64) + (t - __shfl(excl, j, 64));
+      bool crossed = false;
+      int32_t ul = 0;
+      if (t < total) {
+        ul = a.adj[pos] - (a.local_ids ? 0 : (int32_t)base);
+        st_edges++;
+        const bool live = pb ? !((pb[ul >> 5] >> (ul & 31)) & 1u) : d[ul] > k;
+        if (live) {
+          const unsigned old = inl ? atomicSub(&d[ul], 1u) : wsub(&d[ul], 1u);
+          st_decr++;
+          crossed = old == k + 1;
+        }
+      }
+      if (crossed) {
+        if (pb) atomicOr(&pb[ul >> 5], 1u << (ul & 31));
+        a.core[base + ul] = (int32_t)k;
+      }
+      const unsigned long long m = __ballot(crossed);
+      if (m) {
+        int b = 0;
+        if (l == 0) b = atomicAdd(s_tail, __popcll(m));
+        b = __shfl(b, 0, 64);
+        if (crossed) lds_st(&q[b + rank_in(m)], ul);
+      }
+    }
+  }
+}
+
 __global__ __launch_bounds__(kBatchThreads) void batched_kernel(BatchArgs a) {
   extern __shared__ uint32_t s_dyn[];
   __shared__ long long s_pref[kBatchThreads];
@@ -1248,6 +1358,7 @@ __global__ __launch_bounds__(kBatchThreads) void batched_kernel(BatchArgs a) {
   __shared__ long long s_w[kBatchThreads / 64 + 1];
   __shared__ unsigned s_min[kBatchThreads / 64];
   __shared__ int s_tail;
+  __shared__ int s_claim, s_busy;
   __shared__ long long s_g;
 
   long long st_edges = 0, st_decr = 0, st_rounds = 0, st_sub = 0, st_scanned = 0;
@@ -1281,6 +1392,8 @@ __global__ __launch_bounds__(kBatchThreads) void batched_kernel(BatchArgs a) {
     }
     if (pb)
       for (long long i = tid; i < (ng + 31) / 32; i += kBatchThreads) pb[i] = 0u;
+    if (a.chained)
+      for (long long i = tid; i < ng; i += kBatchThreads) q[i] = -1;  // unwritten queue entries
     mn = wave_min(mn);
     if (l == 0) s_min[w] = mn;
     if (tid == 0) s_tail = 0;
@@ -1360,7 +1473,21 @@ __global__ __launch_bounds__(kBatchThreads) void batched_kernel(BatchArgs a) {
       }
       st_rounds++;
       if (k > kmax_all) kmax_all = k;
-      // subrounds: frontier = q[head, tail)
+      if (a.chained) {
+        if (tid == 0) {
+          s_claim = head;
+          s_busy = kBatchThreads / 64;
+        }
+        __syncthreads();
+        if (!batch_chain(a, d, q, pb, off, base, inl, k, &s_claim, &s_tail, &s_busy, st_edges, st_decr) &&
+            l == 0)
+          aor(&a.ctl->status, (unsigned)KC_ERR_TIMEOUT);
+        __syncthreads();
+        st_sub++;
+        head = tail = s_tail;
+        __syncthreads();
+      }
+      // level-synchronous subrounds: frontier = q[head, tail)
       while (head < tail) {
         st_sub++;
         for (long long c0 = head; c0 < tail; c0 += kBatchThreads) {

@@ -117,6 +117,7 @@ struct BatchArgs {
   int32_t local_ids;      // adjacency holds per-graph local ids (serving) instead of global ids
   BatchCtl* ctl;
   int32_t lds_cap;        // vertices per graph held in LDS
+  int32_t chained;        // 1: each round is peeled through a dynamic workgroup queue (no subround barriers)
 };
 
 // Error text returned by kcore_last_error (thread-local; defined in kcore_api.cpp).
@@ -130,7 +131,7 @@ int reserve_batched(hipStream_t stream, int64_t V, int32_t G);
 void release_batched(hipStream_t stream);
 int decompose_batched_local(const int64_t* graph_vptr, const int64_t* offsets, const int32_t* adj,
                             int32_t num_graphs, int64_t total_vertices, int32_t* coreness_out,
-                            hipStream_t stream);
+                            hipStream_t stream, unsigned* status_out);
 
 // Launch helpers (defined in kcore_device.hip).
 hipError_t launch_peel(const PeelArgs& a, int blocks, hipStream_t s);

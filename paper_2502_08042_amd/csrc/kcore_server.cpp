@@ -52,6 +52,7 @@ struct Slot {
   int64_t v_cap = 0, e_cap = 0, g_cap = 0, c_cap = 0;      // device buffers (elements)
   int64_t vh_cap = 0, eh_cap = 0, gh_cap = 0, ch_cap = 0;  // pinned staging buffers
   std::vector<void*> retired_dev, retired_host;             // outgrown, freed at destroy
+  unsigned* status_h = nullptr;  // pinned: the batch's device failure bits
   int64_t *vptr_d = nullptr, *off_d = nullptr;
   int32_t *adj_d = nullptr, *core_d = nullptr;
   int64_t *vptr_h = nullptr, *off_h = nullptr;
@@ -242,7 +243,12 @@ int launch_slot(kcore_server* s, Slot* sl) {
       hipMemcpyAsync(sl->off_d, sl->off_h, 8 * (V + 1), hipMemcpyHostToDevice, st) != hipSuccess ||
       (!direct && E > 0 && hipMemcpyAsync(sl->adj_d, sl->adj_h, 4 * E, hipMemcpyHostToDevice, st) != hipSuccess))
     return KCORE_EDEVICE;
-  int rc = kc::decompose_batched_local(sl->vptr_d, sl->off_d, sl->adj_d, (int32_t)G, V, sl->core_d, st);
+  if (!sl->status_h &&
+      hipHostMalloc((void**)&sl->status_h, sizeof(unsigned), hipHostMallocDefault) != hipSuccess)
+    return KCORE_ENOMEM;
+  *sl->status_h = 0u;
+  int rc = kc::decompose_batched_local(sl->vptr_d, sl->off_d, sl->adj_d, (int32_t)G, V, sl->core_d, st,
+                                       sl->status_h);
   if (rc) return rc;
   if (hipMemcpyAsync(sl->core_h, sl->core_d, 4 * V, hipMemcpyDeviceToHost, st) != hipSuccess)
     return KCORE_EDEVICE;
@@ -262,6 +268,7 @@ int launch_slot(kcore_server* s, Slot* sl) {
 void finish_slot(kcore_server* s, Slot* sl) {
   // called with s->mu held
   const double t = s->now_us();
+  if (sl->rc == 0 && sl->status_h && *sl->status_h != 0u) sl->rc = KCORE_EDEVICE;
   int64_t vb = 0;
   for (Request* r : sl->reqs) {
     if (sl->rc == 0) {
@@ -282,6 +289,7 @@ void finish_slot(kcore_server* s, Slot* sl) {
   sl->bytes = 0;
   sl->reqs.clear();
   sl->busy = false;
+  sl->rc = 0;
   sl->finished.store(0);
 }
 
@@ -562,6 +570,7 @@ void kcore_server_destroy(kcore_server* s) {
     hipHostFree(sl->adj_h);
     hipHostFree(sl->core_h);
     for (void* p : sl->retired_dev) hipFree(p);
+    if (sl->status_h) hipHostFree(sl->status_h);
     for (void* p : sl->retired_host) hipHostFree(p);
     kc::release_batched(sl->stream);
     hipStreamDestroy(sl->stream);

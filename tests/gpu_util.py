@@ -32,11 +32,11 @@ def run_single(off, adj, mode="auto", stats=True, **kw):
     return r.cpu().numpy(), None
 
 
-def run_batched(off, adj, vptr, stats=True):
+def run_batched(off, adj, vptr, stats=True, mode="auto"):
     import torch
     import paper_2502_08042_amd as K
     d_off, d_adj, d_vptr = to_dev(off, adj, vptr)
-    r = K.decompose_batched(d_vptr, d_off, d_adj, stats=stats)
+    r = K.decompose_batched(d_vptr, d_off, d_adj, stats=stats, mode=mode)
     torch.cuda.synchronize()
     if stats:
         core, st = r

@@ -137,33 +137,38 @@ def test_residual_rows_do_not_change_results(mode):
                 assert st["peeled"] == len(off) - 1 and st["device_status"] == 0
 
 
-def test_batched_small():
+@pytest.mark.parametrize("mode", MODES)
+def test_batched_small(mode):
     b = gg.batch(64, 4, hi=20000)
-    say(f"[gpu] batched 64 graphs V={b.n} m={b.m}")
-    got, st = run_batched(b.offsets, b.adj, b.vptr)
+    say(f"[gpu] batched 64 graphs V={b.n} m={b.m} mode={mode}")
+    got, st = run_batched(b.offsets, b.adj, b.vptr, mode=mode)
     want = oracle.bz(b.offsets, b.adj)
     assert not first_mismatch(got, want), first_mismatch(got, want)
     assert st["edges"] == b.m
 
 
-def test_batched_equals_per_graph_and_handles_empty_graphs():
+@pytest.mark.parametrize("mode", MODES)
+def test_batched_equals_per_graph_and_handles_empty_graphs(mode):
     parts = [G.complete(9), G.csr(0, []), G.csr(5, []), G.hcns(30), G.grid(12), G.csr(1, [])]
     off, adj = G.union(parts)
     vptr = np.cumsum([0] + [len(p[0]) - 1 for p in parts]).astype(np.int64)
-    say(f"[gpu] batched with empty graphs V={len(off) - 1}")
-    got, _ = run_batched(off, adj, vptr)
+    say(f"[gpu] batched with empty graphs V={len(off) - 1} mode={mode}")
+    got, _ = run_batched(off, adj, vptr, mode=mode)
     want = np.concatenate([oracle.bz(*p) for p in parts])
     assert not first_mismatch(got, want), first_mismatch(got, want)
 
 
-def test_batched_large_graph_in_global_memory():
-    # graphs above the LDS capacity keep their state in the global workspace
-    parts = [(gg.rmat(15, 8, 3).offsets, gg.rmat(15, 8, 3).adj), G.complete(40),
-             (gg.grid_road(200, 0.05, 0.01, 9).offsets, gg.grid_road(200, 0.05, 0.01, 9).adj)]
+@pytest.mark.parametrize("mode", MODES)
+def test_batched_large_graph_in_global_memory(mode):
+    # graphs above the LDS capacity keep their state in the global workspace, with a peeled bitmap
+    # in LDS up to 393,216 vertices and without one above (R-MAT scale 19)
+    r15, r19 = gg.rmat(15, 8, 3), gg.rmat(19, 4, 12)
+    road = gg.grid_road(200, 0.05, 0.01, 9)
+    parts = [(r15.offsets, r15.adj), G.complete(40), (road.offsets, road.adj), (r19.offsets, r19.adj)]
     off, adj = G.union(parts)
     vptr = np.cumsum([0] + [len(p[0]) - 1 for p in parts]).astype(np.int64)
-    say(f"[gpu] batched large graphs V={len(off) - 1} m={len(adj)}")
-    got, _ = run_batched(off, adj, vptr)
+    say(f"[gpu] batched large graphs V={len(off) - 1} m={len(adj)} mode={mode}")
+    got, _ = run_batched(off, adj, vptr, mode=mode)
     want = oracle.bz(off, adj)
     assert not first_mismatch(got, want), first_mismatch(got, want)
 
