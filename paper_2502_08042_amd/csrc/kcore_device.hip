@@ -4,11 +4,15 @@
 //  * peel_kernel — one persistent, co-resident grid peels a single graph following the paper's
 //    framework (Alg. 1) with the online peel (Alg. 3). Phases are separated by a fence-free grid
 //    barrier; a phase either scans the active set (extracting the round's first frontier and
-//    refining the set, Alg. 1 extract/refine) or expands the current frontier. Cross-workgroup data
-//    (frontiers, active lists, counters) goes through agent-scope relaxed atomics, which the MI355X
-//    keeps coherent across its XCD L2 caches, so barriers need no L2 write-back or invalidate.
-//  * batched_kernel — many independent graphs, one workgroup per graph with its induced degrees and
-//    peel queue in LDS, so a graph's rounds and subrounds synchronise at workgroup level only.
+//    refining the set, Alg. 1 extract/refine), expands the current frontier, or (once) rewrites the
+//    live rows without peeled neighbours. In chained mode (VGC, Sec. 4.2) a wavefront peels what it
+//    pushes through a local queue and a workgroup peels the small hubs it pushes through an LDS tile
+//    queue, inside the same phase. Cross-workgroup data (frontiers, active lists, counters) goes
+//    through agent-scope relaxed atomics, which the MI355X keeps coherent across its XCD L2
+//    caches, so barriers need no L2 write-back or invalidate.
+//  * batched_kernel — many independent graphs, one workgroup per graph, with its induced degrees
+//    and peel queue in LDS (or, for graphs beyond the LDS, in global memory with a peeled bitmap in
+//    LDS), so a graph's rounds and subrounds synchronise at workgroup level only.
 #include "kcore_internal.h"
 
 namespace kc {
