@@ -7,7 +7,7 @@ directed edges per second (GTEPS: adjacency entries m divided by the time of one
 graph resident in HBM), the roofline position of the peel kernel and the CPU oracle's rate on the
 same graph.
 
-    python bench.py [--steps K] [--warmup W] [--workload chunglu|grid|rmat16|batch|serve]
+    python bench.py [--steps K] [--warmup W] [--workload chunglu|grid|rmat16|batch|serve|kquery]
 
 Prints exactly one JSON line. One GPU only: --gpus N with N > 1 exits with a message.
 """
@@ -327,6 +327,45 @@ def bench_serve(args, seconds: float = 5.0, rate: float = 20000.0, warm: float =
     }
 
 
+def bench_kquery(args, k: int = 1000):
+    """Maximum k-core subgraph (one peeling round at k - 1) of the Chung-Lu graph; membership checked
+    against the oracle's coreness."""
+    import numpy as np
+    import torch
+    import oracle
+    import paper_2502_08042_amd as K
+    off, adj, desc = build_workload("chunglu")
+    torch.cuda.synchronize()
+    n, m = off.numel() - 1, adj.numel()
+    out = torch.empty(n, dtype=torch.int32, device=off.device)
+    for _ in range(args.warmup):
+        K.kcore_subgraph(off, adj, k, out)
+    _, st = K.kcore_subgraph(off, adj, k, out, stats=True)
+    stream = torch.cuda.current_stream()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for e0, e1 in evs:
+        e0.record(stream)
+        K.kcore_subgraph(off, adj, k, out)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - t1) * 1000.0 / args.steps
+    kern_ms = sum(e0.elapsed_time(e1) for e0, e1 in evs) / args.steps
+    got = out.cpu().numpy()
+    want = (oracle.bz(off.cpu().numpy(), adj.cpu().numpy()) >= k).astype(np.int32)
+    return {
+        "metric": METRIC, "value": round(m / (ms_step / 1000.0) / 1e9, 4), "unit": "GTEPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "strong", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": f"maximum {k}-core subgraph of: {desc}", "n": n, "m": m, "k": k,
+                   "core_size": int(got.sum()), "peeled": int(n - got.sum())},
+        "kernel_ms_per_launch": round(kern_ms, 4), "parity": bool(np.array_equal(got, want)),
+    }
+
+
 def kernel_sha() -> str:
     import hashlib
     h = hashlib.sha1()
@@ -340,7 +379,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="chunglu", choices=["chunglu", "grid", "rmat16", "batch", "serve"])
+    ap.add_argument("--workload", default="chunglu", choices=["chunglu", "grid", "rmat16", "batch", "serve", "kquery"])
     ap.add_argument("--mode", default="auto", choices=["auto", "levelsync", "chained"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -364,6 +403,8 @@ def main():
         res = bench_batch(args)
     elif args.workload == "serve":
         res = bench_serve(args)
+    elif args.workload == "kquery":
+        res = bench_kquery(args)
     else:
         res = bench_single(args)
     print(json.dumps(res), flush=True)

@@ -126,6 +126,16 @@ int kcore_decompose(const int64_t* offsets, const int32_t* adj, int64_t n, int32
 int kcore_decompose_ex(const int64_t* offsets, const int32_t* adj, int64_t n, int32_t* coreness_out,
                        hipStream_t stream, const kcore_options* opt, kcore_stats* stats_host);
 
+/* Maximum k-core subgraph (App. B): the framework with its peeling condition fixed at "induced
+ * degree below k", i.e. one round at threshold k - 1 with the same (chained) subrounds, after which
+ * the survivors form the k-core (the largest subgraph of minimum degree >= k).
+ *   in_core_out  int32[n] on the device: 1 if v belongs to the k-core, else 0
+ * k <= 0 marks every vertex. Arguments, options, statistics (rounds <= 1) and errors as
+ * kcore_decompose_ex. */
+int kcore_kcore_subgraph(const int64_t* offsets, const int32_t* adj, int64_t n, int32_t k,
+                         int32_t* in_core_out, hipStream_t stream, const kcore_options* opt,
+                         kcore_stats* stats_host);
+
 /* Many independent graphs in one segmented CSR (device pointers). Graph g owns the global vertex
  * range [graph_vptr[g], graph_vptr[g+1]); its rows use global ids inside that range. The k-cores
  * of a disjoint union are the unions of the k-cores of its parts, so every graph is peeled on its

@@ -88,6 +88,8 @@ P, I32, I64, U64P = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.POIN
 SIGNATURES = {
     "kcore_decompose": (ctypes.c_int, [P, P, I64, P, P]),
     "kcore_decompose_ex": (ctypes.c_int, [P, P, I64, P, P, ctypes.POINTER(Options), ctypes.POINTER(Stats)]),
+    "kcore_kcore_subgraph": (ctypes.c_int, [P, P, I64, I32, P, P, ctypes.POINTER(Options),
+                                            ctypes.POINTER(Stats)]),
     "kcore_decompose_batched": (ctypes.c_int, [P, P, P, I32, I64, P, P]),
     "kcore_decompose_batched_ex": (ctypes.c_int, [P, P, P, I32, I64, P, P, ctypes.POINTER(Options),
                                                   ctypes.POINTER(Stats)]),
@@ -191,6 +193,27 @@ def decompose(offsets, adj, out=None, *, mode="auto", stats=False, validate=Fals
                                  out.data_ptr() if n else None, _stream_ptr(stream),
                                  ctypes.byref(opt), ctypes.byref(st) if st is not None else None)
     _check(rc, "kcore_decompose_ex")
+    return (out, st.as_dict()) if stats else out
+
+
+def kcore_subgraph(offsets, adj, k, out=None, *, mode="auto", stats=False, validate=False, stream=None,
+                   **tuning):
+    """Membership of the maximum k-core subgraph: int32 tensor, 1 for vertices of the k-core."""
+    import torch
+    _dev_tensor(offsets, torch.int64, "offsets")
+    _dev_tensor(adj, torch.int32, "adj")
+    n = offsets.numel() - 1
+    if out is None:
+        out = torch.empty(max(n, 0), dtype=torch.int32, device=offsets.device)
+    _dev_tensor(out, torch.int32, "out")
+    if out.numel() < n:
+        raise ValueError("out is too small")
+    opt = _options(mode, validate, adj.numel(), **tuning)
+    st = Stats() if stats else None
+    rc = _lib.kcore_kcore_subgraph(offsets.data_ptr(), adj.data_ptr() if adj.numel() else None, n, int(k),
+                                   out.data_ptr() if n else None, _stream_ptr(stream), ctypes.byref(opt),
+                                   ctypes.byref(st) if st is not None else None)
+    _check(rc, "kcore_kcore_subgraph")
     return (out, st.as_dict()) if stats else out
 
 

@@ -269,8 +269,10 @@ int kcore_version(void) { return 10000; }
 
 const char* kcore_last_error(void) { return g_err.c_str(); }
 
-int kcore_decompose_ex(const int64_t* offsets, const int32_t* adj, int64_t n, int32_t* coreness_out,
-                       hipStream_t stream, const kcore_options* opt, kcore_stats* stats_host) {
+// Single graph: the full decomposition (k_query < 0), or the k-core membership for k = k_query >= 1
+// (one peeling round at threshold k - 1; out[v] = 1 for the survivors, 0 otherwise).
+static int peel_impl(const int64_t* offsets, const int32_t* adj, int64_t n, int32_t* coreness_out,
+                     hipStream_t stream, const kcore_options* opt, kcore_stats* stats_host, int64_t k_query) {
   g_err.clear();
   if (n < 0) return fail(KCORE_EINVAL, "n = %lld is negative", (long long)n);
   if (n > 0x7fffffffLL) return fail(KCORE_EINVAL, "n = %lld exceeds the int32 id range", (long long)n);
@@ -363,6 +365,7 @@ int kcore_decompose_ex(const int64_t* offsets, const int32_t* adj, int64_t n, in
   a.bq_max_tiles = bt < 0 ? 0 : (bt ? bt : 32);
   a.bq_backlog = (opt && opt->block_queue) ? opt->block_queue : 64;
   a.tile_probe_always = !(opt && opt->tile_probe < 0);
+  a.k_query = k_query;
   a.rrow = w->rrow;
   a.radj = w->radj;
   a.rcap = rcap;
@@ -429,6 +432,29 @@ int kcore_debug_blocks(hipStream_t stream, unsigned long long* out) {
   HIP_TRY(hipStreamSynchronize(stream));
   HIP_TRY(hipMemcpy(out, w->ctl->dbg, sizeof(w->ctl->dbg), hipMemcpyDeviceToHost));
   return KCORE_OK;
+}
+
+int kcore_decompose_ex(const int64_t* offsets, const int32_t* adj, int64_t n, int32_t* coreness_out,
+                       hipStream_t stream, const kcore_options* opt, kcore_stats* stats_host) {
+  return peel_impl(offsets, adj, n, coreness_out, stream, opt, stats_host, -1);
+}
+
+int kcore_kcore_subgraph(const int64_t* offsets, const int32_t* adj, int64_t n, int32_t k, int32_t* in_core_out,
+                         hipStream_t stream, const kcore_options* opt, kcore_stats* stats_host) {
+  if (k <= 0 && n > 0) {
+    // every vertex belongs to the 0-core
+    g_err.clear();
+    if (n > 0x7fffffffLL) return fail(KCORE_EINVAL, "n = %lld exceeds the int32 id range", (long long)n);
+    if (int rc = check_opts(opt)) return rc;
+    if (!in_core_out) return fail(KCORE_EINVAL, "null pointer argument");
+    HIP_TRY(kc::launch_fill_u32(in_core_out, 1u, (size_t)n, stream));
+    if (stats_host) {
+      HIP_TRY(hipStreamSynchronize(stream));
+      memset(stats_host, 0, sizeof *stats_host);
+    }
+    return KCORE_OK;
+  }
+  return peel_impl(offsets, adj, n, in_core_out, stream, opt, stats_host, k);
 }
 
 int kcore_decompose(const int64_t* offsets, const int32_t* adj, int64_t n, int32_t* coreness_out,

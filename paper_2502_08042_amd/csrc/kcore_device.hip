@@ -416,7 +416,7 @@ __device__ __forceinline__ void edges_batch(const PeelArgs& a, WaveCtx& c, const
         __hip_atomic_fetch_or(&a.state[u[j] >> 4], bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
       if (crossed) {
-        a.core[u[j]] = (int32_t)k;
+        if (a.k_query <= 0) a.core[u[j]] = (int32_t)k;
         c.peeled += 1;
       }
     }
@@ -514,7 +514,7 @@ __device__ __forceinline__ void comb_flush(const PeelArgs& a, WaveCtx& c, const 
         if (!(aor(&a.state[u >> 4], bit) & bit)) {
           crossed = true;
           hub = (old & HUBBIT) != 0u;
-          a.core[u] = (int32_t)k;
+          if (a.k_query <= 0) a.core[u] = (int32_t)k;
           c.peeled += 1;
         }
       }
@@ -781,7 +781,8 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
 
   if (threadIdx.x == 0) s_out[0] = (long long)ald(&C->slot[0].minv);
   __syncthreads();
-  long long kx = s_out[0];     // round being extracted or expanded
+  // round being extracted or expanded; a k-core query runs the single round k - 1
+  long long kx = a.k_query > 0 ? a.k_query - 1 : s_out[0];
   __syncthreads();
   int kind = PH_SCAN;
   bool dense = true, compact = false;
@@ -1001,7 +1002,7 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
           if (aor(&a.state[v >> 4], bit) & bit) {
             ext = false;  // already peeled in this round by a chain (chained mode)
           } else {
-            a.core[v] = (int32_t)k;
+            if (a.k_query <= 0) a.core[v] = (int32_t)k;
             c.peeled += 1;
           }
         }
@@ -1163,8 +1164,16 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
         compact = removed_since * 8 >= asize;
       }
     }
+    // a k-core query ends with its one round: the survivors are the k-core
+    if (a.k_query > 0 && kind == PH_SCAN) break;
     // at a round boundary with a small active set whose live rows fit: rewrite the rows once
     if (kind == PH_SCAN && resid_limit >= 0 && asize <= resid_limit) kind = PH_RESIDUAL;
+  }
+  if (a.k_query > 0) {
+    // membership: every workgroup left the loop after the same barrier, so the peeled bits are final.
+    // This is the only write of the output in a query (no coreness is written while peeling): plain
+    // stores to one address from workgroups on different XCDs have no defined order.
+    for (long long v = gt; v < n; v += GT) a.core[v] = ((ald(&a.state[v >> 4]) >> (v & 15)) & 1u) ? 0 : 1;
   }
 
   // ---- statistics: per-lane counters reduced per block, one atomic each per block

@@ -95,6 +95,7 @@ struct PeelArgs {
   int32_t* radj;          // residual adjacency (live neighbours only), rcap entries
   int64_t rcap;
   int64_t resid_vmax;     // rewrite the rows once the active set is at most this large (-1 = never)
+  int64_t k_query;        // >= 1: only the k_query-core (one round at k_query - 1, membership out)
 };
 
 struct BatchCtl {

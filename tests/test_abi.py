@@ -67,6 +67,9 @@ def test_argument_errors_without_device_work():
     o = K.Options()
     o.reserved[0] = 1
     assert lib.kcore_decompose_ex(one.ctypes.data, None, 0, None, None, ctypes.byref(o), None) == -1
+    # k-core query: same argument checks
+    assert lib.kcore_kcore_subgraph(one.ctypes.data, None, -1, 3, None, None, None, None) == -1
+    assert lib.kcore_kcore_subgraph(None, None, 0, 3, None, None, None, None) == 0
     # batched: negative sizes, empty batch
     assert lib.kcore_decompose_batched(None, None, None, -1, 0, None, None) == -1
     assert lib.kcore_decompose_batched(None, None, None, 0, 0, None, None) == 0

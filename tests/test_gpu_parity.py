@@ -138,6 +138,29 @@ def test_residual_rows_do_not_change_results(mode):
 
 
 @pytest.mark.parametrize("mode", MODES)
+def test_kcore_subgraph_query(mode):
+    """Maximum k-core subgraph (App. B): membership equals coreness >= k from the oracle, for k
+    below, at and above the largest coreness, on graphs with hubs, chains and a dense core."""
+    import paper_2502_08042_amd as K
+    import torch
+    from gpu_util import to_dev
+    cases = [("rmat13", gg.rmat(13, 16, 7)), ("road256", gg.grid_road(256, 0.05, 0.01, 3)),
+             ("hcns60", None)]
+    for name, g in cases:
+        off, adj = (g.offsets, g.adj) if g is not None else G.hcns(60)
+        core = oracle.bz(off, adj)
+        d_off, d_adj = to_dev(off, adj)
+        kmax = int(core.max())
+        for k in sorted({0, 1, 2, 3, max(kmax // 2, 1), kmax, kmax + 1}):
+            say(f"[gpu] k-core query {name} mode={mode} k={k}")
+            got, st = K.kcore_subgraph(d_off, d_adj, k, mode=mode, stats=True)
+            torch.cuda.synchronize()
+            want = (core >= k).astype(np.int32)
+            assert np.array_equal(got.cpu().numpy(), want), (name, k)
+            assert st["device_status"] == 0 and st["rounds"] <= 1
+
+
+@pytest.mark.parametrize("mode", MODES)
 def test_batched_small(mode):
     b = gg.batch(64, 4, hi=20000)
     say(f"[gpu] batched 64 graphs V={b.n} m={b.m} mode={mode}")
