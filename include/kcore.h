@@ -194,6 +194,10 @@ typedef struct {
                                   so that serving rarely stops to allocate or pin memory (buffers
                                   a slot outgrows are kept until kcore_server_destroy) */
   int64_t reserve_entries;
+  uint64_t fail_ticket;        /* testing: the launch of any batch holding this ticket fails with
+                                  KCORE_EDEVICE before it touches the device (0 = none); as with a
+                                  real launch failure, the batch's requests are retried one per
+                                  batch, so only the failing request ends in an error */
 } kcore_server_config;
 
 typedef struct {

@@ -70,7 +70,8 @@ class ServerConfig(ctypes.Structure):
                 ("max_batch_vertices", ctypes.c_int64), ("hbm_budget_bytes", ctypes.c_int64),
                 ("max_request_vertices", ctypes.c_int64), ("batch_wait_us", ctypes.c_double),
                 ("borrow_inputs", ctypes.c_int32), ("reserved1", ctypes.c_int32),
-                ("reserve_vertices", ctypes.c_int64), ("reserve_entries", ctypes.c_int64)]
+                ("reserve_vertices", ctypes.c_int64), ("reserve_entries", ctypes.c_int64),
+                ("fail_ticket", ctypes.c_uint64)]
 
 
 class RequestStats(ctypes.Structure):
@@ -253,7 +254,8 @@ class Server:
     def __init__(self, device: int = 0, max_inflight: int = 0, max_batch_graphs: int = 0,
                  max_batch_vertices: int = 0, hbm_budget_bytes: int = 0,
                  max_request_vertices: int = 0, batch_wait_us: float = 0.0,
-                 borrow_inputs: bool = False, reserve_vertices: int = 0, reserve_entries: int = 0):
+                 borrow_inputs: bool = False, reserve_vertices: int = 0, reserve_entries: int = 0,
+                 fail_ticket: int = 0):
         cfg = ServerConfig()
         cfg.device = device
         cfg.max_inflight = max_inflight
@@ -265,6 +267,7 @@ class Server:
         cfg.borrow_inputs = 1 if borrow_inputs else 0
         cfg.reserve_vertices = reserve_vertices
         cfg.reserve_entries = reserve_entries
+        cfg.fail_ticket = fail_ticket
         self._h = _lib.kcore_server_create(ctypes.byref(cfg))
         if not self._h:
             raise KcoreError(-1, "kcore_server_create", last_error())

@@ -40,6 +40,7 @@ struct Request {
   const int32_t* adjp = nullptr;
   std::vector<int32_t> core;
   int state = RQ_QUEUED;
+  bool solo = false;  // retried alone after its batch failed to launch
   int err = 0;
   int64_t bytes = 0;
   kcore_request_stats st{};
@@ -181,6 +182,9 @@ int launch_slot(kcore_server* s, Slot* sl) {
   // Borrowed large requests are copied to the device straight from the caller's arrays (one DMA
   // each); everything else is packed into the slot's pinned buffer and copied in one piece.
   const bool direct = s->cfg.borrow_inputs && sl->large;
+  if (s->cfg.fail_ticket)
+    for (const Request* r : sl->reqs)
+      if (r->ticket == s->cfg.fail_ticket) return KCORE_EDEVICE;  // injected launch failure
   const double t_start = s->now_us();
   if (int rc = grow(sl, V, E, G, !direct)) return rc;
   const double t_grown = s->now_us();
@@ -339,6 +343,7 @@ void dispatcher(kcore_server* s) {
           continue;
         }
         if ((int64_t)take.size() >= s->cfg.max_batch_graphs) break;
+        if (!take.empty() && (r->solo || take.front()->solo)) break;
         if (!take.empty() && V + r->n > s->cfg.max_batch_vertices) break;
         if (s->bytes_in_use + bytes + r->bytes > s->cfg.hbm_budget_bytes) break;
         it = s->queue.erase(it);
@@ -366,11 +371,24 @@ void dispatcher(kcore_server* s) {
         lk.lock();
         for (Request* r : take) r->st.launch_us = tl;
         if (rc) {
-          // the failure belongs to this batch only
-          free_slot->rc = rc;
-          finish_slot(s, free_slot);
-          free_slot->rc = 0;
-          s->done_cv.notify_all();
+          // the failure belongs to this batch only. A batch of several requests is retried one
+          // request per batch, at the head of the queue, so that only a failing request fails.
+          if (free_slot->reqs.size() > 1) {
+            for (auto it = free_slot->reqs.rbegin(); it != free_slot->reqs.rend(); ++it) {
+              Request* r = *it;
+              r->state = RQ_QUEUED;
+              r->solo = true;
+              s->queue.push_front(r);
+            }
+            s->bytes_in_use -= free_slot->bytes;
+            free_slot->bytes = 0;
+            free_slot->reqs.clear();
+            free_slot->busy = false;
+          } else {
+            free_slot->rc = rc;
+            finish_slot(s, free_slot);
+            s->done_cv.notify_all();
+          }
         }
         continue;
       }

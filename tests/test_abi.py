@@ -40,7 +40,7 @@ def test_struct_layouts_match_header_sizes():
     # sizes implied by the header's field lists (natural alignment on x86-64)
     assert ctypes.sizeof(K.Options) == 64
     assert ctypes.sizeof(K.Stats) == 8 * 8 + 4 * 3 + 4 * 5
-    assert ctypes.sizeof(K.ServerConfig) == 16 + 8 * 3 + 8 + 8 + 16
+    assert ctypes.sizeof(K.ServerConfig) == 16 + 8 * 3 + 8 + 8 + 16 + 8
     assert ctypes.sizeof(K.RequestStats) == 8 * 4 + 8 + 8
 
 

@@ -121,3 +121,22 @@ def test_serving_poll_protocol_and_cancel():
             assert e.value.code == -6
         else:
             s.wait(ts[-1])
+
+
+def test_serving_injected_launch_failure_fails_only_its_request():
+    """A launch failure forced on one ticket (before any device work) fails that request alone: its
+    batch is retried one request per batch, and every other request completes exactly."""
+    import paper_2502_08042_amd as K
+    graphs = _pool()[:16]
+    want = [oracle.bz(g.offsets, g.adj) for g in graphs]
+    say("[gpu] serving: injected launch failure on ticket 5")
+    with K.Server(device=0, max_inflight=2, fail_ticket=5) as s:
+        ts = [s.submit(g.offsets, g.adj) for g in graphs]
+        assert ts[4] == 5
+        for i, (t, w) in enumerate(zip(ts, want)):
+            if t == 5:
+                with pytest.raises(K.KcoreError) as e:
+                    s.wait(t)
+                assert e.value.code == -3
+            else:
+                assert np.array_equal(s.wait(t), w), f"request {i}"
