@@ -126,8 +126,10 @@ int peel_ws(int dev, hipStream_t s, int64_t n, int64_t tcap, int64_t rcap, PeelW
     size_t off = 0;
     const size_t o_dt = off; off = align_up(off + 4 * (size_t)nc);
     const size_t o_st = off; off = align_up(off + 4 * nw);
-    const size_t o_a0 = off; off = align_up(off + 4 * (size_t)nc);
-    const size_t o_a1 = off; off = align_up(off + 4 * (size_t)nc);
+    // active lists are written in per-workgroup segments: room for one 64-entry round-up each
+    const size_t na = (size_t)nc + 64 * (size_t)kc::kMaxPeelBlocks;
+    const size_t o_a0 = off; off = align_up(off + 4 * na);
+    const size_t o_a1 = off; off = align_up(off + 4 * na);
     const size_t o_f0 = off; off = align_up(off + 4 * (size_t)nc);
     const size_t o_f1 = off; off = align_up(off + 4 * (size_t)nc);
     const size_t o_t0 = off; off = align_up(off + 8 * (size_t)tc);
@@ -329,6 +331,7 @@ static int peel_impl(const int64_t* offsets, const int32_t* adj, int64_t n, int3
   // no more workgroups than there are vertex packets to keep barriers cheap on small graphs
   const int64_t want = (n + 64 * kc::kWaves - 1) / (64 * kc::kWaves);
   if (want < blocks) blocks = (int)std::max<int64_t>(want, 1);
+  if (blocks > kc::kMaxPeelBlocks) blocks = kc::kMaxPeelBlocks;
 
   kc::PeelArgs a;
   a.off = offsets;

@@ -176,6 +176,39 @@ __device__ __forceinline__ void block_flush(Stage& s, unsigned long long* tail, 
   __syncthreads();
 }
 
+// Active lists are compacted into one segment per workgroup: a workgroup appends the survivors it
+// scanned to its own segment with an LDS counter, so compaction needs no global atomic (a single
+// shared tail counter would serialise one atomic per wave flush). Item j of a segmented list is the
+// (j - pref[b])-th entry of segment b, where pref holds the exclusive prefix of the segment counts.
+__device__ __forceinline__ void seg_flush(Stage& s, int32_t* seg, int* s_used) {
+  if (s.cnt == 0) return;
+  int base = 0;
+  if (lane_id() == 0) base = atomicAdd(s_used, s.cnt);
+  base = __shfl(base, 0, 64);
+  for (int i = lane_id(); i < s.cnt; i += 64) ast(&seg[base + i], s.buf[i]);
+  s.cnt = 0;
+}
+
+__device__ __forceinline__ void seg_push(Stage& s, bool p, int32_t v, int32_t* seg, int* s_used) {
+  const unsigned long long m = __ballot(p);
+  if (m == 0) return;
+  const int c = __popcll(m);
+  if (s.cnt + c > kStage) seg_flush(s, seg, s_used);
+  if (p) s.buf[s.cnt + rank_in(m)] = v;
+  s.cnt += c;
+}
+
+__device__ __forceinline__ int32_t active_item(const int32_t* alist, bool dense, long long j, long long aseg,
+                                               const int* pref, int nb) {
+  if (dense) return (int32_t)j;
+  int lo = 0, hi = nb - 1;  // last segment with pref[b] <= j
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if ((long long)pref[mid] <= j) lo = mid; else hi = mid - 1;
+  }
+  return ald(&alist[(long long)lo * aseg + (j - pref[lo])]);
+}
+
 // ------------------------------------------------------------------------------------------
 // Single-graph peel.
 // ------------------------------------------------------------------------------------------
@@ -706,6 +739,8 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
   __shared__ uint32_t s_ccnt[kCombSlots];
   __shared__ unsigned long long s_bq[kBlockQ];
   __shared__ int s_bqc[8];
+  __shared__ int s_apref[kMaxPeelBlocks + 1];  // segment prefix of the current active list
+  __shared__ int s_anew;                        // survivors this workgroup appended in this phase
 
   const int w = threadIdx.x >> 6;
   const int l = lane_id();
@@ -738,6 +773,7 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
   c.bq = s_bq;
   c.bqc = s_bqc;
   c.bq_open = false;
+  if (threadIdx.x == 0) s_anew = 0;
   c.adj = a.adj;
   c.rows = reinterpret_cast<const long long*>(a.off);
   c.rstride = 1;
@@ -786,8 +822,10 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
   __syncthreads();
   int kind = PH_SCAN;
   bool dense = true, compact = false;
-  long long asize = n;
+  long long asize = n;   // items of the current active list
+  long long aseg = 0;    // its segment length (segmented lists)
   int acur = 0;
+  const int nb = (int)gridDim.x;
   long long removed_since = 0, total_peeled = 0;
   long long fs = 0, ft = 0;
   // the rows are rewritten once the active set is at most this large (-1: done, or never); a
@@ -834,7 +872,7 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
       for (long long i0 = gw * 64; i0 < asize; i0 += W * 64) {
         const long long i = i0 + l;
         int32_t v = -1;
-        if (i < asize) v = dense ? (int32_t)i : ald(&alist[i]);
+        if (i < asize) v = active_item(alist, dense, i, aseg, s_apref, nb);
         bool live = false;
         long long len = 0, ob = 0, od = 0, nt = 0;
         if (v >= 0) {
@@ -976,12 +1014,15 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
     if (kind == PH_SCAN) {
       // Alg. 1: F = {v in A : induced degree <= k}; survivors refine A.
       int32_t* alist = a.act[acur];
-      int32_t* anext = a.act[acur ^ 1];
+      // this workgroup's segment of the next list: at most the items it scans (64-entry chunks
+      // dealt round-robin over workgroups)
+      const long long nseg = 64 * (((asize + 63) / 64 + nb - 1) / nb);
+      int32_t* myseg = a.act[acur ^ 1] + (long long)blockIdx.x * nseg;
       for (long long i0 = gw * 64; i0 < asize; i0 += W * 64) {
         const long long i = i0 + l;
         const bool valid = i < asize;
         int32_t v = -1;
-        if (valid) v = dense ? (int32_t)i : ald(&alist[i]);
+        if (valid) v = active_item(alist, dense, i, aseg, s_apref, nb);
         uint32_t word = 0, x = 0;
         bool alive = false;
         if (valid) {
@@ -996,7 +1037,7 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
         bool ext = alive && (long long)x <= kx;
         const bool keep = alive && (long long)x > kx;
         if (keep) c.mymin = min(c.mymin, x);
-        if (compact) stage_push(c.sa, keep, v, &o.slot->active, anext, n, &C->status);
+        if (compact) seg_push(c.sa, keep, v, myseg, &s_anew);
         if (ext) {
           const uint32_t bit = 1u << (v & 15);
           if (aor(&a.state[v >> 4], bit) & bit) {
@@ -1055,8 +1096,16 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
 
     // ---- phase end: block-level flushes and reductions
     block_flush(c.sf, &o.slot->small, o.fr, a.fcap, &C->status, s_cnt, &s_base);
-    if (kind == PH_SCAN && compact)
-      block_flush(c.sa, &o.slot->active, a.act[acur ^ 1], n, &C->status, s_cnt, &s_base);
+    if (kind == PH_SCAN && compact) {
+      const long long nseg = 64 * (((asize + 63) / 64 + nb - 1) / nb);
+      seg_flush(c.sa, a.act[acur ^ 1] + (long long)blockIdx.x * nseg, &s_anew);
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        ast(&C->acnt[acur ^ 1][blockIdx.x], (unsigned)s_anew);
+        if (s_anew) aadd(&o.slot->active, (unsigned long long)s_anew);
+        s_anew = 0;
+      }
+    }
     {
       const unsigned mn = wave_min(c.mymin);
       long long pc = c.peeled - peeled_before;
@@ -1119,10 +1168,29 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
     const bool go_async = a.chained && nfs <= a.async_small && nft <= a.async_tiles;
     if (npeel > 0) kmax_seen = k;
     if (kind == PH_SCAN && compact) {
+      aseg = 64 * (((asize + 63) / 64 + nb - 1) / nb);
       asize = nact;
       acur ^= 1;
       dense = false;
       removed_since = npeel;
+      // segment prefix of the new list (every workgroup computes the same one)
+      const int b = threadIdx.x;
+      const long long cnt = b < nb ? (long long)ald(&C->acnt[acur][b]) : 0;
+      const long long incl = wave_incl_scan(cnt);
+      if (l == 63) s_red64[w] = incl;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        long long t = 0;
+        for (int i = 0; i < kWaves; ++i) {
+          const long long x = s_red64[i];
+          s_red64[i] = t;
+          t += x;
+        }
+      }
+      __syncthreads();
+      if (b < nb) s_apref[b] = (int)(s_red64[w] + incl - cnt);
+      if (b == nb - 1) s_apref[nb] = (int)(s_red64[w] + incl);
+      __syncthreads();
     }
     if (kind == PH_SCAN) {
       if (npeel > 0) st_rounds++;

@@ -14,6 +14,8 @@ constexpr int kCombSlots = 1 << kCombBits;  // per-workgroup LDS combining table
 constexpr int kCombProbe = 4;               // linear-probe window of that table
 constexpr int kEdgeUnroll = 2;              // adjacency entries in flight per lane (rows)
 constexpr int kTileUnroll = 4;              //   (hub tiles: a default tile is one pass)
+constexpr int kMaxPeelBlocks = 1024;  // workgroups of the persistent grid at most (segmented lists)
+static_assert(kPeelThreads >= kMaxPeelBlocks, "one thread per segment when prefixing segment counts");
 constexpr int kDbgPhases = 64;             // phases of the per-workgroup debug record
 constexpr int kDbgBlocks = 256;
 constexpr int kBlockQ = 1024;              // workgroup-local hub tile queue (chained mode)
@@ -52,6 +54,8 @@ struct alignas(128) PeelCtl {
   unsigned int status;        // error bits (KC_ERR_*)
   unsigned int pad2[31];
   unsigned long long stats[16];
+  // survivors each workgroup wrote into its segment of active list 0 / 1 (see the peel kernel)
+  unsigned int acnt[2][kMaxPeelBlocks];
   // phase timeline of workgroup 0, not cleared between launches: 100 MHz wall clock at start,
   // work done, flushed and barrier passed; then kind | precheck << 2 | async << 3 | k << 8, the
   // frontier's vertices, its hub tiles and the active-set size
