@@ -95,7 +95,13 @@ typedef struct {
                             rewritten once without their peeled neighbours, so later rounds stop
                             reading dead entries; costs 16 bytes per vertex and half the adjacency
                             in workspace; 0 = default (n / 256, at least 4096), -1 = never */
-  int32_t reserved[1];   /* must be zero */
+  int32_t tail;          /* once at most this many vertices are live at a round boundary (they then
+                            form the k-core of that round, whose coreness is the same inside it
+                            as in the whole graph), one workgroup finishes the decomposition on
+                            them with their induced degrees in LDS, so the last, small rounds
+                            synchronise at workgroup level instead of grid-wide; costs 4 bytes
+                            per vertex plus min(m, tail^2) entries of workspace; capped at what
+                            the workgroup's LDS holds; 0 = that cap, -1 = never */
 } kcore_options;
 
 /* Counters of one decomposition (filled when a kcore_stats* is passed; that call synchronises

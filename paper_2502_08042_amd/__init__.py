@@ -49,7 +49,7 @@ class Options(ctypes.Structure):
                 ("tile_edges", ctypes.c_int32), ("async_frontier", ctypes.c_int32),
                 ("async_scan", ctypes.c_int32), ("block_tiles", ctypes.c_int32),
                 ("block_queue", ctypes.c_int32), ("tile_probe", ctypes.c_int32),
-                ("residual", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
+                ("residual", ctypes.c_int32), ("tail", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -148,7 +148,7 @@ def _stream_ptr(stream) -> int:
 
 def _options(mode, validate, num_entries, hub_degree=0, local_budget=0, tile_edges=0,
              blocks_per_cu=0, async_frontier=0, async_scan=0, block_tiles=0,
-             block_queue=0, tile_probe=0, residual=0) -> Options:
+             block_queue=0, tile_probe=0, residual=0, tail=0) -> Options:
     o = Options()
     o.mode = MODES[mode] if isinstance(mode, str) else int(mode)
     o.validate = 1 if validate else 0
@@ -163,6 +163,7 @@ def _options(mode, validate, num_entries, hub_degree=0, local_budget=0, tile_edg
     o.block_queue = block_queue
     o.tile_probe = tile_probe
     o.residual = residual
+    o.tail = tail
     return o
 
 

@@ -41,6 +41,7 @@ struct DevInfo {
   int cus = 0;
   size_t lds_per_block = 0;
   int peel_bpc = 0;
+  int32_t tail_lcap = 0;  // vertices the tail peel's LDS holds
 };
 
 std::mutex g_mu;
@@ -59,6 +60,12 @@ int dev_info(int dev, DevInfo& out) {
   HIP_TRY(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
   d.lds_per_block = (size_t)lds;
   HIP_TRY(kc::peel_occupancy(&d.peel_bpc));
+  size_t tail_static = 0;
+  HIP_TRY(kc::tail_static_lds(&tail_static));
+  // 8 bytes per vertex (induced degree and queue slot) plus 64 spare slots, in whole 1024-vertex
+  // steps
+  d.tail_lcap = lds > (int)tail_static + 256 ? (int32_t)(((size_t)lds - tail_static - 256) / 8 / 1024 * 1024) : 0;
+  if (d.tail_lcap > 0) HIP_TRY(kc::tail_allow_lds(d.tail_lcap));
   g_dev[dev] = d;
   out = d;
   return KCORE_OK;
@@ -66,7 +73,7 @@ int dev_info(int dev, DevInfo& out) {
 
 // ---- single-graph workspace ---------------------------------------------------------------
 struct PeelWs {
-  int64_t n_cap = -1, t_cap = -1, r_cap = -1;
+  int64_t n_cap = -1, t_cap = -1, r_cap = -1, l_cap = -1, e_cap = -1;
   void* block = nullptr;  // one allocation for everything
   size_t bytes = 0;
   uint32_t* dt = nullptr;
@@ -78,6 +85,10 @@ struct PeelWs {
   int64_t q_cap = 0;
   long long* rrow = nullptr;
   int32_t* radj = nullptr;
+  int32_t* tmap = nullptr;   // tail handoff: id -> local id (n entries)
+  int32_t* tgid = nullptr;   //   local id -> id (l_cap)
+  long long* trow = nullptr; //   local rows (2 l_cap)
+  int32_t* tadj = nullptr;   //   their entries (e_cap)
   kc::PeelCtl* ctl = nullptr;
   unsigned long long* host_stats = nullptr;  // pinned
   unsigned* vstat = nullptr;                 // validation status + xor sum (device)
@@ -104,7 +115,8 @@ std::map<Key, BatchWs*> g_batch;
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
-int peel_ws(int dev, hipStream_t s, int64_t n, int64_t tcap, int64_t rcap, PeelWs*& out) {
+int peel_ws(int dev, hipStream_t s, int64_t n, int64_t tcap, int64_t rcap, int64_t lcap, int64_t ecap,
+            PeelWs*& out) {
   std::lock_guard<std::mutex> lk(g_mu);
   PeelWs*& w = g_peel[Key(dev, s)];
   if (!w) {
@@ -113,7 +125,7 @@ int peel_ws(int dev, hipStream_t s, int64_t n, int64_t tcap, int64_t rcap, PeelW
     HIP_TRY(hipEventCreate(&w->ev0));
     HIP_TRY(hipEventCreate(&w->ev1));
   }
-  if (w->n_cap < n || w->t_cap < tcap || w->r_cap < rcap) {
+  if (w->n_cap < n || w->t_cap < tcap || w->r_cap < rcap || w->l_cap < lcap || w->e_cap < ecap) {
     if (w->block) {
       HIP_TRY(hipStreamSynchronize(s));
       HIP_TRY(hipFree(w->block));
@@ -122,6 +134,8 @@ int peel_ws(int dev, hipStream_t s, int64_t n, int64_t tcap, int64_t rcap, PeelW
     const int64_t nc = n > w->n_cap ? n + n / 8 : w->n_cap;
     const int64_t tc = tcap > w->t_cap ? tcap + tcap / 8 + 64 : w->t_cap;
     const int64_t rc = rcap > w->r_cap ? rcap : std::max<int64_t>(w->r_cap, 0);
+    const int64_t lc = std::max<int64_t>(lcap, std::max<int64_t>(w->l_cap, 0));
+    const int64_t ec = std::max<int64_t>(ecap, std::max<int64_t>(w->e_cap, 0));
     const size_t nw = (size_t)((nc + 15) / 16);
     size_t off = 0;
     const size_t o_dt = off; off = align_up(off + 4 * (size_t)nc);
@@ -138,12 +152,16 @@ int peel_ws(int dev, hipStream_t s, int64_t n, int64_t tcap, int64_t rcap, PeelW
     const size_t o_q = off; off = align_up(off + 8 * (size_t)qc);
     const size_t o_rr = off; off = align_up(off + (rc > 0 ? 16 * (size_t)nc : 0));
     const size_t o_ra = off; off = align_up(off + 4 * (size_t)rc);
+    const size_t o_tm = off; off = align_up(off + (lc > 0 ? 4 * (size_t)nc : 0));
+    const size_t o_tg = off; off = align_up(off + 4 * (size_t)lc);
+    const size_t o_tr = off; off = align_up(off + 16 * (size_t)lc);
+    const size_t o_te = off; off = align_up(off + 4 * (size_t)ec);
     const size_t o_c = off; off = align_up(off + sizeof(kc::PeelCtl));
     const size_t o_v = off; off = align_up(off + 64);
     hipError_t e = hipMalloc(&w->block, off);
     if (e != hipSuccess) {
       w->block = nullptr;
-      w->n_cap = w->t_cap = w->r_cap = -1;
+      w->n_cap = w->t_cap = w->r_cap = w->l_cap = w->e_cap = -1;
       return fail(KCORE_ENOMEM, "workspace of %zu bytes: %s", off, hipGetErrorString(e));
     }
     char* b = static_cast<char*>(w->block);
@@ -161,6 +179,12 @@ int peel_ws(int dev, hipStream_t s, int64_t n, int64_t tcap, int64_t rcap, PeelW
     w->rrow = rc > 0 ? (long long*)(b + o_rr) : nullptr;
     w->radj = rc > 0 ? (int32_t*)(b + o_ra) : nullptr;
     w->r_cap = rc;
+    w->tmap = lc > 0 ? (int32_t*)(b + o_tm) : nullptr;
+    w->tgid = lc > 0 ? (int32_t*)(b + o_tg) : nullptr;
+    w->trow = lc > 0 ? (long long*)(b + o_tr) : nullptr;
+    w->tadj = lc > 0 ? (int32_t*)(b + o_te) : nullptr;
+    w->l_cap = lc;
+    w->e_cap = ec;
     w->ctl = (kc::PeelCtl*)(b + o_c);
     w->vstat = (unsigned*)(b + o_v);
     w->n_cap = nc;
@@ -222,8 +246,7 @@ int check_opts(const kcore_options* o) {
   if (o->blocks_per_cu < 0 || o->hub_degree < 0 || o->num_entries < 0 || o->local_budget < 0 ||
       o->tile_edges < 0 || (o->tile_edges % 64) != 0 || o->tile_edges > 32768)
     return fail(KCORE_EINVAL, "negative option, or tile_edges not a multiple of 64 up to 32768");
-  for (int i = 0; i < 2; ++i)
-    if (o->reserved[i]) return fail(KCORE_EINVAL, "reserved option fields must be zero");
+  if (o->tail < -1) return fail(KCORE_EINVAL, "tail must be >= -1");
   if (o->tile_probe < -1 || o->tile_probe > 0) return fail(KCORE_EINVAL, "tile_probe must be 0 or -1");
   if (o->residual < -1) return fail(KCORE_EINVAL, "residual must be >= -1");
   if (o->block_queue < 0 || o->block_queue > kc::kBlockQ)
@@ -318,8 +341,17 @@ static int peel_impl(const int64_t* offsets, const int32_t* adj, int64_t n, int3
   const int64_t resid_vmax = ro < 0 ? -1 : (ro ? ro : std::max<int64_t>(n / 256, 4096));
   const int64_t rcap = resid_vmax < 0 ? 0 : m / 2 + 64;
 
+  // tail handoff: the last live vertices (at most what the tail peel's LDS holds) are peeled by
+  // one workgroup; their local rows hold at most min(m, L (L - 1)) entries (simple graph)
+  const int32_t to = opt ? opt->tail : 0;
+  int64_t tail_vmax = (to < 0 || k_query > 0) ? 0 : std::min<int64_t>(to ? to : di.tail_lcap, di.tail_lcap);
+  tail_vmax = std::min<int64_t>(tail_vmax, n);
+  // (plus up to 3 pad entries per row: rows start on 16-byte boundaries)
+  const int64_t tail_ecap =
+      tail_vmax > 0 ? std::min<int64_t>(m, tail_vmax * (tail_vmax - 1)) + 3 * tail_vmax + 64 : 0;
+
   PeelWs* w = nullptr;
-  if (int rc = peel_ws(dev, stream, n, tcap, rcap, w)) return rc;
+  if (int rc = peel_ws(dev, stream, n, tcap, rcap, tail_vmax, tail_ecap, w)) return rc;
   if (opt && opt->validate) {
     if (int rc = run_validate(offsets, adj, n, nullptr, 0, w->vstat, stream)) return rc;
   }
@@ -373,6 +405,15 @@ static int peel_impl(const int64_t* offsets, const int32_t* adj, int64_t n, int3
   a.radj = w->radj;
   a.rcap = rcap;
   a.resid_vmax = w->rrow ? resid_vmax : -1;
+  a.tail_vmax = tail_vmax > 0 ? tail_vmax : -1;
+  a.tmap = w->tmap;
+  a.tgid = w->tgid;
+  a.trow = w->trow;
+  a.tadj = w->tadj;
+  a.tail_ecap = tail_ecap;
+  // testing aid: KCORE_DEBUG_TAIL_ECAP=e pretends the local rows hold only e entries, so that
+  // handoffs are called off and retried
+  if (const char* te = getenv("KCORE_DEBUG_TAIL_ECAP")) a.tail_ecap = std::min<int64_t>(tail_ecap, atoll(te));
   // debugging aid: KCORE_DEBUG_PHASE=p records every workgroup's timing in phases [p, p + 64)
   const char* dp = getenv("KCORE_DEBUG_PHASE");
   a.dbg_lo = dp ? atoll(dp) : -1;
@@ -382,6 +423,7 @@ static int peel_impl(const int64_t* offsets, const int32_t* adj, int64_t n, int3
   if (a.chained) HIP_TRY(kc::launch_fill_u32(w->aq, 0xffffffffu, 2 * (size_t)w->q_cap, stream));
   if (stats_host) HIP_TRY(hipEventRecord(w->ev0, stream));
   HIP_TRY(kc::launch_peel(a, blocks, stream));
+  if (tail_vmax > 0) HIP_TRY(kc::launch_tail(a, (int32_t)tail_vmax, stream));
   if (!stats_host) return KCORE_OK;
   HIP_TRY(hipEventRecord(w->ev1, stream));
   HIP_TRY(hipMemcpyAsync(w->host_stats, w->ctl->stats, 16 * sizeof(unsigned long long),

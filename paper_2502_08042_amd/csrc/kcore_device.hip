@@ -723,7 +723,7 @@ __device__ __forceinline__ void async_loop(const PeelArgs& a, WaveCtx& c, const 
   }
 }
 
-enum PhaseKind { PH_SCAN = 0, PH_EXPAND = 1, PH_ASYNC = 2, PH_RESIDUAL = 3 };
+enum PhaseKind { PH_SCAN = 0, PH_EXPAND = 1, PH_ASYNC = 2, PH_RESIDUAL = 3, PH_TAIL = 4 };
 
 __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
   __shared__ int32_t s_sf[kWaves][kStage];
@@ -831,6 +831,9 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
   // the rows are rewritten once the active set is at most this large (-1: done, or never); a
   // rewrite called off for lack of room is tried again when the active set has halved
   long long resid_limit = a.resid_vmax;
+  // the live vertices go to the tail peel once at most this many remain (-1: never); a handoff
+  // called off for lack of room is tried again when half as many remain
+  long long tail_limit = a.k_query > 0 ? -1 : a.tail_vmax;
   const long long max_phases = 4 * n + 64;
 
   for (long long p = 1;; ++p) {
@@ -860,13 +863,23 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
     if (tr) C->trace[p][0] = wall_clock64();
     const bool dbg = threadIdx.x == 0 && blockIdx.x < kDbgBlocks && p >= a.dbg_lo && p < a.dbg_lo + kDbgPhases;
     if (dbg) C->dbg[p - a.dbg_lo][blockIdx.x][0] = wall_clock64();
-    if (kind == PH_RESIDUAL) {
-      // Rewrites the rows of the live vertices without their peeled neighbours, once. It runs at a
-      // round boundary: every decrement has landed, so a live vertex's induced degree is its number
-      // of live neighbours and sizes its new row exactly. (1) Reserve the new rows, list the tiles
-      // of the old ones; (2) copy the live neighbours of each old tile to the new row (order within
-      // a row is free) and refresh the hub flags for the new row lengths. When the live rows do not
-      // fit the residual buffer the rewrite is called off after (1) and nothing changes.
+    if (kind == PH_RESIDUAL || kind == PH_TAIL) {
+      // Rewrites the rows of the live vertices without their peeled neighbours. It runs at a round
+      // boundary: every decrement has landed, so a live vertex's induced degree is its number of
+      // live neighbours and sizes its new row exactly. (1) Reserve the new rows and list the tiles
+      // of the current ones; (2) copy the live neighbours of each tile to the new row (order within
+      // a row is free). When the new rows do not fit their buffer the rewrite is called off after
+      // (1) and nothing changes.
+      //  * PH_RESIDUAL (once): the grid goes on peeling from the new rows, whose hub flags follow
+      //    the new row lengths.
+      //  * PH_TAIL: hands the live vertices to the single-workgroup tail peel. At a round boundary
+      //    they form the kx-core, and a vertex of the kx-core has the same coreness in it as in the
+      //    whole graph, so the tail peel needs only this subgraph: the live vertices are numbered
+      //    0..L-1 in (1), and (2) writes their rows in those local ids. The grid then stops.
+      const bool to_tail = kind == PH_TAIL;
+      long long* nrow = to_tail ? a.trow : a.rrow;
+      int32_t* nadj = to_tail ? a.tadj : a.radj;
+      const long long ncap = to_tail ? a.tail_ecap : a.rcap;
       PhaseSlot* slot = o.slot;
       const int32_t* alist = a.act[acur];
       for (long long i0 = gw * 64; i0 < asize; i0 += W * 64) {
@@ -874,17 +887,25 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
         int32_t v = -1;
         if (i < asize) v = active_item(alist, dense, i, aseg, s_apref, nb);
         bool live = false;
-        long long len = 0, ob = 0, od = 0, nt = 0;
+        long long len = 0, nt = 0;
         if (v >= 0) {
           live = !((ald(&a.state[v >> 4]) >> (v & 15)) & 1u);
           if (live) {
+            long long ob = 0, od = 0;
+            row_of(a, c, v, ob, od);
             len = ald(&a.dt[v]) & DMASK;
-            ob = a.off[v];
-            od = a.off[v + 1] - ob;
             nt = (od + a.tile - 1) / a.tile;
           }
         }
-        const long long incl = wave_incl_scan(len);
+        const unsigned long long lm = __ballot(live);
+        if (lm == 0) continue;
+        unsigned long long vbase = 0;
+        if (l == 0 && to_tail) vbase = aadd(&slot->active, (unsigned long long)__popcll(lm));
+        vbase = __shfl(vbase, 0, 64);
+        // local rows start on 16-byte boundaries (lengths padded to 4 entries with -1) so that the
+        // tail peel streams them with 16-byte loads
+        const long long rlen = to_tail ? (len + 3) & ~3ll : len;
+        const long long incl = wave_incl_scan(rlen);
         const long long tot = __shfl(incl, 63, 64);
         unsigned long long base = 0;
         if (l == 0 && tot) base = aadd(&slot->small, (unsigned long long)tot);
@@ -894,13 +915,20 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
         unsigned long long tbase = 0;
         if (l == 0 && ttot) tbase = aadd(&slot->tiles, (unsigned long long)ttot);
         tbase = __shfl(tbase, 0, 64);
-        if ((long long)base + tot > a.rcap || (long long)tbase + ttot > a.qcap) {
-          // the live rows do not fit the residual buffer: the rewrite is called off
-          if (l == 0) ast(&slot->hubv, 1ull);
+        if ((long long)base + tot > ncap || (long long)tbase + ttot > a.qcap ||
+            (to_tail && (long long)(vbase + __popcll(lm)) > a.tail_vmax)) {
+          if (l == 0) ast(&slot->hubv, 1ull);  // the new rows do not fit: called off
         } else if (live) {
-          const long long rb = (long long)base + incl - len;
-          ast(&a.rrow[2 * (long long)v], rb);      // first entry
-          ast(&a.rrow[2 * (long long)v + 1], rb);  // fill cursor, the row's end once filled
+          long long r = v;  // new row index: the vertex, or its local id
+          if (to_tail) {
+            r = (long long)vbase + rank_in(lm);
+            ast(&a.tmap[v], (int32_t)r);
+            ast(&a.tgid[r], v);
+          }
+          const long long rb = (long long)base + incl - rlen;
+          ast(&nrow[2 * r], rb);      // first entry
+          ast(&nrow[2 * r + 1], rb);  // fill cursor, the row's end once filled
+          for (long long x = rb + len; x < rb + rlen; ++x) ast(&nadj[x], -1);
           const long long t0 = (long long)tbase + tincl - nt;
           for (long long j = 0; j < nt; ++j)
             ast(&a.aq[t0 + j], (long long)(((unsigned long long)j << 32) | (unsigned)v));
@@ -908,14 +936,15 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
       }
       if (!grid_sync(C, epoch)) break;
       st_bar++;
-      // (2) Copy the live neighbours of each old tile to the new row (order within a row is free).
       if (threadIdx.x == 0) {
         s_out[0] = (long long)ald(&slot->tiles);
         s_out[1] = (long long)ald(&slot->hubv);
+        s_out[2] = (long long)ald(&slot->active);
       }
       __syncthreads();
       const long long ntl = s_out[0] <= a.qcap ? s_out[0] : a.qcap;
       const bool called_off = s_out[1] != 0;
+      const long long nlive = s_out[2];
       __syncthreads();
       for (long long it = gw; it < ntl; it += W) {
         const long long e = ald(&a.aq[it]);
@@ -926,37 +955,40 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
         }
         const int32_t v = (int32_t)(e & 0xffffffffll);
         const long long j = (long long)((unsigned long long)e >> 32);
-        const long long ob = a.off[v], oe = a.off[v + 1];
-        const long long b = ob + j * a.tile, en = min(oe, b + a.tile);
+        long long ob = 0, od = 0;
+        row_of(a, c, v, ob, od);
+        const long long b = ob + j * a.tile, en = min(ob + od, b + a.tile);
         const long long len = (long long)(ald(&a.dt[v]) & DMASK);
-        const long long lim = ald(&a.rrow[2 * (long long)v]) + len;
+        const long long r = to_tail ? (long long)ald(&a.tmap[v]) : (long long)v;
+        const long long lim = ald(&nrow[2 * r]) + len;
         // hub flag for the new row length (only the flag bit changes)
-        if (j == 0 && l == 0) ast(&a.dt[v], (uint32_t)len | (len >= (long long)a.hub ? HUBBIT : 0u));
+        if (!to_tail && j == 0 && l == 0) ast(&a.dt[v], (uint32_t)len | (len >= (long long)a.hub ? HUBBIT : 0u));
         // 256 entries per pass: all loads, then all probes, then one reservation for the pass
         for (long long p0 = b; p0 < en; p0 += 64 * kTileUnroll) {
           int32_t u[kTileUnroll];
           uint32_t sw[kTileUnroll];
 #pragma unroll
-          for (int r = 0; r < kTileUnroll; ++r) {
-            const long long q = p0 + 64 * r + l;
-            u[r] = q < en ? a.adj[q] : -1;
+          for (int q = 0; q < kTileUnroll; ++q) {
+            const long long x = p0 + 64 * q + l;
+            u[q] = x < en ? c.adj[x] : -1;
           }
 #pragma unroll
-          for (int r = 0; r < kTileUnroll; ++r) sw[r] = u[r] >= 0 ? ald(&a.state[u[r] >> 4]) : 1u;
+          for (int q = 0; q < kTileUnroll; ++q) sw[q] = u[q] >= 0 ? ald(&a.state[u[q] >> 4]) : 1u;
           unsigned long long mk[kTileUnroll];
           int cnt = 0;
 #pragma unroll
-          for (int r = 0; r < kTileUnroll; ++r) {
-            const bool lv = u[r] >= 0 && !((sw[r] >> (u[r] & 15)) & 1u);
+          for (int q = 0; q < kTileUnroll; ++q) {
+            const bool lv = u[q] >= 0 && !((sw[q] >> (u[q] & 15)) & 1u);
             // entries to peeled neighbours are done with here (they count as expanded)
-            c.edges += (u[r] >= 0 && !lv) ? 1 : 0;
-            mk[r] = __ballot(lv);
-            cnt += __popcll(mk[r]);
+            c.edges += (u[q] >= 0 && !lv) ? 1 : 0;
+            if (lv && to_tail) u[q] = ald(&a.tmap[u[q]]);
+            mk[q] = __ballot(lv);
+            cnt += __popcll(mk[q]);
           }
           if (cnt == 0) continue;
           long long pos = 0;
           if (l == 0)
-            pos = (long long)aadd(reinterpret_cast<unsigned long long*>(&a.rrow[2 * (long long)v + 1]),
+            pos = (long long)aadd(reinterpret_cast<unsigned long long*>(&nrow[2 * r + 1]),
                                   (unsigned long long)cnt);
           pos = __shfl(pos, 0, 64);
           if (pos + cnt > lim) {
@@ -964,23 +996,32 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
             continue;
           }
 #pragma unroll
-          for (int r = 0; r < kTileUnroll; ++r) {
-            if ((mk[r] >> l) & 1ull) ast(&a.radj[pos + rank_in(mk[r])], u[r]);
-            pos += __popcll(mk[r]);
+          for (int q = 0; q < kTileUnroll; ++q) {
+            if ((mk[q] >> l) & 1ull) ast(&nadj[pos + rank_in(mk[q])], u[q]);
+            pos += __popcll(mk[q]);
           }
         }
         if (l == 0) ast(&a.aq[it], kQEmpty);  // the async queue starts every phase empty
       }
       if (tr) {
         C->trace[p][1] = C->trace[p][2] = wall_clock64();
-        C->trace[p][4] = (unsigned long long)PH_RESIDUAL | ((unsigned long long)k << 8);
+        C->trace[p][4] = (unsigned long long)kind | ((unsigned long long)k << 8);
         C->trace[p][5] = C->trace[p][6] = 0;
         C->trace[p][7] = (unsigned long long)asize;
       }
       if (!grid_sync(C, epoch)) break;
       st_bar++;
       if (tr) C->trace[p][3] = wall_clock64();
-      if (!called_off) {
+      if (to_tail) {
+        if (!called_off) {
+          if (blockIdx.x == 0 && threadIdx.x == 0) {
+            ast(&C->tail_k, (unsigned long long)kx);
+            ast(&C->tail_n, (unsigned long long)nlive);
+          }
+          break;
+        }
+        tail_limit = (n - total_peeled) / 2;
+      } else if (!called_off) {
         c.resid = true;
         c.adj = a.radj;
         c.rows = a.rrow;
@@ -1234,8 +1275,12 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
     }
     // a k-core query ends with its one round: the survivors are the k-core
     if (a.k_query > 0 && kind == PH_SCAN) break;
-    // at a round boundary with a small active set whose live rows fit: rewrite the rows once
-    if (kind == PH_SCAN && resid_limit >= 0 && asize <= resid_limit) kind = PH_RESIDUAL;
+    // at a round boundary with few live vertices left: hand them to the tail peel; else, with a
+    // small active set whose live rows fit: rewrite the rows once
+    if (kind == PH_SCAN && tail_limit > 0 && n - total_peeled <= tail_limit)
+      kind = PH_TAIL;
+    else if (kind == PH_SCAN && resid_limit >= 0 && asize <= resid_limit)
+      kind = PH_RESIDUAL;
   }
   if (a.k_query > 0) {
     // membership: every workgroup left the loop after the same barrier, so the peeled bits are final.
@@ -1278,6 +1323,7 @@ hipError_t launch_peel(const PeelArgs& a, int blocks, hipStream_t s) {
 hipError_t peel_occupancy(int* blocks_per_cu) {
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, peel_kernel, kPeelThreads, 0);
 }
+
 
 // ------------------------------------------------------------------------------------------
 // Batched peel: one workgroup per graph, graphs claimed largest-first from a shared counter.
@@ -1642,6 +1688,409 @@ hipError_t launch_batched(const BatchArgs& a, int blocks, size_t lds_bytes, hipS
 hipError_t batched_occupancy(size_t lds_bytes, int* blocks_per_cu) {
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batched_kernel, kBatchThreads,
                                                       lds_bytes);
+}
+
+// ------------------------------------------------------------------------------------------
+// Tail peel: one workgroup finishes the decomposition on the live vertices peel_kernel handed over
+// (Alg. 1 with the online peel of Alg. 3: chained rounds in chained mode, level-synchronous
+// subrounds in level-sync mode) with their induced degrees in LDS, so its rounds synchronise at
+// workgroup level instead of grid-wide. The local rows hold live neighbours only, in local ids. A
+// round scans every local vertex: at its start a live vertex has induced degree >= k, and a vertex
+// peeled earlier stays below k (it is never decremented once at or below the current k), so
+// degree == k picks the round's first frontier. The queue holds vertices in peel order; a
+// subround's frontier is the queue segment between two marks.
+// ------------------------------------------------------------------------------------------
+// Decrements of the induced degrees of N neighbours per lane (local ids; a lane with no entry
+// passes L + lane, a private spare slot past the vertices, so that no lane branches). A vertex
+// peeled before is at or below k and stays there, and every neighbour decrements it once, so its
+// degree never wraps and never returns to k + 1; the decrement that takes u from k + 1 to k pushes
+// it (slot reserved first, then written: chained rounds read slots as they fill). Every atomic of
+// the batch is issued before any result is looked at. All lanes of the wavefront call.
+template <int N>
+__device__ __forceinline__ void tail_edges(const PeelArgs& a, uint32_t* d, int32_t* q, int* s_tail, int L,
+                                           const int32_t (&u)[N], uint32_t k) {
+  uint32_t old[N];
+#pragma unroll
+  for (int j = 0; j < N; ++j) old[j] = atomicSub(&d[u[j]], 1u);
+  unsigned cm = 0;  // this lane's crossings
+#pragma unroll
+  for (int j = 0; j < N; ++j) cm |= (old[j] == k + 1 ? 1u : 0u) << j;
+  if (!__ballot(cm != 0)) return;
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    const bool crossed = (cm >> j) & 1u;
+    const unsigned long long m = __ballot(crossed);
+    if (!m) continue;
+    if (crossed) a.core[a.tgid[u[j]]] = (int32_t)k;
+    int b = 0;
+    if (lane_id() == 0) b = atomicAdd(s_tail, __popcll(m));
+    b = __shfl(b, 0, 64);
+    if (crossed) lds_st(&q[b + rank_in(m)], u[j]);
+  }
+}
+
+// Entries [tb, tb + len) of the local rows, len <= kTailTile, through one wavefront with 16-byte
+// loads, every load in flight before the first decrement (tb on a 16-byte boundary; rows are
+// padded to whole 16-byte words). All lanes call with the same range.
+__device__ __forceinline__ void tail_tile(const PeelArgs& a, uint32_t* d, int32_t* q, int* s_tail, int L, int tb,
+                                          int len, uint32_t k) {
+  const int l = lane_id();
+  const int spare = L + l;
+  int4 x[kTailTile / 256];
+#pragma unroll
+  for (int j = 0; j < kTailTile / 256; ++j) {
+    const int r = 256 * j + 4 * l;
+    x[j] = r < len ? *reinterpret_cast<const int4*>(a.tadj + (tb + r)) : make_int4(spare, spare, spare, spare);
+  }
+  int32_t u[kTailTile / 64];
+#pragma unroll
+  for (int j = 0; j < kTailTile / 256; ++j) {
+    const int r = 256 * j + 4 * l;
+    u[4 * j] = x[j].x;  // r < len whenever the load happened
+    u[4 * j + 1] = r + 1 < len ? x[j].y : spare;
+    u[4 * j + 2] = r + 2 < len ? x[j].z : spare;
+    u[4 * j + 3] = r + 3 < len ? x[j].w : spare;
+  }
+  tail_edges(a, d, q, s_tail, L, u, k);
+}
+
+// Chained round of the tail peel (VGC, Sec. 4.2, at workgroup level): the round's queue segment
+// grows while it is worked off. A wavefront claims a share of the waiting vertices (all waiting
+// ones split over the wavefronts, at most 64), streams each long row itself and expands the short
+// ones edge-balanced across its lanes; what it takes to k joins the same queue. A wave leaves when
+// it sees no busy wave (busy first) and then no unclaimed entry; entries are reserved before they
+// are written, so a claimed slot is read once it is no longer -1. False on a timeout. All threads
+// call.
+__device__ __forceinline__ bool tail_chain(const PeelArgs& a, uint32_t* d, int32_t* q, int L, uint32_t k,
+                                           int* s_claim, int* s_tail, int* s_busy, long long& st_edges) {
+  constexpr int nw = kTailThreads / 64;
+  const int l = lane_id();
+  const unsigned long long t_start = wall_clock64();
+  for (;;) {
+    int state = 0, h = 0, cnt = 0;  // state: 1 claimed, 2 done, 3 timeout
+    if (l == 0) {
+      bool counted = true;
+      for (int spin = 0;; ++spin) {
+        const int hh = lds_ld(s_claim);
+        const int tt = lds_ld(s_tail);
+        if (hh < tt) {
+          if (!counted) {
+            atomicAdd(s_busy, 1);
+            counted = true;
+          }
+          const int n = min(64, (tt - hh + nw - 1) / nw);
+          if (atomicCAS(s_claim, hh, hh + n) == hh) {
+            h = hh;
+            cnt = n;
+            state = 1;
+            break;
+          }
+          continue;
+        }
+        if (counted) {
+          atomicSub(s_busy, 1);
+          counted = false;
+          continue;
+        }
+        if (lds_ld(s_busy) == 0) {
+          if (lds_ld(s_claim) >= lds_ld(s_tail)) {
+            state = 2;
+            break;
+          }
+          continue;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        if ((spin & 255) == 255 && wall_clock64() - t_start > 400000000ull) {
+          state = 3;
+          break;
+        }
+      }
+    }
+    state = __shfl(state, 0, 64);
+    if (state != 1) return state == 2;
+    h = __shfl(h, 0, 64);
+    cnt = __shfl(cnt, 0, 64);
+    int32_t v = -1;
+    if (l < cnt) {
+      for (int spin = 0;; ++spin) {
+        v = lds_ld(&q[h + l]);
+        if (v >= 0) break;
+        if ((spin & 255) == 255 && wall_clock64() - t_start > 400000000ull) break;
+      }
+    }
+    if (__ballot(l < cnt && v < 0)) return false;
+    int rb = 0, dg = 0;
+    if (v >= 0) {
+      rb = (int)a.trow[2 * (long long)v];
+      dg = (int)(a.trow[2 * (long long)v + 1] - rb);
+    }
+    unsigned long long big = __ballot(dg >= kTailBig);
+    while (big) {
+      const int j = __ffsll((long long)big) - 1;
+      big &= big - 1;
+      const int rs = __shfl(rb, j, 64), len = __shfl(dg, j, 64);
+      if (l == 0) st_edges += len;
+      for (int o = 0; o < len; o += kTailTile) tail_tile(a, d, q, s_tail, L, rs + o, min(len - o, kTailTile), k);
+    }
+    const int sd = dg >= kTailBig ? 0 : dg;
+    const int incl = wave_incl_scan(sd);
+    const int excl = incl - sd;
+    const int total = __shfl(incl, 63, 64);
+    if (l == 0) st_edges += total;
+    for (int e0 = 0; e0 < total; e0 += 64 * kTailUnroll) {
+      int32_t u[kTailUnroll];
+#pragma unroll
+      for (int r = 0; r < kTailUnroll; ++r) {
+        const int t = e0 + 64 * r + l;
+        int j = 0;
+#pragma unroll
+        for (int step = 32; step >= 1; step >>= 1) {
+          const int cand = j + step;
+          const int ex = __shfl(excl, cand & 63, 64);
+          if (cand < 64 && ex <= t) j = cand;
+        }
+        const int pos = __shfl(rb, j, 64) + (t - __shfl(excl, j, 64));
+        u[r] = t < total ? a.tadj[pos] : L + l;
+      }
+      tail_edges(a, d, q, s_tail, L, u, k);
+    }
+  }
+}
+
+__device__ __forceinline__ int tail_excl_scan(int x, int* s_w, int& total) {
+  constexpr int nw = kTailThreads / 64;
+  const int w = threadIdx.x >> 6, l = lane_id();
+  const int incl = wave_incl_scan(x);
+  if (l == 63) s_w[w] = incl;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int i = 0; i < nw; ++i) {
+      const int c = s_w[i];
+      s_w[i] = t;
+      t += c;
+    }
+    s_w[nw] = t;
+  }
+  __syncthreads();
+  total = s_w[nw];
+  const int r = s_w[w] + incl - x;
+  __syncthreads();
+  return r;
+}
+
+// LDS of the tail peel: per vertex an induced degree and a queue slot, plus 64 spare degree slots
+// (one per lane) that lanes without an entry decrement.
+constexpr size_t tail_dyn_lds(int32_t lcap) { return (size_t)lcap * 8 + 64 * 4; }
+
+template <bool kChained>
+__global__ __launch_bounds__(kTailThreads) void tail_kernel(PeelArgs a, int32_t lcap) {
+  extern __shared__ uint32_t s_dyn[];
+  __shared__ int s_pref[kTailThreads];   // chunk prefix of short-row entries
+  __shared__ int s_tpref[kTailThreads];  // chunk prefix of long-row tiles
+  __shared__ int s_rb[kTailThreads];     // row start
+  __shared__ int s_len[kTailThreads];    // row length
+  __shared__ int s_w[kTailThreads / 64 + 1];
+  __shared__ unsigned s_min[kTailThreads / 64];
+  __shared__ int s_tail;
+  __shared__ int s_claim, s_busy;
+  const int tid = threadIdx.x, l = lane_id(), w = tid >> 6;
+  const long long Ln = (long long)ald(&a.ctl->tail_n);
+  if (Ln == 0) return;
+  if (Ln > lcap) {
+    if (tid == 0) aor(&a.ctl->status, (unsigned)KC_ERR_OVERFLOW);
+    return;
+  }
+  const int L = (int)Ln;
+  uint32_t* d = s_dyn;                                       // L degrees, then 64 spare slots
+  int32_t* q = reinterpret_cast<int32_t*>(s_dyn + lcap + 64);
+  const long long* rows = a.trow;
+  // per-round timeline in the upper half of the phase timeline (100 MHz clock): start, first
+  // frontier extracted, round peeled; then k, first frontier size, vertices peeled so far
+  unsigned long long* trc = nullptr;
+  int ntr = 0;
+  long long st_edges = 0, st_scanned = 0, st_rounds = 0, st_sub = 0;
+
+  // induced degree = length of the local row (its live neighbours); k = the smallest
+  unsigned mn = 0xffffffffu;
+  for (int i = tid; i < L; i += kTailThreads) {
+    const unsigned dg = (unsigned)(rows[2 * (long long)i + 1] - rows[2 * (long long)i]);
+    d[i] = dg;
+    q[i] = -1;  // unwritten queue slot
+    mn = min(mn, dg);
+  }
+  if (tid < 64) d[L + tid] = 0x7fffffffu;  // spare slots: never near any k
+  mn = wave_min(mn);
+  if (l == 0) s_min[w] = mn;
+  if (tid == 0) s_tail = 0;
+  __syncthreads();
+  unsigned k = 0xffffffffu;
+  for (int i = 0; i < kTailThreads / 64; ++i) k = min(k, s_min[i]);
+  __syncthreads();
+  unsigned kmax = 0;
+  int head = 0;
+  for (;;) {
+    trc = (tid == 0 && ntr < kTracePhases / 2) ? a.ctl->trace[kTracePhases / 2 + ntr] : nullptr;
+    if (trc) trc[0] = wall_clock64();
+    // the round's first frontier, and the smallest degree above k for a jump over empty rounds
+    unsigned nm = 0xffffffffu;
+    for (int i0 = 0; i0 < L; i0 += 4 * kTailThreads) {
+      unsigned x[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + r * kTailThreads + tid;
+        x[r] = i < L ? d[i] : 0u;
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + r * kTailThreads + tid;
+        const bool ext = i < L && x[r] == k;
+        if (x[r] > k) nm = min(nm, x[r]);
+        if (ext) a.core[a.tgid[i]] = (int32_t)k;
+        team_push(ext, i, q, &s_tail);
+      }
+    }
+    if (tid == 0) st_scanned += L;
+    nm = wave_min(nm);
+    if (l == 0) s_min[w] = nm;
+    __syncthreads();
+    int tail = s_tail;
+    unsigned nextmin = 0xffffffffu;
+    for (int i = 0; i < kTailThreads / 64; ++i) nextmin = min(nextmin, s_min[i]);
+    __syncthreads();
+    if (tail == head) {
+      if (nextmin == 0xffffffffu) break;  // (cannot happen while vertices are live)
+      k = nextmin;
+      continue;
+    }
+    st_rounds++;
+    kmax = k;
+    if (trc) {
+      trc[1] = wall_clock64();
+      trc[4] = k;
+      trc[5] = (unsigned long long)(tail - head);
+    }
+    if (kChained) {
+      if (tid == 0) {
+        s_claim = head;
+        s_busy = kTailThreads / 64;
+      }
+      __syncthreads();
+      if (!tail_chain(a, d, q, L, k, &s_claim, &s_tail, &s_busy, st_edges) && l == 0)
+        aor(&a.ctl->status, (unsigned)KC_ERR_TIMEOUT);
+      __syncthreads();
+      st_sub++;
+      head = tail = s_tail;
+      __syncthreads();
+    }
+    // level-synchronous subrounds: frontier = q[head, tail). Short rows are expanded
+    // edge-balanced over the workgroup (one search per entry); long rows are cut into tiles that
+    // a wavefront streams with 16-byte loads.
+    while (!kChained && head < tail) {
+      st_sub++;
+      for (int c0 = head; c0 < tail; c0 += kTailThreads) {
+        const int i = c0 + tid;
+        int rb = 0, dg = 0;
+        if (i < tail) {
+          const int32_t v = q[i];
+          rb = (int)rows[2 * (long long)v];
+          dg = (int)(rows[2 * (long long)v + 1] - rb);
+        }
+        const bool big = dg >= kTailBig;
+        int total, tiles;
+        const int ex = tail_excl_scan(big ? 0 : dg, s_w, total);
+        const int tex = tail_excl_scan(big ? (dg + kTailTile - 1) / kTailTile : 0, s_w, tiles);
+        s_pref[tid] = ex;
+        s_tpref[tid] = tex;
+        s_rb[tid] = rb;
+        s_len[tid] = dg;
+        if (tid == 0) st_edges += total;
+        if (big) st_edges += dg;
+        __syncthreads();
+        for (int e0 = 0; e0 < total; e0 += kTailThreads * kTailUnroll) {
+          int32_t u[kTailUnroll];
+#pragma unroll
+          for (int r = 0; r < kTailUnroll; ++r) {
+            const int t = e0 + r * kTailThreads + tid;
+            u[r] = L + l;
+            if (t < total) {
+              int lo = 0, hi = kTailThreads - 1;  // largest j with s_pref[j] <= t
+              while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_pref[mid] <= t) lo = mid; else hi = mid - 1;
+              }
+              u[r] = a.tadj[s_rb[lo] + (t - s_pref[lo])];
+            }
+          }
+          tail_edges(a, d, q, &s_tail, L, u, k);
+        }
+        for (int tt = w; tt < tiles; tt += kTailThreads / 64) {
+          int lo = 0, hi = kTailThreads - 1;  // largest j with s_tpref[j] <= tt (wave-uniform)
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_tpref[mid] <= tt) lo = mid; else hi = mid - 1;
+          }
+          // the row starts on a 16-byte boundary and is padded to whole 16-byte words
+          const int o = (tt - s_tpref[lo]) * kTailTile;
+          tail_tile(a, d, q, &s_tail, L, s_rb[lo] + o, min(s_len[lo] - o, kTailTile), k);
+        }
+        __syncthreads();
+      }
+      head = tail;
+      tail = s_tail;
+      __syncthreads();
+    }
+    if (trc) {
+      trc[2] = wall_clock64();
+      trc[6] = (unsigned long long)tail;
+      ntr++;
+    }
+    if (tail >= L) break;
+    k = k + 1;
+  }
+  // statistics: the tail's share of the decomposition's counters (every entry is one LDS decrement)
+  long long v5[2] = {st_edges, st_scanned};
+  for (int qd = 0; qd < 2; ++qd) {
+    long long x = v5[qd];
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    if (l == 0 && x) aadd(&a.ctl->stats[qd == 0 ? ST_EDGES : ST_SCANNED], (unsigned long long)x);
+    if (l == 0 && x && qd == 0) aadd(&a.ctl->stats[ST_DECR], (unsigned long long)x);
+  }
+  if (tid == 0) {
+    aadd(&a.ctl->stats[ST_PEELED], (unsigned long long)L);
+    if (st_rounds) aadd(&a.ctl->stats[ST_ROUNDS], (unsigned long long)st_rounds);
+    if (st_sub) aadd(&a.ctl->stats[ST_SUBROUNDS], (unsigned long long)st_sub);
+    __hip_atomic_fetch_max(&a.ctl->stats[ST_KMAX], (unsigned long long)kmax, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+hipError_t launch_tail(const PeelArgs& a, int32_t lcap, hipStream_t s) {
+  if (a.chained)
+    hipLaunchKernelGGL(tail_kernel<true>, dim3(1), dim3(kTailThreads), tail_dyn_lds(lcap), s, a, lcap);
+  else
+    hipLaunchKernelGGL(tail_kernel<false>, dim3(1), dim3(kTailThreads), tail_dyn_lds(lcap), s, a, lcap);
+  return hipGetLastError();
+}
+
+hipError_t tail_static_lds(size_t* bytes) {
+  hipFuncAttributes fa;
+  size_t mx = 0;
+  for (const void* f : {reinterpret_cast<const void*>(tail_kernel<true>), reinterpret_cast<const void*>(tail_kernel<false>)}) {
+    hipError_t e = hipFuncGetAttributes(&fa, f);
+    if (e != hipSuccess) return e;
+    mx = fa.sharedSizeBytes > mx ? fa.sharedSizeBytes : mx;
+  }
+  *bytes = mx;
+  return hipSuccess;
+}
+
+hipError_t tail_allow_lds(int32_t lcap) {
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(tail_kernel<true>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)tail_dyn_lds(lcap));
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(tail_kernel<false>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)tail_dyn_lds(lcap));
 }
 
 // Largest-first order of the graphs of a batch: counting sort on floor(log2(edges + 1)),

@@ -23,6 +23,10 @@ constexpr int kAsyncWaves = 2;              // waves per workgroup claiming asyn
 constexpr int kBarGroups = 32;       // arrival groups of the grid barrier
 constexpr int kBatchThreads = 512;   // threads per workgroup of the batched peel
 constexpr int kTracePhases = 16384;   // phases whose timeline workgroup 0 records
+constexpr int kTailThreads = 1024;    // threads of the single-workgroup tail peel
+constexpr int kTailUnroll = 4;        //   short rows: adjacency entries in flight per thread
+constexpr int kTailBig = 256;         //   rows at least this long are streamed in tiles ...
+constexpr int kTailTile = 1024;       //   ... of this many entries (4 16-byte loads per lane)
 
 enum StatIdx {
   ST_ROUNDS = 0, ST_SUBROUNDS, ST_BARRIERS, ST_PEELED, ST_EDGES, ST_DECR, ST_COMBINED, ST_SCANNED,
@@ -53,6 +57,10 @@ struct alignas(128) PeelCtl {
   PhaseSlot slot[3];
   unsigned int status;        // error bits (KC_ERR_*)
   unsigned int pad2[31];
+  // live vertices handed to the tail peel (0 = none) and the round at which they were handed over
+  unsigned long long tail_n;
+  unsigned long long tail_k;
+  unsigned long long pad3[14];
   unsigned long long stats[16];
   // survivors each workgroup wrote into its segment of active list 0 / 1 (see the peel kernel)
   unsigned int acnt[2][kMaxPeelBlocks];
@@ -100,6 +108,15 @@ struct PeelArgs {
   int64_t rcap;
   int64_t resid_vmax;     // rewrite the rows once the active set is at most this large (-1 = never)
   int64_t k_query;        // >= 1: only the k_query-core (one round at k_query - 1, membership out)
+  // tail handoff: once at most tail_vmax vertices are live at a round boundary (-1 = never), they
+  // are renumbered 0..L-1 (tmap: id -> local id, tgid: local id -> id) and their rows rewritten
+  // with live neighbours only, in local ids (trow: [2i] first entry, [2i + 1] end, in tadj)
+  int64_t tail_vmax;
+  int32_t* tmap;
+  int32_t* tgid;
+  long long* trow;
+  int32_t* tadj;
+  int64_t tail_ecap;      // entries tadj holds
 };
 
 struct BatchCtl {
@@ -147,6 +164,11 @@ hipError_t launch_order(const int64_t* vptr, const int64_t* off, int32_t G, int3
                         hipStream_t s);
 hipError_t launch_fill_u32(void* p, uint32_t v, size_t count, hipStream_t s);
 hipError_t launch_init_ctl(PeelCtl* c, hipStream_t s);
+// Single-workgroup peel of the live vertices handed over by peel_kernel (returns at once when none
+// were); lcap = vertices its LDS holds.
+hipError_t launch_tail(const PeelArgs& a, int32_t lcap, hipStream_t s);
+hipError_t tail_static_lds(size_t* bytes);
+hipError_t tail_allow_lds(int32_t lcap);
 hipError_t launch_validate(const int64_t* off, const int32_t* adj, int64_t n, const int64_t* vptr,
                            int32_t G, unsigned* status, unsigned long long* xsum, hipStream_t s);
 

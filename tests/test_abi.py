@@ -65,7 +65,7 @@ def test_argument_errors_without_device_work():
     o.block_queue = 2000
     assert lib.kcore_decompose_ex(one.ctypes.data, None, 0, None, None, ctypes.byref(o), None) == -1
     o = K.Options()
-    o.reserved[0] = 1
+    o.tail = -2
     assert lib.kcore_decompose_ex(one.ctypes.data, None, 0, None, None, ctypes.byref(o), None) == -1
     # k-core query: same argument checks
     assert lib.kcore_kcore_subgraph(one.ctypes.data, None, -1, 3, None, None, None, None) == -1

@@ -39,11 +39,12 @@ def small_cases():
             yield f, G.csr(fx["n"], fx["edges"])
 
 
+@pytest.mark.parametrize("tail", [0, -1])
 @pytest.mark.parametrize("mode", MODES)
-def test_small_graphs(mode):
+def test_small_graphs(mode, tail):
     for name, (off, adj) in small_cases():
-        say(f"[gpu] small {name} mode={mode} n={len(off) - 1} m={len(adj)}")
-        got, st = run_single(off, adj, mode=mode)
+        say(f"[gpu] small {name} mode={mode} tail={tail} n={len(off) - 1} m={len(adj)}")
+        got, st = run_single(off, adj, mode=mode, tail=tail)
         want = oracle.bz(off, adj)
         assert not first_mismatch(got, want), f"{name}: {first_mismatch(got, want)}"
         assert st["peeled"] == len(off) - 1, (name, st)
@@ -51,9 +52,10 @@ def test_small_graphs(mode):
         assert st["device_status"] == 0
 
 
+@pytest.mark.parametrize("tail", [0, -1])
 @pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("which", ["rmat12", "er3000", "road128", "hcns200", "rmat16", "road1024"])
-def test_medium_graphs(mode, which):
+def test_medium_graphs(mode, which, tail):
     if which == "rmat12":
         g = gg.rmat(12, 16, 11)
         off, adj = g.offsets, g.adj
@@ -73,8 +75,8 @@ def test_medium_graphs(mode, which):
     else:
         g = gg.config_rmat16()
         off, adj = g.offsets, g.adj
-    say(f"[gpu] medium {which} mode={mode} n={len(off) - 1} m={len(adj)}")
-    got, st = run_single(off, adj, mode=mode)
+    say(f"[gpu] medium {which} mode={mode} tail={tail} n={len(off) - 1} m={len(adj)}")
+    got, st = run_single(off, adj, mode=mode, tail=tail)
     want, sub, ls = oracle.levelsync(off, adj)
     assert not first_mismatch(got, want), first_mismatch(got, want)
     assert st["peeled"] == len(off) - 1 and st["edges"] == len(adj)
@@ -135,6 +137,49 @@ def test_residual_rows_do_not_change_results(mode):
                                      tile_edges=64 if hub else 0)
                 assert not first_mismatch(got, want), first_mismatch(got, want)
                 assert st["peeled"] == len(off) - 1 and st["device_status"] == 0
+
+
+def _tail_cases():
+    return [("rmat13", gg.rmat(13, 16, 7)), ("road256", gg.grid_road(256, 0.05, 0.01, 3)),
+            ("hcns120", None), ("er5000", gg.erdos_renyi(5000, 0.01, 8))]
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_tail_handoff_sizes(mode):
+    """The last live vertices (the k-core of the round boundary where at most `tail` remain) are
+    peeled by one workgroup: from a handoff of a single vertex up to the whole graph after its first
+    round, with and without rewritten rows before, the coreness must be the oracle's, every vertex
+    and entry counted once, the round count that of the sequential framework, and in level-sync
+    mode the subround count its rho."""
+    for name, g in _tail_cases():
+        off, adj = (g.offsets, g.adj) if g is not None else G.hcns(120)
+        want, sub, ls = oracle.levelsync(off, adj)
+        for tail in (1, 2, 64, 1000, 1 << 30):
+            for resid in (-1, 0, 1 << 30):
+                say(f"[gpu] tail {name} mode={mode} tail={tail} residual={resid}")
+                got, st = run_single(off, adj, mode=mode, tail=tail, residual=resid)
+                assert not first_mismatch(got, want), first_mismatch(got, want)
+                assert st["peeled"] == len(off) - 1 and st["edges"] == len(adj), st
+                assert st["device_status"] == 0 and st["kmax"] == int(want.max())
+                assert st["rounds"] == ls["nonempty_rounds"], (st, ls)
+                if mode == "levelsync":
+                    assert st["subrounds"] == ls["subrounds"], (st, ls)
+
+
+def test_tail_handoff_called_off(monkeypatch):
+    """A handoff whose local rows do not fit is called off and retried when half as many
+    vertices are live (or never happens): the grid keeps peeling and the result is unchanged."""
+    for name, g in _tail_cases():
+        off, adj = (g.offsets, g.adj) if g is not None else G.hcns(120)
+        want = oracle.bz(off, adj)
+        for ecap in (0, 50, 2000):
+            monkeypatch.setenv("KCORE_DEBUG_TAIL_ECAP", str(ecap))
+            say(f"[gpu] tail called off {name} ecap={ecap}")
+            got, st = run_single(off, adj, mode="chained")
+            assert not first_mismatch(got, want), first_mismatch(got, want)
+            assert st["peeled"] == len(off) - 1 and st["edges"] == len(adj), st
+            assert st["device_status"] == 0
+    monkeypatch.delenv("KCORE_DEBUG_TAIL_ECAP")
 
 
 @pytest.mark.parametrize("mode", MODES)
