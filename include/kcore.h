@@ -119,7 +119,9 @@ typedef struct {
   int32_t kmax;            /* largest coreness */
   int32_t device_status;   /* 0, or internal failure bits */
   float ms;                /* device time of the call in milliseconds */
-  int32_t reserved[5];
+  int32_t tail_vertices;   /* vertices peeled by the single-workgroup tail (0 = no handoff); its
+                              decrements are LDS operations and not counted in `decrements` */
+  int32_t reserved[4];
 } kcore_stats;
 
 /* Single graph. n == 0 is a no-op; adj may be null when offsets[n] == 0; KCORE_ETOOBIG when

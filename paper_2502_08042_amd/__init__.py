@@ -58,7 +58,7 @@ class Stats(ctypes.Structure):
                 ("edges", ctypes.c_int64), ("decrements", ctypes.c_int64),
                 ("combined", ctypes.c_int64), ("scanned", ctypes.c_int64),
                 ("kmax", ctypes.c_int32), ("device_status", ctypes.c_int32),
-                ("ms", ctypes.c_float), ("reserved", ctypes.c_int32 * 5)]
+                ("ms", ctypes.c_float), ("tail_vertices", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}

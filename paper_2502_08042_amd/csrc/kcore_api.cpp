@@ -280,6 +280,7 @@ void fill_stats(kcore_stats* st, const unsigned long long* hs, unsigned status, 
   st->combined = (int64_t)hs[kc::ST_COMBINED];
   st->scanned = (int64_t)hs[kc::ST_SCANNED];
   st->kmax = (int32_t)hs[kc::ST_KMAX];
+  st->tail_vertices = (int32_t)hs[kc::ST_TAIL];
   st->device_status = (int32_t)status;
   st->ms = ms;
 }

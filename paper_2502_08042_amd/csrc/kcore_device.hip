@@ -2048,16 +2048,17 @@ __global__ __launch_bounds__(kTailThreads) void tail_kernel(PeelArgs a, int32_t 
     if (tail >= L) break;
     k = k + 1;
   }
-  // statistics: the tail's share of the decomposition's counters (every entry is one LDS decrement)
+  // statistics: the tail's share of the decomposition's counters (its decrements are LDS
+  // operations, not counted with the global ones)
   long long v5[2] = {st_edges, st_scanned};
   for (int qd = 0; qd < 2; ++qd) {
     long long x = v5[qd];
     for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
     if (l == 0 && x) aadd(&a.ctl->stats[qd == 0 ? ST_EDGES : ST_SCANNED], (unsigned long long)x);
-    if (l == 0 && x && qd == 0) aadd(&a.ctl->stats[ST_DECR], (unsigned long long)x);
   }
   if (tid == 0) {
     aadd(&a.ctl->stats[ST_PEELED], (unsigned long long)L);
+    ast(&a.ctl->stats[ST_TAIL], (unsigned long long)L);
     if (st_rounds) aadd(&a.ctl->stats[ST_ROUNDS], (unsigned long long)st_rounds);
     if (st_sub) aadd(&a.ctl->stats[ST_SUBROUNDS], (unsigned long long)st_sub);
     __hip_atomic_fetch_max(&a.ctl->stats[ST_KMAX], (unsigned long long)kmax, __ATOMIC_RELAXED,

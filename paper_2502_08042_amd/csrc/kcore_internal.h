@@ -30,7 +30,7 @@ constexpr int kTailTile = 1024;       //   ... of this many entries (4 16-byte l
 
 enum StatIdx {
   ST_ROUNDS = 0, ST_SUBROUNDS, ST_BARRIERS, ST_PEELED, ST_EDGES, ST_DECR, ST_COMBINED, ST_SCANNED,
-  ST_KMAX, ST_NUM
+  ST_KMAX, ST_TAIL, ST_NUM
 };
 
 // Counters produced during one phase (three-way rotation, see the peel kernel).
