@@ -93,10 +93,11 @@ def bench_single(args):
     value = m / (ms_step / 1000.0) / 1e9
     B = alg_bytes(n, m, st)
     achieved = B / (avg_ms / 1000.0) / 1e9
-    # HBM bytes per launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs (calibrated against a
-    # plain copy), valid only for the kernel source they were taken on
+    # HBM bytes per decomposition (peel kernel + tail kernel) from the rocprofv3 FETCH_SIZE /
+    # WRITE_SIZE runs (calibrated against a plain copy), valid only for the kernel source they were
+    # taken on
     traffic = None
-    tfile = os.path.join(ROOT, "profiles", f"peel_kernel_{args.workload}_traffic.txt")
+    tfile = os.path.join(ROOT, "profiles", f"peel_kernels_{args.workload}_traffic.txt")
     if os.path.exists(tfile):
         with open(tfile) as f:
             tj = json.load(f)
@@ -109,10 +110,13 @@ def bench_single(args):
         "data": "synthetic",
         "config": {"workload": desc, "n": n, "m": m, "mode": args.mode,
                    "kmax": st["kmax"], "rounds": st["rounds"], "subrounds": st["subrounds"],
-                   "barriers": st["barriers"]},
+                   "barriers": st["barriers"], "tail_vertices": st["tail_vertices"]},
+        # one decomposition = the persistent peel kernel, then the single-workgroup tail kernel on
+        # the last live vertices (plus two tiny set-up kernels), all inside the events
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
                      "traffic": traffic, "alg_bytes_per_launch": B,
+                     "kernel": "peel_kernel + tail_kernel",
                      "kernel_ms_per_launch": round(avg_ms, 4)},
     }
     if not args.no_cpu_baseline:
