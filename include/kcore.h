@@ -99,9 +99,11 @@ typedef struct {
                             form the k-core of that round, whose coreness is the same inside it
                             as in the whole graph), one workgroup finishes the decomposition on
                             them with their induced degrees in LDS, so the last, small rounds
-                            synchronise at workgroup level instead of grid-wide; costs 4 bytes
-                            per vertex plus min(m, tail^2) entries of workspace; capped at what
-                            the workgroup's LDS holds; 0 = that cap, -1 = never */
+                            synchronise at workgroup level instead of grid-wide (the k-core
+                            query never hands over); costs 4 bytes per vertex plus
+                            min(m, tail^2) entries of workspace; capped at what the workgroup's
+                            LDS holds at 8 bytes per vertex (17,408 on a 160 KB-LDS device);
+                            0 = that cap, -1 = never */
 } kcore_options;
 
 /* Counters of one decomposition (filled when a kcore_stats* is passed; that call synchronises

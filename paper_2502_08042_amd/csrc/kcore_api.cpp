@@ -445,7 +445,9 @@ static int peel_impl(const int64_t* offsets, const int32_t* adj, int64_t n, int3
 
 // Debugging aid, not part of kcore.h: copies the phase timeline of the last single-graph call on
 // `stream` (rows of eight: start, work done, flushed, barrier passed in 100 MHz ticks, then the
-// phase kind word, frontier vertices, hub tiles and active-set size). Synchronises.
+// phase kind word, frontier vertices, hub tiles and active-set size; from row 8192 on, one row per
+// round of the tail kernel: start, first frontier extracted, round peeled, -, k, first frontier
+// size, vertices peeled so far). Synchronises.
 int kcore_debug_trace(hipStream_t stream, unsigned long long* out, int max_phases) {
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
