@@ -53,10 +53,18 @@ typedef enum {
   KCORE_MODE_LEVELSYNC = 1, /* Alg. 1 + Alg. 3 literally: one grid-wide barrier per subround; the
                                frontiers, and so the subround count rho (Sec. 3.2, span analysis),
                                equal those of the sequential framework */
-  KCORE_MODE_CHAINED = 2    /* vertices that drop to k inside a round are peeled in the same
+  KCORE_MODE_CHAINED = 2,   /* vertices that drop to k inside a round are peeled in the same
                                pass by whichever workgroup finds them, without waiting for a
                                barrier (the idea of vertical granularity control, Sec. 4.2);
                                one grid-wide barrier per round */
+  KCORE_MODE_SAMPLING = 3   /* chained, with the sampling scheme of Sec. 4.1 (Alg. 4/5) for
+                               vertices of degree above 1024 instead of LDS combining: removing a
+                               neighbour counts a hit with probability mu / (0.9 d*) instead of
+                               decrementing, sampled vertices are validated and recounted at round
+                               boundaries; a sampled vertex found below k there voids the run,
+                               which is repeated in chained mode (the result is always exact).
+                               The call then synchronises `stream`. No tail handoff, no residual
+                               rows; at most 2^30 vertices; not for kcore_kcore_subgraph */
 } kcore_mode;
 
 typedef struct {
@@ -123,7 +131,10 @@ typedef struct {
   float ms;                /* device time of the call in milliseconds */
   int32_t tail_vertices;   /* vertices peeled by the single-workgroup tail (0 = no handoff); its
                               decrements are LDS operations and not counted in `decrements` */
-  int32_t reserved[4];
+  int32_t sampled_vertices;/* sampling mode: vertices that started in sample mode */
+  int32_t sample_recounts; /* sampling mode: validations that recounted a vertex's live degree */
+  int32_t sample_restarts; /* sampling mode: 1 if the sampled run failed and was repeated */
+  int32_t reserved[1];
 } kcore_stats;
 
 /* Single graph. n == 0 is a no-op; adj may be null when offsets[n] == 0; KCORE_ETOOBIG when

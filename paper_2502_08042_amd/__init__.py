@@ -33,7 +33,7 @@ LIB_PATH = os.path.join(_HERE, "libkcore.so")
 KCORE_OK, KCORE_PENDING = 0, 1
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ETOOBIG", -5: "ENOTFOUND",
           -6: "ECANCELED", -7: "EBADGRAPH"}
-MODES = {"auto": 0, "levelsync": 1, "chained": 2}
+MODES = {"auto": 0, "levelsync": 1, "chained": 2, "sampling": 3}
 
 
 class KcoreError(RuntimeError):
@@ -58,7 +58,9 @@ class Stats(ctypes.Structure):
                 ("edges", ctypes.c_int64), ("decrements", ctypes.c_int64),
                 ("combined", ctypes.c_int64), ("scanned", ctypes.c_int64),
                 ("kmax", ctypes.c_int32), ("device_status", ctypes.c_int32),
-                ("ms", ctypes.c_float), ("tail_vertices", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+                ("ms", ctypes.c_float), ("tail_vertices", ctypes.c_int32),
+                ("sampled_vertices", ctypes.c_int32), ("sample_recounts", ctypes.c_int32),
+                ("sample_restarts", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -89,6 +90,16 @@ struct PeelWs {
   int32_t* tgid = nullptr;   //   local id -> id (l_cap)
   long long* trow = nullptr; //   local rows (2 l_cap)
   int32_t* tadj = nullptr;   //   their entries (e_cap)
+  // sampling mode (allocated on first use): srate, scnt, sbase, scount (uint32[s_cap] each),
+  // scand, srl (int32[s_cap] each)
+  void* sblock = nullptr;
+  int64_t s_cap = -1;
+  uint32_t* srate = nullptr;
+  uint32_t* scnt = nullptr;
+  uint32_t* sbase = nullptr;
+  uint32_t* scount = nullptr;
+  int32_t* scand = nullptr;
+  int32_t* srl = nullptr;
   kc::PeelCtl* ctl = nullptr;
   unsigned long long* host_stats = nullptr;  // pinned
   unsigned* vstat = nullptr;                 // validation status + xor sum (device)
@@ -194,6 +205,33 @@ int peel_ws(int dev, hipStream_t s, int64_t n, int64_t tcap, int64_t rcap, int64
   return KCORE_OK;
 }
 
+// Sampling-mode arrays of a single-graph workspace, grown to n vertices.
+int sample_ws(PeelWs* w, hipStream_t s, int64_t n) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (w->s_cap >= n) return KCORE_OK;
+  if (w->sblock) {
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipFree(w->sblock));
+    w->sblock = nullptr;
+    w->s_cap = -1;
+  }
+  const size_t each = align_up(4 * (size_t)n);
+  hipError_t e = hipMalloc(&w->sblock, 6 * each);
+  if (e != hipSuccess) {
+    w->sblock = nullptr;
+    return fail(KCORE_ENOMEM, "sampling workspace of %zu bytes: %s", 6 * each, hipGetErrorString(e));
+  }
+  char* b = static_cast<char*>(w->sblock);
+  w->srate = (uint32_t*)b;
+  w->scnt = (uint32_t*)(b + each);
+  w->sbase = (uint32_t*)(b + 2 * each);
+  w->scount = (uint32_t*)(b + 3 * each);
+  w->scand = (int32_t*)(b + 4 * each);
+  w->srl = (int32_t*)(b + 5 * each);
+  w->s_cap = n;
+  return KCORE_OK;
+}
+
 int batch_ws(int dev, hipStream_t s, int64_t V, int32_t G, BatchWs*& out) {
   std::lock_guard<std::mutex> lk(g_mu);
   BatchWs*& w = g_batch[Key(dev, s)];
@@ -242,7 +280,7 @@ int batch_ws(int dev, hipStream_t s, int64_t V, int32_t G, BatchWs*& out) {
 
 int check_opts(const kcore_options* o) {
   if (!o) return KCORE_OK;
-  if (o->mode < 0 || o->mode > 2) return fail(KCORE_EINVAL, "mode %d unknown", o->mode);
+  if (o->mode < 0 || o->mode > 3) return fail(KCORE_EINVAL, "mode %d unknown", o->mode);
   if (o->blocks_per_cu < 0 || o->hub_degree < 0 || o->num_entries < 0 || o->local_budget < 0 ||
       o->tile_edges < 0 || (o->tile_edges % 64) != 0 || o->tile_edges > 32768)
     return fail(KCORE_EINVAL, "negative option, or tile_edges not a multiple of 64 up to 32768");
@@ -281,6 +319,8 @@ void fill_stats(kcore_stats* st, const unsigned long long* hs, unsigned status, 
   st->scanned = (int64_t)hs[kc::ST_SCANNED];
   st->kmax = (int32_t)hs[kc::ST_KMAX];
   st->tail_vertices = (int32_t)hs[kc::ST_TAIL];
+  st->sampled_vertices = (int32_t)hs[kc::ST_SAMPLED];
+  st->sample_recounts = (int32_t)hs[kc::ST_RECOUNTS];
   st->device_status = (int32_t)status;
   st->ms = ms;
 }
@@ -314,6 +354,10 @@ static int peel_impl(const int64_t* offsets, const int32_t* adj, int64_t n, int3
   if (int rc = dev_info(dev, di)) return rc;
 
   const int mode = (opt && opt->mode) ? opt->mode : KCORE_MODE_CHAINED;
+  const bool sampling = mode == KCORE_MODE_SAMPLING;
+  if (sampling && k_query > 0) return fail(KCORE_EINVAL, "the k-core query has no sampling mode");
+  if (sampling && n > (1ll << 30))
+    return fail(KCORE_EINVAL, "sampling mode takes at most 2^30 vertices (n = %lld)", (long long)n);
   const uint32_t hub = (opt && opt->hub_degree) ? (uint32_t)opt->hub_degree : 256u;
   const int tile = (opt && opt->tile_edges) ? opt->tile_edges : 256;
   const int budget = (opt && opt->local_budget) ? opt->local_budget : 4096;
@@ -339,13 +383,14 @@ static int peel_impl(const int64_t* offsets, const int32_t* adj, int64_t n, int3
   // residual rows (rewritten without peeled neighbours once the active set is small): room for
   // half the adjacency; the rewrite happens only if the live rows fit
   const int32_t ro = opt ? opt->residual : 0;
-  const int64_t resid_vmax = ro < 0 ? -1 : (ro ? ro : std::max<int64_t>(n / 256, 4096));
+  // (sampling mode keeps the original rows: its recounts and its biased induced degrees assume them)
+  const int64_t resid_vmax = (ro < 0 || sampling) ? -1 : (ro ? ro : std::max<int64_t>(n / 256, 4096));
   const int64_t rcap = resid_vmax < 0 ? 0 : m / 2 + 64;
 
   // tail handoff: the last live vertices (at most what the tail peel's LDS holds) are peeled by
   // one workgroup; their local rows hold at most min(m, L (L - 1)) entries (simple graph)
   const int32_t to = opt ? opt->tail : 0;
-  int64_t tail_vmax = (to < 0 || k_query > 0) ? 0 : std::min<int64_t>(to ? to : di.tail_lcap, di.tail_lcap);
+  int64_t tail_vmax = (to < 0 || k_query > 0 || sampling) ? 0 : std::min<int64_t>(to ? to : di.tail_lcap, di.tail_lcap);
   tail_vmax = std::min<int64_t>(tail_vmax, n);
   // (plus up to 3 pad entries per row: rows start on 16-byte boundaries)
   const int64_t tail_ecap =
@@ -385,7 +430,7 @@ static int peel_impl(const int64_t* offsets, const int32_t* adj, int64_t n, int3
   a.hub = hub;
   a.comb_degree = hub > 1024u ? hub : 1024u;
   a.tile = tile;
-  a.chained = mode == KCORE_MODE_CHAINED ? 1 : 0;
+  a.chained = (mode == KCORE_MODE_CHAINED || sampling) ? 1 : 0;
   a.lq_budget = budget;
   a.big_phase = 16384;
   a.aq = w->aq;
@@ -415,6 +460,33 @@ static int peel_impl(const int64_t* offsets, const int32_t* adj, int64_t n, int3
   // testing aid: KCORE_DEBUG_TAIL_ECAP=e pretends the local rows hold only e entries, so that
   // handoffs are called off and retried
   if (const char* te = getenv("KCORE_DEBUG_TAIL_ECAP")) a.tail_ecap = std::min<int64_t>(tail_ecap, atoll(te));
+  a.sampling = sampling ? 1 : 0;
+  a.s_threshold = a.s_mu = a.s_seed = 0;
+  a.srate = a.scnt = a.sbase = a.scount = nullptr;
+  a.scand = a.srl = nullptr;
+  if (sampling) {
+    if (int rc = sample_ws(w, stream, n)) return rc;
+    a.srate = w->srate;
+    a.scnt = w->scnt;
+    a.sbase = w->sbase;
+    a.scount = w->scount;
+    a.scand = w->scand;
+    a.srl = w->srl;
+    // Alg. 5's parameters: mu = 4 (c + 2) ln n with c = 1, so that the scheme is correct with
+    // probability at least 1 - 1/n (a failure is detected and answered by a second run), at least
+    // 16; vertices of degree above 1024 start in sample mode. Testing aid:
+    // KCORE_DEBUG_SAMPLE="threshold,mu" overrides both.
+    a.s_mu = (uint32_t)std::max(16.0, std::ceil(12.0 * std::log((double)std::max<int64_t>(n, 2))));
+    a.s_threshold = 1024;
+    if (const char* ds = getenv("KCORE_DEBUG_SAMPLE")) {
+      unsigned th = 0, mu = 0;
+      if (sscanf(ds, "%u,%u", &th, &mu) == 2 && mu > 0) {
+        a.s_threshold = th;
+        a.s_mu = mu;
+      }
+    }
+    a.s_seed = 0x2545f491u;
+  }
   // debugging aid: KCORE_DEBUG_PHASE=p records every workgroup's timing in phases [p, p + 64)
   const char* dp = getenv("KCORE_DEBUG_PHASE");
   a.dbg_lo = dp ? atoll(dp) : -1;
@@ -422,6 +494,9 @@ static int peel_impl(const int64_t* offsets, const int32_t* adj, int64_t n, int3
 
   HIP_TRY(kc::launch_init_ctl(w->ctl, stream));
   if (a.chained) HIP_TRY(kc::launch_fill_u32(w->aq, 0xffffffffu, 2 * (size_t)w->q_cap, stream));
+  // sampling mode reads its outcome back before returning (a failed sampling run is repeated)
+  kcore_stats local_stats;
+  if (sampling && !stats_host) stats_host = &local_stats;
   if (stats_host) HIP_TRY(hipEventRecord(w->ev0, stream));
   HIP_TRY(kc::launch_peel(a, blocks, stream));
   if (tail_vmax > 0) HIP_TRY(kc::launch_tail(a, (int32_t)tail_vmax, stream));
@@ -437,6 +512,22 @@ static int peel_impl(const int64_t* offsets, const int32_t* adj, int64_t n, int3
   float ms = 0;
   HIP_TRY(hipEventElapsedTime(&ms, w->ev0, w->ev1));
   fill_stats(stats_host, w->host_stats, status, ms);
+  if (sampling && status == kc::KC_ERR_SAMPLE) {
+    // a sampled vertex was caught below k at a round boundary: the result of this run is void;
+    // peel again without sampling (the scheme's answer to its rare failure, so it stays exact)
+    const kcore_stats first = *stats_host;
+    kcore_options o2;
+    memset(&o2, 0, sizeof o2);
+    if (opt) o2 = *opt;
+    o2.mode = KCORE_MODE_CHAINED;
+    o2.num_entries = m;
+    const int rc = peel_impl(offsets, adj, n, coreness_out, stream, &o2, stats_host, k_query);
+    stats_host->sampled_vertices = first.sampled_vertices;
+    stats_host->sample_recounts = first.sample_recounts;
+    stats_host->sample_restarts = 1;
+    stats_host->ms += first.ms;
+    return rc;
+  }
   if (status)
     return fail(KCORE_EDEVICE, "device reported failure bits 0x%x (diag %llu %llu %llu %llu)", status,
                 w->host_stats[12], w->host_stats[13], w->host_stats[14], w->host_stats[15]);
@@ -606,6 +697,8 @@ static int batched_impl(const int64_t* graph_vptr, const int64_t* offsets, const
   a.lds_cap = cap;
   // barrier-separated subrounds by default: inside one workgroup a barrier is cheap, and peeling a
   // whole frontier edge-balanced over all 512 threads beats 64-vertex packets claimed per wave
+  if (opt && opt->mode == KCORE_MODE_SAMPLING)
+    return fail(KCORE_EINVAL, "the batched peel has no sampling mode (its degrees live in LDS)");
   a.chained = (opt && opt->mode == KCORE_MODE_CHAINED) ? 1 : 0;
   if (stats_host) HIP_TRY(hipEventRecord(w->ev0, stream));
   HIP_TRY(kc::launch_batched(a, blocks, lds, stream));

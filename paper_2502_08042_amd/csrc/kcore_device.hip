@@ -399,6 +399,65 @@ __device__ __forceinline__ void push_vertices(const PeelArgs& a, WaveCtx& c, con
   }
 }
 
+// ------------------------------------------------------------------------------------------
+// Sampling mode (Sec. 4.1, Alg. 4/5). A vertex of degree above s_threshold starts in sample mode:
+// bit 30 of its induced degree is set (so no decrement ever takes it to k and no scan extracts it)
+// and the "hot" bits of the state words mark it. Removing one of its neighbours then increments its
+// hit count with probability rate = mu / ((1 - r) d*), r = 1/10, instead of decrementing it: in
+// large phases, where the state word is read anyway, no atomic is spent on its induced degree;
+// in small ones the decrement lands on the biased value and is ignored. Validation (Error of
+// Alg. 5) and recounts run at round boundaries, where no expansion is pending, so a recount from
+// the peeled bits is exact; a vertex found below k there was missed in an earlier round, which
+// the host answers by peeling again without sampling (the scheme stays exact).
+// ------------------------------------------------------------------------------------------
+constexpr uint32_t SAMPLEBIT = 0x40000000u;
+
+// Hit threshold on a uniform 32-bit draw for the rate mu / ((1 - r) d), r = 1/10.
+__device__ __forceinline__ uint32_t sample_rate32(uint32_t mu, uint32_t d) {
+  const double rate = (double)mu / (0.9 * (double)d);
+  return rate >= 1.0 ? 0xffffffffu : (uint32_t)(rate * 4294967296.0);
+}
+
+// Smallest round k at which Error (Alg. 5) fails for a vertex with induced degree b at its last
+// (re)initialisation, hit threshold thr and cnt hits: d* r <= k, or cnt >= rate (d* - k) / 4, i.e.
+// k >= d* - 4 cnt / rate. Rounded down (validated early rather than late); 0 once mu hits are in.
+__device__ __forceinline__ uint32_t sample_valk(uint32_t b, uint32_t thr, uint32_t cnt, uint32_t mu) {
+  if (cnt >= mu || thr == 0u) return 0u;
+  const uint32_t k1 = (b + 9u) / 10u;
+  const unsigned long long t = ((((unsigned long long)cnt) << 34) + thr - 1u) / thr;  // ceil(4 cnt / rate)
+  const uint32_t k2 = t >= b ? 0u : b - (uint32_t)t;
+  return k1 < k2 ? k1 : k2;
+}
+
+// Error (Alg. 5) at round k: true while the vertex may stay in sample mode.
+__device__ __forceinline__ bool sample_safe(uint32_t b, uint32_t thr, uint32_t cnt, uint32_t k) {
+  if ((unsigned long long)b <= 10ull * k) return false;
+  return ((unsigned long long)cnt << 34) < (unsigned long long)thr * (unsigned long long)(b - k);
+}
+
+// The coin: murmur3's 32-bit finaliser over the seed, the lane's global index and its count of
+// entries processed so far (a distinct counter value for every removal the lane handles).
+__device__ __forceinline__ uint32_t sample_coin(uint32_t seed, uint32_t lane, uint32_t ctr) {
+  uint32_t h = seed ^ (lane * 0x9e3779b1u) ^ (ctr * 0x85ebca77u);
+  h ^= h >> 16;
+  h *= 0x85ebca6bu;
+  h ^= h >> 13;
+  h *= 0xc2b2ae35u;
+  h ^= h >> 16;
+  return h;
+}
+
+// One removal of a neighbour of sampled vertex u: a hit with the vertex's rate; a hit moves the
+// round of its next validation forward when needed.
+__device__ __forceinline__ void sample_hit(const PeelArgs& a, const WaveCtx& c, int32_t u) {
+  const uint32_t thr = ald(&a.srate[u]);
+  const uint32_t gl = blockIdx.x * blockDim.x + threadIdx.x;
+  if (sample_coin(a.s_seed, gl, (uint32_t)c.edges) >= thr) return;
+  const uint32_t cnt = aadd(&a.scnt[u], 1u) + 1u;
+  const uint32_t kb = sample_valk(ald(&a.sbase[u]), thr, cnt, a.s_mu);
+  if (kb < ald(&a.ctl->s_valk)) amin(&a.ctl->s_valk, kb);
+}
+
 // Up to U adjacency entries per lane: the online decrement of Alg. 3. All loads, and
 // then all atomics, of a lane are issued before any result is used, so one pass costs a few memory
 // round trips however many entries it covers. In large phases (c.precheck) a neighbour whose
@@ -406,7 +465,7 @@ __device__ __forceinline__ void push_vertices(const PeelArgs& a, WaveCtx& c, con
 // latency-bound phases the probe is skipped (decrementing a peeled vertex is harmless: it can
 // never cross k again, and each neighbour decrements it once, so it never drops below zero).
 // The lane whose decrement takes u from k+1 to k pushes it.
-template <int U>
+template <bool S, int U>
 __device__ __forceinline__ void edges_batch(const PeelArgs& a, WaveCtx& c, const PhaseOut& o,
                                             const int32_t (&u)[U], unsigned valid, uint32_t k) {
   uint32_t sw[U];
@@ -425,15 +484,29 @@ __device__ __forceinline__ void edges_batch(const PeelArgs& a, WaveCtx& c, const
     if (!((valid >> j) & 1u)) continue;
     c.edges += 1;
     if ((sw[j] >> (u[j] & 15)) & 1u) continue;  // already peeled
-    // hub targets collect their decrements in LDS for the rest of the phase (the flush applies
-    // them with one atomic per target); everything else is decremented right away
-    if (c.combine && ((sw[j] >> (16 + (u[j] & 15))) & 1u) && comb_add(c, u[j])) {
-      c.comb += 1;
-      continue;
+    if constexpr (S) {
+      // sampling mode: the state word marks sampled targets (large phases read it anyway)
+      if ((sw[j] >> (16 + (u[j] & 15))) & 1u) {
+        sample_hit(a, c, u[j]);
+        continue;
+      }
+    } else {
+      // hub targets collect their decrements in LDS for the rest of the phase (the flush applies
+      // them with one atomic per target); everything else is decremented right away
+      if (c.combine && ((sw[j] >> (16 + (u[j] & 15))) & 1u) && comb_add(c, u[j])) {
+        c.comb += 1;
+        continue;
+      }
     }
     old[j] = asub(&a.dt[u[j]], 1u);
     c.decr += 1;
     did |= 1u << j;
+  }
+  if constexpr (S) {
+    // a decrement that landed on a sampled vertex (small phases do not read the state word)
+#pragma unroll
+    for (int j = 0; j < U; ++j)
+      if (((did >> j) & 1u) && (old[j] & SAMPLEBIT)) sample_hit(a, c, u[j]);
   }
 #pragma unroll
   for (int j = 0; j < U; ++j) {
@@ -460,6 +533,7 @@ __device__ __forceinline__ void edges_batch(const PeelArgs& a, WaveCtx& c, const
 // Expands the rows of up to 64 vertices (one per lane, -1 = none) edge-balanced across the wave:
 // an exclusive scan of the degrees, then each lane finds the row of each of its entries by binary
 // search over the scan.
+template <bool S>
 __device__ __forceinline__ void expand_rows(const PeelArgs& a, WaveCtx& c, const PhaseOut& o, int32_t v, uint32_t k) {
   long long b = 0, d = 0;
   if (v >= 0) row_of(a, c, v, b, d);
@@ -487,11 +561,12 @@ __device__ __forceinline__ void expand_rows(const PeelArgs& a, WaveCtx& c, const
         valid |= 1u << q;
       }
     }
-    edges_batch(a, c, o, u, valid, k);
+    edges_batch<S>(a, c, o, u, valid, k);
   }
 }
 
 // A hub tile: adjacency entries [pos, pos + len), len <= 64 * kTileUnroll for default tiles.
+template <bool S>
 __device__ __forceinline__ void expand_span(const PeelArgs& a, WaveCtx& c, const PhaseOut& o, long long pos,
                                             long long len, uint32_t k) {
   // hub rows mostly point at vertices peeled long ago: probe the peeled bits here (in every phase
@@ -512,18 +587,19 @@ __device__ __forceinline__ void expand_span(const PeelArgs& a, WaveCtx& c, const
         valid |= 1u << q;
       }
     }
-    edges_batch(a, c, o, u, valid, k);
+    edges_batch<S>(a, c, o, u, valid, k);
   }
   c.precheck = saved;
 }
 
 // Tile j of the row of v (async queue entries name the vertex).
+template <bool S>
 __device__ __forceinline__ void expand_tile(const PeelArgs& a, WaveCtx& c, const PhaseOut& o, int32_t v, int32_t j,
                                             uint32_t k) {
   long long rb = 0, d = 0;
   row_of(a, c, v, rb, d);
   const long long b = rb + (long long)j * a.tile;
-  expand_span(a, c, o, b, min(rb + d, b + a.tile) - b, k);
+  expand_span<S>(a, c, o, b, min(rb + d, b + a.tile) - b, k);
 }
 
 // Applies the block's combined decrements: one atomic subtraction of c per target; exactly one
@@ -559,6 +635,7 @@ __device__ __forceinline__ void comb_flush(const PeelArgs& a, WaveCtx& c, const 
 
 // Chained mode: peel what the wave queued locally, in packets of up to 64 vertices, until the
 // queue is empty or the wave's budget for this phase is spent; what is left joins the frontier.
+template <bool S>
 __device__ __forceinline__ void drain_local(const PeelArgs& a, WaveCtx& c, const PhaseOut& o, uint32_t k) {
   while (c.lq_cnt > 0 && c.lq_used < a.lq_budget) {
     const int take = c.lq_cnt < 64 ? c.lq_cnt : 64;
@@ -567,7 +644,7 @@ __device__ __forceinline__ void drain_local(const PeelArgs& a, WaveCtx& c, const
     c.lq_cnt -= take;
     c.lq_used += take;
     if (lane_id() == 0) atomicAdd(&c.bqc[5], take);
-    expand_rows(a, c, o, v, k);
+    expand_rows<S>(a, c, o, v, k);
   }
   while (c.lq_cnt > 0) {
     const int take = c.lq_cnt < 64 ? c.lq_cnt : 64;
@@ -588,6 +665,7 @@ __device__ __forceinline__ void drain_local(const PeelArgs& a, WaveCtx& c, const
 // busy wave (busy first) and then no unclaimed slot: entries are only reserved by busy waves, and a
 // wave that reserved entries stays until it sees them claimed, so no entry is left behind. Waits
 // are bounded.
+template <bool S>
 __device__ __forceinline__ void block_loop(const PeelArgs& a, WaveCtx& c, const PhaseOut& o, uint32_t k) {
   int* head = &c.bqc[0];
   int* tail = &c.bqc[1];
@@ -643,8 +721,8 @@ __device__ __forceinline__ void block_loop(const PeelArgs& a, WaveCtx& c, const 
     if (state != 1) return;
     e = __shfl(e, 0, 64);
     if (e == kQSkip) continue;
-    expand_span(a, c, o, (long long)((unsigned long long)e >> 16), e & 0xffff, k);
-    drain_local(a, c, o, k);
+    expand_span<S>(a, c, o, (long long)((unsigned long long)e >> 16), e & 0xffff, k);
+    drain_local<S>(a, c, o, k);
   }
 }
 
@@ -655,14 +733,15 @@ __device__ __forceinline__ void block_loop(const PeelArgs& a, WaveCtx& c, const 
 // (read after done) nothing is left in flight and nothing more can be created. Only wave 0 of a
 // workgroup polls those shared counters (and publishes the outcome in LDS for its siblings), so
 // waiting waves do not slow down the atomics of working ones. Waits are bounded.
+template <bool S>
 __device__ __forceinline__ void async_loop(const PeelArgs& a, WaveCtx& c, const PhaseOut& o, uint32_t k,
                                            volatile int* s_quiet) {
-  PhaseSlot* S = o.slot;
+  PhaseSlot* PS = o.slot;
   const unsigned nb = gridDim.x;
   const bool watcher = (threadIdx.x >> 6) == 0;
   for (;;) {
     unsigned long long idx = 0;
-    if (lane_id() == 0) idx = aadd(&S->qhead, 1ull);
+    if (lane_id() == 0) idx = aadd(&PS->qhead, 1ull);
     idx = __shfl(idx, 0, 64);
     long long e = kQEmpty;
     int state = 0;  // 0 waiting, 1 got entry, 2 quiescent, 3 error
@@ -682,9 +761,9 @@ __device__ __forceinline__ void async_loop(const PeelArgs& a, WaveCtx& c, const 
           break;
         }
         if (watcher) {
-          if (ald(&S->bdone) >= nb) {
-            const unsigned long long dn = ald(&S->qdone);
-            const unsigned long long tl = ald(&S->qtail);
+          if (ald(&PS->bdone) >= nb) {
+            const unsigned long long dn = ald(&PS->qdone);
+            const unsigned long long tl = ald(&PS->qtail);
             if (dn == tl && (long long)idx >= (long long)tl) {
               *s_quiet = 2;
               state = 2;
@@ -714,17 +793,18 @@ __device__ __forceinline__ void async_loop(const PeelArgs& a, WaveCtx& c, const 
     const uint32_t j = (uint32_t)((unsigned long long)e >> 32);
     c.lq_used = 0;
     if (j == kWholeRow)
-      expand_rows(a, c, o, lane_id() == 0 ? v : -1, k);
+      expand_rows<S>(a, c, o, lane_id() == 0 ? v : -1, k);
     else
-      expand_tile(a, c, o, v, (int32_t)j, k);
-    if (a.chained) drain_local(a, c, o, k);
+      expand_tile<S>(a, c, o, v, (int32_t)j, k);
+    if (a.chained) drain_local<S>(a, c, o, k);
     __builtin_amdgcn_s_waitcnt(0);
-    if (lane_id() == 0) aadd(&S->qdone, 1ull);
+    if (lane_id() == 0) aadd(&PS->qdone, 1ull);
   }
 }
 
-enum PhaseKind { PH_SCAN = 0, PH_EXPAND = 1, PH_ASYNC = 2, PH_RESIDUAL = 3, PH_TAIL = 4 };
+enum PhaseKind { PH_SCAN = 0, PH_EXPAND = 1, PH_ASYNC = 2, PH_RESIDUAL = 3, PH_TAIL = 4, PH_SAMPLE = 5 };
 
+template <bool S>
 __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
   __shared__ int32_t s_sf[kWaves][kStage];
   __shared__ int32_t s_sa[kWaves][kStage];
@@ -796,8 +876,25 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
         if (v >= n) break;
         const long long d = a.off[v + 1] - a.off[v];
         const bool hub = d >= (long long)a.hub;        // rows split into tiles when peeled
-        const bool hot = d >= (long long)a.comb_degree;  // decrements combined in LDS
-        ast(&a.dt[v], (uint32_t)d | (hub ? HUBBIT : 0u));
+        bool hot = d >= (long long)a.comb_degree;      // decrements combined in LDS
+        uint32_t sbit = 0u;
+        if constexpr (S) {
+          // InitSampler (Alg. 5) at k = 0: sample mode for degrees above the threshold; the hot
+          // bit then marks sampled vertices (there is no LDS combining in this mode)
+          hot = d > (long long)a.s_threshold;
+          if (hot) {
+            const uint32_t thr = sample_rate32(a.s_mu, (uint32_t)d);
+            ast(&a.srate[v], thr);
+            ast(&a.scnt[v], 0u);
+            ast(&a.sbase[v], (uint32_t)d);
+            const uint32_t slot = aadd(&C->s_ncand, 1u);
+            ast(&a.scand[slot], (int32_t)v);
+            const uint32_t kb = sample_valk((uint32_t)d, thr, 0u, a.s_mu);
+            if (kb < ald(&C->s_valk)) amin(&C->s_valk, kb);
+            sbit = SAMPLEBIT;
+          }
+        }
+        ast(&a.dt[v], (uint32_t)d | (hub ? HUBBIT : 0u) | sbit);
         bits |= (hot ? 1u : 0u) << (16 + j);
         mn = min(mn, (unsigned)d);
       }
@@ -815,12 +912,19 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
   if (!grid_sync(C, epoch)) return;
   st_bar++;
 
-  if (threadIdx.x == 0) s_out[0] = (long long)ald(&C->slot[0].minv);
+  if (threadIdx.x == 0) {
+    s_out[0] = (long long)ald(&C->slot[0].minv);
+    s_out[5] = (long long)ald(&C->s_valk);
+  }
   __syncthreads();
   // round being extracted or expanded; a k-core query runs the single round k - 1
   long long kx = a.k_query > 0 ? a.k_query - 1 : s_out[0];
-  __syncthreads();
   int kind = PH_SCAN;
+  if constexpr (S) {
+    // sampled vertices due for validation at the first round are validated before its scan
+    if (s_out[5] <= kx) kind = PH_SAMPLE;
+  }
+  __syncthreads();
   bool dense = true, compact = false;
   long long asize = n;   // items of the current active list
   long long aseg = 0;    // its segment length (segmented lists)
@@ -863,6 +967,126 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
     if (tr) C->trace[p][0] = wall_clock64();
     const bool dbg = threadIdx.x == 0 && blockIdx.x < kDbgBlocks && p >= a.dbg_lo && p < a.dbg_lo + kDbgPhases;
     if (dbg) C->dbg[p - a.dbg_lo][blockIdx.x][0] = wall_clock64();
+    if constexpr (S) {
+      if (kind == PH_SAMPLE) {
+        // Validation and recounts of the sampled vertices at the start of round kx (Alg. 4's loop
+        // over sample-mode vertices, Error and SetSampler of Alg. 5). Every expansion has landed,
+        // so a live neighbour is one whose peeled bit is clear. (1) Check each sampled vertex;
+        // those that fail are marked (rate 0) and their row tiles listed; (2) count the live
+        // entries of each listed tile; (3) re-initialise each recounted vertex (InitSampler) or
+        // return it to exact counting, and collect the round of the next validation.
+        PhaseSlot* slot = o.slot;
+        const long long ncand = (long long)ald(&C->s_ncand);
+        if (blockIdx.x == 0 && threadIdx.x == 0) ast(&C->s_valk, 0xffffffffu);  // rebuilt in (3)
+        for (long long i0 = gw * 64; i0 < ncand; i0 += W * 64) {
+          const long long i = i0 + l;
+          int32_t v = -1;
+          bool redo = false;
+          long long nt = 0;
+          if (i < ncand) {
+            v = ald(&a.scand[i]);
+            const uint32_t thr = ald(&a.srate[v]);
+            if (thr != 0u && !sample_safe(ald(&a.sbase[v]), thr, ald(&a.scnt[v]), k)) {
+              redo = true;
+              ast(&a.srate[v], 0u);
+              ast(&a.scount[v], 0u);
+              nt = (a.off[v + 1] - a.off[v] + a.tile - 1) / a.tile;
+            }
+          }
+          const unsigned long long rm = __ballot(redo);
+          if (rm == 0) continue;
+          unsigned long long rbase = 0;
+          if (l == 0) rbase = aadd(&slot->small, (unsigned long long)__popcll(rm));
+          rbase = __shfl(rbase, 0, 64);
+          const long long tincl = wave_incl_scan(nt);
+          const long long ttot = __shfl(tincl, 63, 64);
+          unsigned long long tbase = 0;
+          if (l == 0 && ttot) tbase = aadd(&slot->tiles, (unsigned long long)ttot);
+          tbase = __shfl(tbase, 0, 64);
+          if ((long long)tbase + ttot > a.qcap) {
+            if (l == 0) aor(&C->status, (unsigned)KC_ERR_OVERFLOW);
+          } else if (redo) {
+            ast(&a.srl[rbase + rank_in(rm)], v);
+            const long long t0 = (long long)tbase + tincl - nt;
+            for (long long j = 0; j < nt; ++j)
+              ast(&a.aq[t0 + j], (long long)(((unsigned long long)j << 32) | (unsigned)v));
+          }
+        }
+        if (!grid_sync(C, epoch)) break;
+        st_bar++;
+        if (threadIdx.x == 0) {
+          s_out[0] = (long long)ald(&slot->tiles);
+          s_out[1] = (long long)ald(&slot->small);
+        }
+        __syncthreads();
+        const long long ntl = s_out[0] <= a.qcap ? s_out[0] : a.qcap;
+        const long long nrl = s_out[1];
+        __syncthreads();
+        // (2) live entries of each listed tile
+        for (long long it = gw; it < ntl; it += W) {
+          const long long e = ald(&a.aq[it]);
+          const int32_t v = (int32_t)(e & 0xffffffffll);
+          const long long j = (long long)((unsigned long long)e >> 32);
+          const long long ob = a.off[v], oe = a.off[v + 1];
+          const long long b = ob + j * a.tile, en = min(oe, b + a.tile);
+          int cnt = 0;
+          for (long long q = b + l; q < en; q += 64) {
+            const int32_t u = a.adj[q];
+            cnt += ((ald(&a.state[u >> 4]) >> (u & 15)) & 1u) ? 0 : 1;
+          }
+          for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
+          if (l == 0) {
+            if (cnt) aadd(&a.scount[v], (uint32_t)cnt);
+            ast(&a.aq[it], kQEmpty);  // the async queue starts every phase empty
+          }
+        }
+        if (!grid_sync(C, epoch)) break;
+        st_bar++;
+        // (3) InitSampler for the recounted vertices; the others report their next validation
+        for (long long i = gt; i < nrl; i += GT) {
+          const int32_t v = ald(&a.srl[i]);
+          const uint32_t cnt = ald(&a.scount[v]);
+          const uint32_t hubf = (a.off[v + 1] - a.off[v]) >= (long long)a.hub ? HUBBIT : 0u;
+          if (cnt < k) {
+            // live at the start of round k with fewer than k live neighbours: it should have been
+            // peeled in an earlier round (the rare failure of the sampling scheme)
+            aor(&C->status, (unsigned)KC_ERR_SAMPLE);
+          } else if ((unsigned long long)cnt > 10ull * k && cnt > a.s_threshold) {
+            const uint32_t thr = sample_rate32(a.s_mu, cnt);
+            ast(&a.sbase[v], cnt);
+            ast(&a.scnt[v], 0u);
+            ast(&a.srate[v], thr);
+            ast(&a.dt[v], cnt | hubf | SAMPLEBIT);
+            const uint32_t kb = max(sample_valk(cnt, thr, 0u, a.s_mu), k + 1u);
+            amin(&C->s_valk, kb);
+          } else {
+            ast(&a.dt[v], cnt | hubf);
+            __hip_atomic_fetch_and(&a.state[v >> 4], ~(1u << (16 + (v & 15))), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+          }
+          aadd(&C->stats[ST_RECOUNTS], 1ull);
+        }
+        for (long long i = gt; i < ncand; i += GT) {
+          const int32_t v = ald(&a.scand[i]);
+          const uint32_t thr = ald(&a.srate[v]);
+          if (thr == 0u) continue;
+          const uint32_t kb = max(sample_valk(ald(&a.sbase[v]), thr, ald(&a.scnt[v]), a.s_mu), k + 1u);
+          if (kb < ald(&C->s_valk)) amin(&C->s_valk, kb);
+        }
+        if (tr) {
+          C->trace[p][1] = C->trace[p][2] = wall_clock64();
+          C->trace[p][4] = (unsigned long long)PH_SAMPLE | ((unsigned long long)k << 8);
+          C->trace[p][5] = (unsigned long long)nrl;
+          C->trace[p][6] = (unsigned long long)ntl;
+          C->trace[p][7] = (unsigned long long)asize;
+        }
+        if (!grid_sync(C, epoch)) break;
+        st_bar++;
+        if (tr) C->trace[p][3] = wall_clock64();
+        kind = PH_SCAN;
+        continue;
+      }
+    }
     if (kind == PH_RESIDUAL || kind == PH_TAIL) {
       // Rewrites the rows of the live vertices without their peeled neighbours. It runs at a round
       // boundary: every decrement has landed, so a live vertex's induced degree is its number of
@@ -1103,16 +1327,16 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
         if (it < npk) {
           const long long i = it * per + l;
           const int32_t v = (l < per && i < fs) ? ald(&fcur[i]) : -1;
-          expand_rows(a, c, o, v, k);
+          expand_rows<S>(a, c, o, v, k);
         } else {
           const unsigned long long sw = ald(&tcur[it - npk]);
-          expand_span(a, c, o, (long long)(sw >> 16), (long long)(sw & 0xffff), k);
+          expand_span<S>(a, c, o, (long long)(sw >> 16), (long long)(sw & 0xffff), k);
         }
       }
     }
-    if (a.chained) drain_local(a, c, o, k);
+    if (a.chained) drain_local<S>(a, c, o, k);
     if (c.bq_open) {
-      block_loop(a, c, o, k);
+      block_loop<S>(a, c, o, k);
       c.bq_open = false;
     }
     if (c.async) {
@@ -1124,14 +1348,14 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
       }
       // a few waves per workgroup take part in the dynamic part: every claim is an atomic on one
       // shared counter, so thousands of claimers would serialise there
-      if ((threadIdx.x >> 6) < kAsyncWaves) async_loop(a, c, o, k, &s_quiet);
+      if ((threadIdx.x >> 6) < kAsyncWaves) async_loop<S>(a, c, o, k, &s_quiet);
     }
     comb_flush(a, c, o, k);
     // every wave has left the tile queue (comb_flush starts with a workgroup barrier): reset it for
     // the next phase; the barriers of the flushes below order this before its next use
     for (int i = threadIdx.x; i < kBlockQ; i += kPeelThreads) s_bq[i] = (unsigned long long)kQEmpty;
     if (threadIdx.x < 4) s_bqc[threadIdx.x] = threadIdx.x == 2 ? kWaves : 0;
-    if (a.chained) drain_local(a, c, o, k);
+    if (a.chained) drain_local<S>(a, c, o, k);
     if (tr) C->trace[p][1] = wall_clock64();
     if (dbg) C->dbg[p - a.dbg_lo][blockIdx.x][1] = wall_clock64();
 
@@ -1189,6 +1413,7 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
       s_out[2] = (long long)ald(&o.slot->active);
       s_out[3] = (long long)ald(&o.slot->minv);
       s_out[4] = (long long)ald(&o.slot->peeled);
+      if constexpr (S) s_out[5] = (long long)ald(&C->s_valk);
     }
     __syncthreads();
     const long long nfs = s_out[0];
@@ -1196,6 +1421,7 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
     const long long nact = s_out[2];
     const unsigned mv = (unsigned)s_out[3];
     const long long npeel = s_out[4];
+    const long long valk = S ? s_out[5] : (long long)0xffffffffu;  // next validation (sampling)
     __syncthreads();
     if (nfs > a.fcap || nft > a.tcap || nact > n) {
       // a list overflowed (its entries were not written): stop before reading them
@@ -1257,7 +1483,8 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
           }
           break;
         }
-        kx = (long long)mv;
+        // (in sampling mode not past the next validation)
+        kx = S ? min((long long)mv, max(valk, kx + 1)) : (long long)mv;
         compact = false;
       }
     } else {
@@ -1275,6 +1502,8 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
     }
     // a k-core query ends with its one round: the survivors are the k-core
     if (a.k_query > 0 && kind == PH_SCAN) break;
+    // sampling mode: sampled vertices due for validation are checked before the round's scan
+    if (S && kind == PH_SCAN && valk <= kx) kind = PH_SAMPLE;
     // at a round boundary with few live vertices left: hand them to the tail peel; else, with a
     // small active set whose live rows fit: rewrite the rows once
     if (kind == PH_SCAN && tail_limit > 0 && n - total_peeled <= tail_limit)
@@ -1310,18 +1539,24 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
       ast(&C->stats[ST_SUBROUNDS], (unsigned long long)st_sub);
       ast(&C->stats[ST_BARRIERS], (unsigned long long)st_bar);
       ast(&C->stats[ST_KMAX], (unsigned long long)kmax_seen);
+      if (S) ast(&C->stats[ST_SAMPLED], (unsigned long long)ald(&C->s_ncand));
     }
   }
 }
 
 hipError_t launch_peel(const PeelArgs& a, int blocks, hipStream_t s) {
   void* args[] = {const_cast<PeelArgs*>(&a)};
-  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(peel_kernel), dim3(blocks),
+  return hipLaunchCooperativeKernel(a.sampling ? reinterpret_cast<const void*>(peel_kernel<true>)
+                                               : reinterpret_cast<const void*>(peel_kernel<false>), dim3(blocks),
                                     dim3(kPeelThreads), args, 0, s);
 }
 
 hipError_t peel_occupancy(int* blocks_per_cu) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, peel_kernel, kPeelThreads, 0);
+  int b0 = 0, b1 = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b0, peel_kernel<false>, kPeelThreads, 0);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b1, peel_kernel<true>, kPeelThreads, 0);
+  *blocks_per_cu = b0 < b1 ? b0 : b1;
+  return e;
 }
 
 
@@ -2138,6 +2373,7 @@ __global__ void init_ctl_kernel(PeelCtl* c) {
   for (size_t i = threadIdx.x; i < offsetof(PeelCtl, trace) / 4; i += blockDim.x) w[i] = 0u;
   __syncthreads();
   if (threadIdx.x < 3) c->slot[threadIdx.x].minv = 0xffffffffu;
+  if (threadIdx.x == 0) c->s_valk = 0xffffffffu;
 }
 
 hipError_t launch_init_ctl(PeelCtl* c, hipStream_t s) {

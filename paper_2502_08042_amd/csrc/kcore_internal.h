@@ -30,7 +30,7 @@ constexpr int kTailTile = 1024;       //   ... of this many entries (4 16-byte l
 
 enum StatIdx {
   ST_ROUNDS = 0, ST_SUBROUNDS, ST_BARRIERS, ST_PEELED, ST_EDGES, ST_DECR, ST_COMBINED, ST_SCANNED,
-  ST_KMAX, ST_TAIL, ST_NUM
+  ST_KMAX, ST_TAIL, ST_SAMPLED, ST_RECOUNTS, ST_NUM
 };
 
 // Counters produced during one phase (three-way rotation, see the peel kernel).
@@ -60,7 +60,10 @@ struct alignas(128) PeelCtl {
   // live vertices handed to the tail peel (0 = none) and the round at which they were handed over
   unsigned long long tail_n;
   unsigned long long tail_k;
-  unsigned long long pad3[14];
+  // sampling mode: smallest round at which a sampled vertex must be validated, candidates listed
+  unsigned int s_valk;
+  unsigned int s_ncand;
+  unsigned long long pad3[13];
   unsigned long long stats[16];
   // survivors each workgroup wrote into its segment of active list 0 / 1 (see the peel kernel)
   unsigned int acnt[2][kMaxPeelBlocks];
@@ -73,7 +76,10 @@ struct alignas(128) PeelCtl {
   unsigned long long dbg[kDbgPhases][kDbgBlocks][4];
 };
 
-enum : unsigned { KC_ERR_TIMEOUT = 1u, KC_ERR_OVERFLOW = 2u, KC_ERR_PHASES = 4u, KC_ERR_BADGRAPH = 8u };
+// KC_ERR_SAMPLE: a sampled vertex was found below k at a round boundary (the Las Vegas check of
+// the sampling scheme); the host then runs the decomposition again without sampling.
+enum : unsigned { KC_ERR_TIMEOUT = 1u, KC_ERR_OVERFLOW = 2u, KC_ERR_PHASES = 4u, KC_ERR_BADGRAPH = 8u,
+                  KC_ERR_SAMPLE = 16u };
 
 struct PeelArgs {
   const int64_t* off;
@@ -117,6 +123,20 @@ struct PeelArgs {
   long long* trow;
   int32_t* tadj;
   int64_t tail_ecap;      // entries tadj holds
+  // sampling mode (Alg. 4/5): vertices of degree above s_threshold start in sample mode; per vertex
+  // the hit threshold of the counter-based coin (rate x 2^32, 0 = not sampled), the hits, the
+  // induced degree at the last (re)initialisation and a recount accumulator; the candidates list
+  // and the list of vertices being recounted
+  int32_t sampling;
+  uint32_t s_threshold;
+  uint32_t s_mu;          // hits expected before a resample (mu of Alg. 5)
+  uint32_t s_seed;
+  uint32_t* srate;
+  uint32_t* scnt;
+  uint32_t* sbase;
+  uint32_t* scount;
+  int32_t* scand;
+  int32_t* srl;
 };
 
 struct BatchCtl {

@@ -182,6 +182,46 @@ def test_tail_handoff_called_off(monkeypatch):
     monkeypatch.delenv("KCORE_DEBUG_TAIL_ECAP")
 
 
+def test_sampling_mode_is_exact(monkeypatch):
+    """Sampling mode (Alg. 4/5): hubs count hits instead of decrementing and are validated and
+    recounted at round boundaries; the coreness must still be the oracle's, every vertex peeled
+    and every entry expanded once. Low thresholds put many vertices in sample mode."""
+    cases = [("rmat13", gg.rmat(13, 16, 7)), ("rmat16", gg.config_rmat16()),
+             ("road256", gg.grid_road(256, 0.05, 0.01, 3)), ("hcns120", None),
+             ("er5000", gg.erdos_renyi(5000, 0.01, 8))]
+    for name, g in cases:
+        off, adj = (g.offsets, g.adj) if g is not None else G.hcns(120)
+        want = oracle.bz(off, adj)
+        for knobs in (None, "128,100", "16,32", "8,400"):
+            if knobs is None:
+                monkeypatch.delenv("KCORE_DEBUG_SAMPLE", raising=False)
+            else:
+                monkeypatch.setenv("KCORE_DEBUG_SAMPLE", knobs)
+            say(f"[gpu] sampling {name} threshold,mu={knobs}")
+            got, st = run_single(off, adj, mode="sampling")
+            assert not first_mismatch(got, want), first_mismatch(got, want)
+            assert st["peeled"] == len(off) - 1 and st["edges"] == len(adj), st
+            assert st["device_status"] == 0 and st["kmax"] == int(want.max())
+            thr = 1024 if knobs is None else int(knobs.split(",")[0])
+            assert st["sampled_vertices"] == int((np.diff(off) > thr).sum()), st
+    monkeypatch.delenv("KCORE_DEBUG_SAMPLE", raising=False)
+
+
+def test_sampling_failure_is_detected_and_repeated(monkeypatch):
+    """A star's centre in sample mode with one expected hit (mu = 1) loses every neighbour in
+    round 1 unseen: the recount at a later round boundary finds it below k, the run is void and
+    is repeated without sampling, and the result is still exact."""
+    off, adj = G.star(64)
+    want = oracle.bz(off, adj)
+    monkeypatch.setenv("KCORE_DEBUG_SAMPLE", "4,1")
+    say("[gpu] sampling failure on star64")
+    got, st = run_single(off, adj, mode="sampling")
+    monkeypatch.delenv("KCORE_DEBUG_SAMPLE")
+    assert not first_mismatch(got, want), first_mismatch(got, want)
+    assert st["sample_restarts"] == 1 and st["sampled_vertices"] == 1, st
+    assert st["device_status"] == 0 and st["peeled"] == len(off) - 1
+
+
 @pytest.mark.parametrize("mode", MODES)
 def test_kcore_subgraph_query(mode):
     """Maximum k-core subgraph (App. B): membership equals coreness >= k from the oracle, for k
