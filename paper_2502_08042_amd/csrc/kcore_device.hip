@@ -1269,7 +1269,7 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
     c.arbitrate = kind == PH_SCAN && a.chained;
     c.bq_open = a.chained && a.bq_max_tiles > 0 && !c.async;
     if (tr) {
-      C->trace[p][4] = (unsigned long long)kind | (c.precheck ? 4ull : 0ull) | (c.async ? 8ull : 0ull) |
+      C->trace[p][4] = (unsigned long long)kind | (c.precheck ? 16ull : 0ull) | (c.async ? 32ull : 0ull) |
                        ((unsigned long long)k << 8);
       C->trace[p][5] = (unsigned long long)fs;
       C->trace[p][6] = (unsigned long long)ft;

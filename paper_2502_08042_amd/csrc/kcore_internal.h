@@ -68,7 +68,7 @@ struct alignas(128) PeelCtl {
   // survivors each workgroup wrote into its segment of active list 0 / 1 (see the peel kernel)
   unsigned int acnt[2][kMaxPeelBlocks];
   // phase timeline of workgroup 0, not cleared between launches: 100 MHz wall clock at start,
-  // work done, flushed and barrier passed; then kind | precheck << 2 | async << 3 | k << 8, the
+  // work done, flushed and barrier passed; then kind | precheck << 4 | async << 5 | k << 8, the
   // frontier's vertices, its hub tiles and the active-set size
   unsigned long long trace[kTracePhases][8];
   // per-workgroup record of the phases [dbg_lo, dbg_lo + kDbgPhases) when asked for: start, work
