@@ -384,7 +384,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="chunglu", choices=["chunglu", "grid", "rmat16", "batch", "serve", "kquery"])
-    ap.add_argument("--mode", default="auto", choices=["auto", "levelsync", "chained", "sampling"])
+    ap.add_argument("--mode", default="auto", choices=["auto", "levelsync", "chained", "sampling", "offline"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy 3 times (reference for HBM counters)")

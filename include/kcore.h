@@ -57,7 +57,7 @@ typedef enum {
                                pass by whichever workgroup finds them, without waiting for a
                                barrier (the idea of vertical granularity control, Sec. 4.2);
                                one grid-wide barrier per round */
-  KCORE_MODE_SAMPLING = 3   /* chained, with the sampling scheme of Sec. 4.1 (Alg. 4/5) for
+  KCORE_MODE_SAMPLING = 3,  /* chained, with the sampling scheme of Sec. 4.1 (Alg. 4/5) for
                                vertices of degree above 1024 instead of LDS combining: removing a
                                neighbour counts a hit with probability mu / (0.9 d*) instead of
                                decrementing, sampled vertices are validated and recounted at round
@@ -65,6 +65,12 @@ typedef enum {
                                which is repeated in chained mode (the result is always exact).
                                The call then synchronises `stream`. No tail handoff, no residual
                                rows; at most 2^30 vertices; not for kcore_kcore_subgraph */
+  KCORE_MODE_OFFLINE = 4    /* level-sync subrounds with the offline peel of Alg. 2: within a
+                               subround each workgroup first counts the decrements per target in
+                               an LDS table (the histogram), then applies each count once with the
+                               batch rule old > k >= old - c; targets that find no free slot of the
+                               4,096 are decremented directly. Frontiers and rho are those of
+                               KCORE_MODE_LEVELSYNC */
 } kcore_mode;
 
 typedef struct {

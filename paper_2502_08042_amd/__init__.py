@@ -33,7 +33,7 @@ LIB_PATH = os.path.join(_HERE, "libkcore.so")
 KCORE_OK, KCORE_PENDING = 0, 1
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ETOOBIG", -5: "ENOTFOUND",
           -6: "ECANCELED", -7: "EBADGRAPH"}
-MODES = {"auto": 0, "levelsync": 1, "chained": 2, "sampling": 3}
+MODES = {"auto": 0, "levelsync": 1, "chained": 2, "sampling": 3, "offline": 4}
 
 
 class KcoreError(RuntimeError):

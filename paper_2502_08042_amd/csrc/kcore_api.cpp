@@ -280,7 +280,7 @@ int batch_ws(int dev, hipStream_t s, int64_t V, int32_t G, BatchWs*& out) {
 
 int check_opts(const kcore_options* o) {
   if (!o) return KCORE_OK;
-  if (o->mode < 0 || o->mode > 3) return fail(KCORE_EINVAL, "mode %d unknown", o->mode);
+  if (o->mode < 0 || o->mode > 4) return fail(KCORE_EINVAL, "mode %d unknown", o->mode);
   if (o->blocks_per_cu < 0 || o->hub_degree < 0 || o->num_entries < 0 || o->local_budget < 0 ||
       o->tile_edges < 0 || (o->tile_edges % 64) != 0 || o->tile_edges > 32768)
     return fail(KCORE_EINVAL, "negative option, or tile_edges not a multiple of 64 up to 32768");
@@ -355,6 +355,7 @@ static int peel_impl(const int64_t* offsets, const int32_t* adj, int64_t n, int3
 
   const int mode = (opt && opt->mode) ? opt->mode : KCORE_MODE_CHAINED;
   const bool sampling = mode == KCORE_MODE_SAMPLING;
+  const bool offline = mode == KCORE_MODE_OFFLINE;
   if (sampling && k_query > 0) return fail(KCORE_EINVAL, "the k-core query has no sampling mode");
   if (sampling && n > (1ll << 30))
     return fail(KCORE_EINVAL, "sampling mode takes at most 2^30 vertices (n = %lld)", (long long)n);
@@ -428,11 +429,12 @@ static int peel_impl(const int64_t* offsets, const int32_t* adj, int64_t n, int3
   a.tcap = w->t_cap;
   a.ctl = w->ctl;
   a.hub = hub;
-  a.comb_degree = hub > 1024u ? hub : 1024u;
+  // offline mode: every target is combined (Alg. 2's histogram, per workgroup), in every phase
+  a.comb_degree = offline ? 0u : (hub > 1024u ? hub : 1024u);
   a.tile = tile;
   a.chained = (mode == KCORE_MODE_CHAINED || sampling) ? 1 : 0;
   a.lq_budget = budget;
-  a.big_phase = 16384;
+  a.big_phase = offline ? 0 : 16384;
   a.aq = w->aq;
   a.qcap = w->q_cap;
   const int32_t af = opt ? opt->async_frontier : 0;
@@ -697,8 +699,8 @@ static int batched_impl(const int64_t* graph_vptr, const int64_t* offsets, const
   a.lds_cap = cap;
   // barrier-separated subrounds by default: inside one workgroup a barrier is cheap, and peeling a
   // whole frontier edge-balanced over all 512 threads beats 64-vertex packets claimed per wave
-  if (opt && opt->mode == KCORE_MODE_SAMPLING)
-    return fail(KCORE_EINVAL, "the batched peel has no sampling mode (its degrees live in LDS)");
+  if (opt && (opt->mode == KCORE_MODE_SAMPLING || opt->mode == KCORE_MODE_OFFLINE))
+    return fail(KCORE_EINVAL, "the batched peel has neither sampling nor offline mode (its degrees live in LDS)");
   a.chained = (opt && opt->mode == KCORE_MODE_CHAINED) ? 1 : 0;
   if (stats_host) HIP_TRY(hipEventRecord(w->ev0, stream));
   HIP_TRY(kc::launch_batched(a, blocks, lds, stream));

@@ -182,6 +182,28 @@ def test_tail_handoff_called_off(monkeypatch):
     monkeypatch.delenv("KCORE_DEBUG_TAIL_ECAP")
 
 
+@pytest.mark.parametrize("tail", [0, -1])
+def test_offline_mode_keeps_levelsync_frontiers(tail):
+    """Offline mode (Alg. 2): each subround's decrements are counted per target in a workgroup
+    table and applied once with the batch rule old > k >= old - c. Coreness must be the oracle's
+    and, the frontiers being order independent, the subround count the sequential framework's
+    rho."""
+    cases = [("rmat12", gg.rmat(12, 16, 11)), ("er3000", gg.erdos_renyi(3000, 0.004, 5)),
+             ("road128", gg.grid_road(128, 0.05, 0.01, 2)), ("hcns200", None),
+             ("rmat16", gg.config_rmat16())]
+    for name, g in cases:
+        off, adj = (g.offsets, g.adj) if g is not None else G.hcns(200)
+        say(f"[gpu] offline {name} tail={tail}")
+        want, sub, ls = oracle.levelsync(off, adj)
+        got, st = run_single(off, adj, mode="offline", tail=tail)
+        assert not first_mismatch(got, want), first_mismatch(got, want)
+        assert st["peeled"] == len(off) - 1 and st["edges"] == len(adj), st
+        assert st["rounds"] == ls["nonempty_rounds"] and st["subrounds"] == ls["subrounds"], (st, ls)
+        assert st["device_status"] == 0, st
+        if tail == -1:  # (with the tail, small graphs go to the single workgroup after round one)
+            assert st["combined"] > 0, st
+
+
 def test_sampling_mode_is_exact(monkeypatch):
     """Sampling mode (Alg. 4/5): hubs count hits instead of decrementing and are validated and
     recounted at round boundaries; the coreness must still be the oracle's, every vertex peeled
