@@ -204,6 +204,21 @@ def test_offline_mode_keeps_levelsync_frontiers(tail):
             assert st["combined"] > 0, st
 
 
+@pytest.mark.parametrize("mode,knobs", [("offline", None), ("sampling", None), ("sampling", "2,4")])
+def test_small_graphs_other_modes(monkeypatch, mode, knobs):
+    """Exact graph families and golden fixtures in offline and sampling mode (with nearly every
+    vertex in sample mode for threshold 2)."""
+    if knobs:
+        monkeypatch.setenv("KCORE_DEBUG_SAMPLE", knobs)
+    for name, (off, adj) in small_cases():
+        say(f"[gpu] small {name} mode={mode} knobs={knobs}")
+        got, st = run_single(off, adj, mode=mode)
+        want = oracle.bz(off, adj)
+        assert not first_mismatch(got, want), f"{name}: {first_mismatch(got, want)}"
+        assert st["peeled"] == len(off) - 1 and st["device_status"] == 0, (name, st)
+    monkeypatch.delenv("KCORE_DEBUG_SAMPLE", raising=False)
+
+
 def test_sampling_mode_is_exact(monkeypatch):
     """Sampling mode (Alg. 4/5): hubs count hits instead of decrementing and are validated and
     recounted at round boundaries; the coreness must still be the oracle's, every vertex peeled
