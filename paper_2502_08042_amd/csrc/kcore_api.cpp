@@ -741,6 +741,7 @@ int kcore_release_workspaces(void) {
     PeelWs* w = kv.second;
     if (!w) continue;
     if (w->block) hipFree(w->block);
+    if (w->sblock) hipFree(w->sblock);
     if (w->host_stats) hipHostFree(w->host_stats);
     if (w->ev0) hipEventDestroy(w->ev0);
     if (w->ev1) hipEventDestroy(w->ev1);
