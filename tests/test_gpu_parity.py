@@ -318,6 +318,27 @@ def test_batched_large_graph_in_global_memory(mode):
     assert not first_mismatch(got, want), first_mismatch(got, want)
 
 
+def test_batched_plain_entry_point_large_graphs():
+    # the plain entry point (no options, no statistics) on graphs above the LDS capacity
+    import torch
+    import paper_2502_08042_amd as K
+    from gpu_util import to_dev
+    r15 = gg.rmat(15, 8, 3)
+    road = gg.grid_road(200, 0.05, 0.01, 9)
+    parts = [(r15.offsets, r15.adj), G.complete(40), (road.offsets, road.adj)]
+    off, adj = G.union(parts)
+    vptr = np.cumsum([0] + [len(p[0]) - 1 for p in parts]).astype(np.int64)
+    say(f"[gpu] batched large graphs, plain entry point, V={len(off) - 1} m={len(adj)}")
+    d_off, d_adj, d_vptr = to_dev(off, adj, vptr)
+    out = torch.empty(len(off) - 1, dtype=torch.int32, device="cuda")
+    rc = K._lib.kcore_decompose_batched(d_vptr.data_ptr(), d_off.data_ptr(), d_adj.data_ptr(), len(parts),
+                                        len(off) - 1, out.data_ptr(), None)
+    torch.cuda.synchronize()
+    assert rc == 0, K.last_error()
+    got, want = out.cpu().numpy(), oracle.bz(off, adj)
+    assert not first_mismatch(got, want), first_mismatch(got, want)
+
+
 def test_repeat_is_deterministic():
     g = gg.rmat(14, 16, 5)
     say("[gpu] repeat x5 levelsync rmat14")
