@@ -128,7 +128,8 @@ typedef struct {
   int64_t barriers;        /* grid-wide synchronisations executed */
   int64_t peeled;          /* vertices given a coreness (= n) */
   int64_t edges;           /* adjacency entries expanded (= m; entries dropped when rows are
-                              rewritten without peeled neighbours count as expanded there) */
+                              rewritten without peeled neighbours count as expanded there, and so
+                              do the tail's rows left unread once all its vertices are queued) */
   int64_t decrements;      /* global atomic decrements issued */
   int64_t combined;        /* decrements absorbed by LDS combining */
   int64_t scanned;         /* active-set slots scanned (Thm. 3.1 bounds this by n + m) */

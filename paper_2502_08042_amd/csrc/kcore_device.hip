@@ -2059,12 +2059,24 @@ __device__ __forceinline__ bool tail_chain(const PeelArgs& a, uint32_t* d, int32
       rb = (int)a.trow[2 * (long long)v];
       dg = (int)(a.trow[2 * (long long)v + 1] - rb);
     }
+    // once every local vertex is queued, the rows still waiting can only decrement peeled vertices
+    // (the last round of a dense core queues all of it after a fraction of its rows): they count
+    // as expanded without being read
+    int full = 0;
+    if (l == 0) full = lds_ld(s_tail) >= L;
+    if (__shfl(full, 0, 64)) {
+      const int tot = __shfl(wave_incl_scan(dg), 63, 64);
+      if (l == 0) st_edges += tot;
+      continue;
+    }
     unsigned long long big = __ballot(dg >= kTailBig);
     while (big) {
       const int j = __ffsll((long long)big) - 1;
       big &= big - 1;
       const int rs = __shfl(rb, j, 64), len = __shfl(dg, j, 64);
       if (l == 0) st_edges += len;
+      if (l == 0) full = lds_ld(s_tail) >= L;
+      if (__shfl(full, 0, 64)) continue;  // (as above, row by row)
       for (int o = 0; o < len; o += kTailTile) tail_tile(a, d, q, s_tail, L, rs + o, min(len - o, kTailTile), k);
     }
     const int sd = dg >= kTailBig ? 0 : dg;
@@ -2072,7 +2084,9 @@ __device__ __forceinline__ bool tail_chain(const PeelArgs& a, uint32_t* d, int32
     const int excl = incl - sd;
     const int total = __shfl(incl, 63, 64);
     if (l == 0) st_edges += total;
-    for (int e0 = 0; e0 < total; e0 += 64 * kTailUnroll) {
+    if (l == 0) full = lds_ld(s_tail) >= L;
+    const bool skip = __shfl(full, 0, 64) != 0;
+    for (int e0 = 0; !skip && e0 < total; e0 += 64 * kTailUnroll) {
       int32_t u[kTailUnroll];
 #pragma unroll
       for (int r = 0; r < kTailUnroll; ++r) {
@@ -2223,6 +2237,7 @@ __global__ __launch_bounds__(kTailThreads) void tail_kernel(PeelArgs a, int32_t 
     // a wavefront streams with 16-byte loads.
     while (!kChained && head < tail) {
       st_sub++;
+      const bool full = tail >= L;  // every local vertex queued: rows counted, not read
       for (int c0 = head; c0 < tail; c0 += kTailThreads) {
         const int i = c0 + tid;
         int rb = 0, dg = 0;
@@ -2242,7 +2257,7 @@ __global__ __launch_bounds__(kTailThreads) void tail_kernel(PeelArgs a, int32_t 
         if (tid == 0) st_edges += total;
         if (big) st_edges += dg;
         __syncthreads();
-        for (int e0 = 0; e0 < total; e0 += kTailThreads * kTailUnroll) {
+        for (int e0 = 0; !full && e0 < total; e0 += kTailThreads * kTailUnroll) {
           int32_t u[kTailUnroll];
 #pragma unroll
           for (int r = 0; r < kTailUnroll; ++r) {
@@ -2259,7 +2274,7 @@ __global__ __launch_bounds__(kTailThreads) void tail_kernel(PeelArgs a, int32_t 
           }
           tail_edges(a, d, q, &s_tail, L, u, k);
         }
-        for (int tt = w; tt < tiles; tt += kTailThreads / 64) {
+        for (int tt = w; !full && tt < tiles; tt += kTailThreads / 64) {
           int lo = 0, hi = kTailThreads - 1;  // largest j with s_tpref[j] <= tt (wave-uniform)
           while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
