@@ -23,7 +23,10 @@
  * are reported synchronously and enqueue nothing. The caller owns every buffer it passes; the
  * library owns its device workspace, cached per (device, stream) and reused across calls (see
  * kcore_release_workspaces). Calls on distinct streams may run concurrently; calls on one stream
- * are serialised by it. hipStream_t 0 is the legacy default stream.
+ * are serialised by it. Exception: the single-graph peel (kcore_decompose*, kcore_kcore_subgraph)
+ * runs a persistent grid that fills the device, so those grids run one at a time per device, each
+ * after the one launched before it (ordered through the streams; the host does not block).
+ * hipStream_t 0 is the legacy default stream.
  */
 #ifndef KCORE_H_
 #define KCORE_H_

@@ -48,6 +48,31 @@ struct DevInfo {
 std::mutex g_mu;
 std::map<int, DevInfo> g_dev;
 
+// The peel kernel is a persistent grid that fills the device, and its grid barriers need every one
+// of its workgroups resident: two such grids launched from different streams could each hold part
+// of the device and wait for the rest forever. So the grids of one device run one after another:
+// each launch first waits, in its own stream, for an event recorded after the launch before it
+// (stream order only; the host never blocks here).
+struct GridOrder {
+  hipEvent_t ev = nullptr;
+  hipStream_t last = nullptr;
+  bool any = false;
+};
+std::mutex g_grid_mu;
+std::map<int, GridOrder> g_grid;
+
+int launch_peel_ordered(int dev, const kc::PeelArgs& a, int blocks, hipStream_t stream) {
+  std::lock_guard<std::mutex> lk(g_grid_mu);
+  GridOrder& o = g_grid[dev];
+  if (!o.ev) HIP_TRY(hipEventCreateWithFlags(&o.ev, hipEventDisableTiming));
+  if (o.any && o.last != stream) HIP_TRY(hipStreamWaitEvent(stream, o.ev, 0));
+  HIP_TRY(kc::launch_peel(a, blocks, stream));
+  HIP_TRY(hipEventRecord(o.ev, stream));
+  o.last = stream;
+  o.any = true;
+  return KCORE_OK;
+}
+
 int dev_info(int dev, DevInfo& out) {
   std::lock_guard<std::mutex> lk(g_mu);
   auto it = g_dev.find(dev);
@@ -500,7 +525,7 @@ static int peel_impl(const int64_t* offsets, const int32_t* adj, int64_t n, int3
   kcore_stats local_stats;
   if (sampling && !stats_host) stats_host = &local_stats;
   if (stats_host) HIP_TRY(hipEventRecord(w->ev0, stream));
-  HIP_TRY(kc::launch_peel(a, blocks, stream));
+  if (int rc = launch_peel_ordered(dev, a, blocks, stream)) return rc;
   if (tail_vmax > 0) HIP_TRY(kc::launch_tail(a, (int32_t)tail_vmax, stream));
   if (!stats_host) return KCORE_OK;
   HIP_TRY(hipEventRecord(w->ev1, stream));
@@ -758,6 +783,12 @@ int kcore_release_workspaces(void) {
     delete w;
   }
   g_batch.clear();
+  {
+    std::lock_guard<std::mutex> lg(g_grid_mu);
+    for (auto& kv : g_grid)
+      if (kv.second.ev) hipEventDestroy(kv.second.ev);
+    g_grid.clear();
+  }
   return KCORE_OK;
 }
 
