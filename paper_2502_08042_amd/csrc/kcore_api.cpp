@@ -114,7 +114,7 @@ struct PeelWs {
   int32_t* tmap = nullptr;   // tail handoff: id -> local id (n entries)
   int32_t* tgid = nullptr;   //   local id -> id (l_cap)
   long long* trow = nullptr; //   local rows (2 l_cap)
-  int32_t* tadj = nullptr;   //   their entries (e_cap)
+  uint16_t* tadj = nullptr;  //   their entries (e_cap 16-bit local ids)
   // sampling mode (allocated on first use): srate, scnt, sbase, scount (uint32[s_cap] each),
   // scand, srl (int32[s_cap] each)
   void* sblock = nullptr;
@@ -191,7 +191,7 @@ int peel_ws(int dev, hipStream_t s, int64_t n, int64_t tcap, int64_t rcap, int64
     const size_t o_tm = off; off = align_up(off + (lc > 0 ? 4 * (size_t)nc : 0));
     const size_t o_tg = off; off = align_up(off + 4 * (size_t)lc);
     const size_t o_tr = off; off = align_up(off + 16 * (size_t)lc);
-    const size_t o_te = off; off = align_up(off + 4 * (size_t)ec);
+    const size_t o_te = off; off = align_up(off + 2 * (size_t)ec);
     const size_t o_c = off; off = align_up(off + sizeof(kc::PeelCtl));
     const size_t o_v = off; off = align_up(off + 64);
     hipError_t e = hipMalloc(&w->block, off);
@@ -218,7 +218,7 @@ int peel_ws(int dev, hipStream_t s, int64_t n, int64_t tcap, int64_t rcap, int64
     w->tmap = lc > 0 ? (int32_t*)(b + o_tm) : nullptr;
     w->tgid = lc > 0 ? (int32_t*)(b + o_tg) : nullptr;
     w->trow = lc > 0 ? (long long*)(b + o_tr) : nullptr;
-    w->tadj = lc > 0 ? (int32_t*)(b + o_te) : nullptr;
+    w->tadj = lc > 0 ? (uint16_t*)(b + o_te) : nullptr;
     w->l_cap = lc;
     w->e_cap = ec;
     w->ctl = (kc::PeelCtl*)(b + o_c);
@@ -417,10 +417,11 @@ static int peel_impl(const int64_t* offsets, const int32_t* adj, int64_t n, int3
   // one workgroup; their local rows hold at most min(m, L (L - 1)) entries (simple graph)
   const int32_t to = opt ? opt->tail : 0;
   int64_t tail_vmax = (to < 0 || k_query > 0 || sampling) ? 0 : std::min<int64_t>(to ? to : di.tail_lcap, di.tail_lcap);
-  tail_vmax = std::min<int64_t>(tail_vmax, n);
-  // (plus up to 3 pad entries per row: rows start on 16-byte boundaries)
+  // (local ids are 16-bit: at most 65,535 vertices, 0xffff pads the rows)
+  tail_vmax = std::min<int64_t>(std::min<int64_t>(tail_vmax, n), 65535);
+  // (plus up to 7 pad entries per row: rows start on 16-byte boundaries)
   const int64_t tail_ecap =
-      tail_vmax > 0 ? std::min<int64_t>(m, tail_vmax * (tail_vmax - 1)) + 3 * tail_vmax + 64 : 0;
+      tail_vmax > 0 ? std::min<int64_t>(m, tail_vmax * (tail_vmax - 1)) + 7 * tail_vmax + 64 : 0;
 
   PeelWs* w = nullptr;
   if (int rc = peel_ws(dev, stream, n, tcap, rcap, tail_vmax, tail_ecap, w)) return rc;

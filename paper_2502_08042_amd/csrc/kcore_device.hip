@@ -1102,7 +1102,7 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
       //    0..L-1 in (1), and (2) writes their rows in those local ids. The grid then stops.
       const bool to_tail = kind == PH_TAIL;
       long long* nrow = to_tail ? a.trow : a.rrow;
-      int32_t* nadj = to_tail ? a.tadj : a.radj;
+      int32_t* nadj = a.radj;  // (the tail's rows are 16-bit local ids in a.tadj)
       const long long ncap = to_tail ? a.tail_ecap : a.rcap;
       PhaseSlot* slot = o.slot;
       const int32_t* alist = a.act[acur];
@@ -1126,9 +1126,9 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
         unsigned long long vbase = 0;
         if (l == 0 && to_tail) vbase = aadd(&slot->active, (unsigned long long)__popcll(lm));
         vbase = __shfl(vbase, 0, 64);
-        // local rows start on 16-byte boundaries (lengths padded to 4 entries with -1) so that the
-        // tail peel streams them with 16-byte loads
-        const long long rlen = to_tail ? (len + 3) & ~3ll : len;
+        // local rows start on 16-byte boundaries (lengths padded to 8 16-bit entries with 0xffff)
+        // so that the tail peel streams them with 16-byte loads
+        const long long rlen = to_tail ? (len + 7) & ~7ll : len;
         const long long incl = wave_incl_scan(rlen);
         const long long tot = __shfl(incl, 63, 64);
         unsigned long long base = 0;
@@ -1152,7 +1152,7 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
           const long long rb = (long long)base + incl - rlen;
           ast(&nrow[2 * r], rb);      // first entry
           ast(&nrow[2 * r + 1], rb);  // fill cursor, the row's end once filled
-          for (long long x = rb + len; x < rb + rlen; ++x) ast(&nadj[x], -1);
+          for (long long x = rb + len; x < rb + rlen; ++x) a.tadj[x] = 0xffffu;
           const long long t0 = (long long)tbase + tincl - nt;
           for (long long j = 0; j < nt; ++j)
             ast(&a.aq[t0 + j], (long long)(((unsigned long long)j << 32) | (unsigned)v));
@@ -1221,7 +1221,13 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
           }
 #pragma unroll
           for (int q = 0; q < kTileUnroll; ++q) {
-            if ((mk[q] >> l) & 1ull) ast(&nadj[pos + rank_in(mk[q])], u[q]);
+            if ((mk[q] >> l) & 1ull) {
+              // (the tail kernel, a later launch, is the only reader of the tail's rows)
+              if (to_tail)
+                a.tadj[pos + rank_in(mk[q])] = (uint16_t)u[q];
+              else
+                ast(&nadj[pos + rank_in(mk[q])], u[q]);
+            }
             pos += __popcll(mk[q]);
           }
         }
@@ -1964,29 +1970,58 @@ __device__ __forceinline__ void tail_edges(const PeelArgs& a, uint32_t* d, int32
   }
 }
 
+// tail_edges for 16 entries held as 8 packed words of two 16-bit local ids: entry e is the
+// (e & 1) half of word e >> 1, valid when e < lim (lim <= 0: none); an invalid entry decrements
+// the lane's spare slot. Ids are unpacked where they are used, so the packed words are all that
+// stays live. All lanes of the wavefront call.
+__device__ __forceinline__ void tail_edges16(const PeelArgs& a, uint32_t* d, int32_t* q, int* s_tail, int L,
+                                             const uint32_t (&w)[8], const int (&lim)[2], uint32_t k) {
+  const int spare = L + lane_id();
+  uint32_t old[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int32_t id = (int32_t)((w[e >> 1] >> (16 * (e & 1))) & 0xffffu);
+    old[e] = atomicSub(&d[(e & 7) < lim[e >> 3] ? id : spare], 1u);
+  }
+  unsigned cm = 0;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) cm |= (old[e] == k + 1 ? 1u : 0u) << e;
+  if (!__ballot(cm != 0)) return;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const bool crossed = (cm >> e) & 1u;
+    const unsigned long long m = __ballot(crossed);
+    if (!m) continue;
+    const int32_t u = (int32_t)((w[e >> 1] >> (16 * (e & 1))) & 0xffffu);
+    if (crossed) a.core[a.tgid[u]] = (int32_t)k;
+    int b = 0;
+    if (lane_id() == 0) b = atomicAdd(s_tail, __popcll(m));
+    b = __shfl(b, 0, 64);
+    if (crossed) lds_st(&q[b + rank_in(m)], u);
+  }
+}
+
 // Entries [tb, tb + len) of the local rows, len <= kTailTile, through one wavefront with 16-byte
-// loads, every load in flight before the first decrement (tb on a 16-byte boundary; rows are
-// padded to whole 16-byte words). All lanes call with the same range.
+// loads of eight 16-bit local ids each, every load in flight before the first decrement (tb on a
+// 16-byte boundary; rows are padded to whole 16-byte words); the decrements go in two halves of
+// 16 entries per lane. All lanes call with the same range.
 __device__ __forceinline__ void tail_tile(const PeelArgs& a, uint32_t* d, int32_t* q, int* s_tail, int L, int tb,
                                           int len, uint32_t k) {
+  static_assert(kTailTile == 2048, "four 16-byte loads of 8 entries per lane");
   const int l = lane_id();
-  const int spare = L + l;
-  int4 x[kTailTile / 256];
+  uint4 x[4];
 #pragma unroll
-  for (int j = 0; j < kTailTile / 256; ++j) {
-    const int r = 256 * j + 4 * l;
-    x[j] = r < len ? *reinterpret_cast<const int4*>(a.tadj + (tb + r)) : make_int4(spare, spare, spare, spare);
+  for (int j = 0; j < 4; ++j) {
+    const int r = 512 * j + 8 * l;
+    x[j] = r < len ? *reinterpret_cast<const uint4*>(a.tadj + (tb + r)) : make_uint4(0u, 0u, 0u, 0u);
   }
-  int32_t u[kTailTile / 64];
 #pragma unroll
-  for (int j = 0; j < kTailTile / 256; ++j) {
-    const int r = 256 * j + 4 * l;
-    u[4 * j] = x[j].x;  // r < len whenever the load happened
-    u[4 * j + 1] = r + 1 < len ? x[j].y : spare;
-    u[4 * j + 2] = r + 2 < len ? x[j].z : spare;
-    u[4 * j + 3] = r + 3 < len ? x[j].w : spare;
+  for (int h = 0; h < 2; ++h) {
+    const uint32_t w[8] = {x[2 * h].x, x[2 * h].y, x[2 * h].z, x[2 * h].w,
+                           x[2 * h + 1].x, x[2 * h + 1].y, x[2 * h + 1].z, x[2 * h + 1].w};
+    const int lim[2] = {len - (1024 * h + 8 * l), len - (1024 * h + 512 + 8 * l)};
+    tail_edges16(a, d, q, s_tail, L, w, lim, k);
   }
-  tail_edges(a, d, q, s_tail, L, u, k);
 }
 
 // Chained round of the tail peel (VGC, Sec. 4.2, at workgroup level): the round's queue segment
@@ -2099,7 +2134,7 @@ __device__ __forceinline__ bool tail_chain(const PeelArgs& a, uint32_t* d, int32
           if (cand < 64 && ex <= t) j = cand;
         }
         const int pos = __shfl(rb, j, 64) + (t - __shfl(excl, j, 64));
-        u[r] = t < total ? a.tadj[pos] : L + l;
+        u[r] = t < total ? (int32_t)a.tadj[pos] : L + l;
       }
       tail_edges(a, d, q, s_tail, L, u, k);
     }
@@ -2269,7 +2304,7 @@ __global__ __launch_bounds__(kTailThreads) void tail_kernel(PeelArgs a, int32_t 
                 const int mid = (lo + hi + 1) >> 1;
                 if (s_pref[mid] <= t) lo = mid; else hi = mid - 1;
               }
-              u[r] = a.tadj[s_rb[lo] + (t - s_pref[lo])];
+              u[r] = (int32_t)a.tadj[s_rb[lo] + (t - s_pref[lo])];
             }
           }
           tail_edges(a, d, q, &s_tail, L, u, k);

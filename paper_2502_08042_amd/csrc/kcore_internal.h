@@ -26,7 +26,7 @@ constexpr int kTracePhases = 16384;   // phases whose timeline workgroup 0 recor
 constexpr int kTailThreads = 1024;    // threads of the single-workgroup tail peel
 constexpr int kTailUnroll = 4;        //   short rows: adjacency entries in flight per thread
 constexpr int kTailBig = 256;         //   rows at least this long are streamed in tiles ...
-constexpr int kTailTile = 1024;       //   ... of this many entries (4 16-byte loads per lane)
+constexpr int kTailTile = 2048;       //   ... of this many entries (4 16-byte loads of 8 ids per lane)
 
 enum StatIdx {
   ST_ROUNDS = 0, ST_SUBROUNDS, ST_BARRIERS, ST_PEELED, ST_EDGES, ST_DECR, ST_COMBINED, ST_SCANNED,
@@ -121,7 +121,7 @@ struct PeelArgs {
   int32_t* tmap;
   int32_t* tgid;
   long long* trow;
-  int32_t* tadj;
+  uint16_t* tadj;         // 16-bit local ids (the tail holds fewer than 65,535 vertices)
   int64_t tail_ecap;      // entries tadj holds
   // sampling mode (Alg. 4/5): vertices of degree above s_threshold start in sample mode; per vertex
   // the hit threshold of the counter-based coin (rate x 2^32, 0 = not sampled), the hits, the
