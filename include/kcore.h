@@ -118,9 +118,9 @@ typedef struct {
                             them with their induced degrees in LDS, so the last, small rounds
                             synchronise at workgroup level instead of grid-wide (the k-core
                             query never hands over); costs 4 bytes per vertex plus
-                            min(m, tail^2) entries of workspace; capped at what the workgroup's
-                            LDS holds at 8 bytes per vertex (17,408 on a 160 KB-LDS device);
-                            0 = that cap, -1 = never */
+                            min(m, tail^2) 16-bit entries of workspace; capped at what the
+                            workgroup's LDS holds at 6 bytes per vertex (23,552 on a 160 KB-LDS
+                            device); 0 = default, min(that cap, n / 8); -1 = never */
 } kcore_options;
 
 /* Counters of one decomposition (filled when a kcore_stats* is passed; that call synchronises

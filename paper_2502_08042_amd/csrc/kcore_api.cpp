@@ -88,9 +88,10 @@ int dev_info(int dev, DevInfo& out) {
   HIP_TRY(kc::peel_occupancy(&d.peel_bpc));
   size_t tail_static = 0;
   HIP_TRY(kc::tail_static_lds(&tail_static));
-  // 8 bytes per vertex (induced degree and queue slot) plus 64 spare slots, in whole 1024-vertex
-  // steps
-  d.tail_lcap = lds > (int)tail_static + 256 ? (int32_t)(((size_t)lds - tail_static - 256) / 8 / 1024 * 1024) : 0;
+  // 6 bytes per vertex (induced degree and 16-bit queue slot) plus 64 spare slots, in whole
+  // 1024-vertex steps, below the 16-bit id limit
+  d.tail_lcap = lds > (int)tail_static + 256 ? (int32_t)(((size_t)lds - tail_static - 256) / 6 / 1024 * 1024) : 0;
+  d.tail_lcap = std::min<int32_t>(d.tail_lcap, 64512);
   if (d.tail_lcap > 0) HIP_TRY(kc::tail_allow_lds(d.tail_lcap));
   g_dev[dev] = d;
   out = d;
@@ -416,7 +417,11 @@ static int peel_impl(const int64_t* offsets, const int32_t* adj, int64_t n, int3
   // tail handoff: the last live vertices (at most what the tail peel's LDS holds) are peeled by
   // one workgroup; their local rows hold at most min(m, L (L - 1)) entries (simple graph)
   const int32_t to = opt ? opt->tail : 0;
-  int64_t tail_vmax = (to < 0 || k_query > 0 || sampling) ? 0 : std::min<int64_t>(to ? to : di.tail_lcap, di.tail_lcap);
+  // (default n / 8: one workgroup streams the rows of what it takes over from one CU, which pays on
+  // a large graph's last few thousand rounds but not when the tail would hold much of the graph)
+  int64_t tail_vmax = (to < 0 || k_query > 0 || sampling)
+                          ? 0
+                          : std::min<int64_t>(to ? to : std::max<int64_t>(n / 8, 1), di.tail_lcap);
   // (local ids are 16-bit: at most 65,535 vertices, 0xffff pads the rows)
   tail_vmax = std::min<int64_t>(std::min<int64_t>(tail_vmax, n), 65535);
   // (plus up to 7 pad entries per row: rows start on 16-byte boundaries)

@@ -1600,13 +1600,14 @@ __device__ __forceinline__ long long block_excl_scan(long long x, long long* s_w
   return r;
 }
 
-__device__ __forceinline__ void team_push(bool p, int32_t v, int32_t* q, int* s_tail) {
+template <class QT>
+__device__ __forceinline__ void team_push(bool p, int32_t v, QT* q, int* s_tail) {
   const unsigned long long m = __ballot(p);
   if (!m) return;
   int base = 0;
   if (lane_id() == 0) base = atomicAdd(s_tail, __popcll(m));
   base = __shfl(base, 0, 64);
-  if (p) q[base + rank_in(m)] = v;
+  if (p) q[base + rank_in(m)] = (QT)v;
 }
 
 // Chained round of one graph (VGC, Sec. 4.2, at workgroup level): the round's queue segment grows
@@ -1948,7 +1949,7 @@ hipError_t batched_occupancy(size_t lds_bytes, int* blocks_per_cu) {
 // it (slot reserved first, then written: chained rounds read slots as they fill). Every atomic of
 // the batch is issued before any result is looked at. All lanes of the wavefront call.
 template <int N>
-__device__ __forceinline__ void tail_edges(const PeelArgs& a, uint32_t* d, int32_t* q, int* s_tail, int L,
+__device__ __forceinline__ void tail_edges(const PeelArgs& a, uint32_t* d, uint16_t* q, int* s_tail, int L,
                                            const int32_t (&u)[N], uint32_t k) {
   uint32_t old[N];
 #pragma unroll
@@ -1966,7 +1967,7 @@ __device__ __forceinline__ void tail_edges(const PeelArgs& a, uint32_t* d, int32
     int b = 0;
     if (lane_id() == 0) b = atomicAdd(s_tail, __popcll(m));
     b = __shfl(b, 0, 64);
-    if (crossed) lds_st(&q[b + rank_in(m)], u[j]);
+    if (crossed) lds_st(&q[b + rank_in(m)], (uint16_t)u[j]);
   }
 }
 
@@ -1974,7 +1975,7 @@ __device__ __forceinline__ void tail_edges(const PeelArgs& a, uint32_t* d, int32
 // (e & 1) half of word e >> 1, valid when e < lim (lim <= 0: none); an invalid entry decrements
 // the lane's spare slot. Ids are unpacked where they are used, so the packed words are all that
 // stays live. All lanes of the wavefront call.
-__device__ __forceinline__ void tail_edges16(const PeelArgs& a, uint32_t* d, int32_t* q, int* s_tail, int L,
+__device__ __forceinline__ void tail_edges16(const PeelArgs& a, uint32_t* d, uint16_t* q, int* s_tail, int L,
                                              const uint32_t (&w)[8], const int (&lim)[2], uint32_t k) {
   const int spare = L + lane_id();
   uint32_t old[16];
@@ -1997,7 +1998,7 @@ __device__ __forceinline__ void tail_edges16(const PeelArgs& a, uint32_t* d, int
     int b = 0;
     if (lane_id() == 0) b = atomicAdd(s_tail, __popcll(m));
     b = __shfl(b, 0, 64);
-    if (crossed) lds_st(&q[b + rank_in(m)], u);
+    if (crossed) lds_st(&q[b + rank_in(m)], (uint16_t)u);
   }
 }
 
@@ -2005,7 +2006,7 @@ __device__ __forceinline__ void tail_edges16(const PeelArgs& a, uint32_t* d, int
 // loads of eight 16-bit local ids each, every load in flight before the first decrement (tb on a
 // 16-byte boundary; rows are padded to whole 16-byte words); the decrements go in two halves of
 // 16 entries per lane. All lanes call with the same range.
-__device__ __forceinline__ void tail_tile(const PeelArgs& a, uint32_t* d, int32_t* q, int* s_tail, int L, int tb,
+__device__ __forceinline__ void tail_tile(const PeelArgs& a, uint32_t* d, uint16_t* q, int* s_tail, int L, int tb,
                                           int len, uint32_t k) {
   static_assert(kTailTile == 2048, "four 16-byte loads of 8 entries per lane");
   const int l = lane_id();
@@ -2031,7 +2032,7 @@ __device__ __forceinline__ void tail_tile(const PeelArgs& a, uint32_t* d, int32_
 // it sees no busy wave (busy first) and then no unclaimed entry; entries are reserved before they
 // are written, so a claimed slot is read once it is no longer -1. False on a timeout. All threads
 // call.
-__device__ __forceinline__ bool tail_chain(const PeelArgs& a, uint32_t* d, int32_t* q, int L, uint32_t k,
+__device__ __forceinline__ bool tail_chain(const PeelArgs& a, uint32_t* d, uint16_t* q, int L, uint32_t k,
                                            int* s_claim, int* s_tail, int* s_busy, long long& st_edges) {
   constexpr int nw = kTailThreads / 64;
   const int l = lane_id();
@@ -2083,7 +2084,8 @@ __device__ __forceinline__ bool tail_chain(const PeelArgs& a, uint32_t* d, int32
     int32_t v = -1;
     if (l < cnt) {
       for (int spin = 0;; ++spin) {
-        v = lds_ld(&q[h + l]);
+        const uint16_t x = lds_ld(&q[h + l]);
+        v = x == kTailQEmpty ? -1 : (int32_t)x;
         if (v >= 0) break;
         if ((spin & 255) == 255 && wall_clock64() - t_start > 400000000ull) break;
       }
@@ -2165,7 +2167,7 @@ __device__ __forceinline__ int tail_excl_scan(int x, int* s_w, int& total) {
 
 // LDS of the tail peel: per vertex an induced degree and a queue slot, plus 64 spare degree slots
 // (one per lane) that lanes without an entry decrement.
-constexpr size_t tail_dyn_lds(int32_t lcap) { return (size_t)lcap * 8 + 64 * 4; }
+constexpr size_t tail_dyn_lds(int32_t lcap) { return (size_t)lcap * 6 + 64 * 4; }
 
 template <bool kChained>
 __global__ __launch_bounds__(kTailThreads) void tail_kernel(PeelArgs a, int32_t lcap) {
@@ -2187,7 +2189,7 @@ __global__ __launch_bounds__(kTailThreads) void tail_kernel(PeelArgs a, int32_t 
   }
   const int L = (int)Ln;
   uint32_t* d = s_dyn;                                       // L degrees, then 64 spare slots
-  int32_t* q = reinterpret_cast<int32_t*>(s_dyn + lcap + 64);
+  uint16_t* q = reinterpret_cast<uint16_t*>(s_dyn + lcap + 64);  // lcap 16-bit queue slots
   const long long* rows = a.trow;
   // per-round timeline in the upper half of the phase timeline (100 MHz clock): start, first
   // frontier extracted, round peeled; then k, first frontier size, vertices peeled so far
@@ -2200,7 +2202,7 @@ __global__ __launch_bounds__(kTailThreads) void tail_kernel(PeelArgs a, int32_t 
   for (int i = tid; i < L; i += kTailThreads) {
     const unsigned dg = (unsigned)(rows[2 * (long long)i + 1] - rows[2 * (long long)i]);
     d[i] = dg;
-    q[i] = -1;  // unwritten queue slot
+    q[i] = kTailQEmpty;  // unwritten queue slot
     mn = min(mn, dg);
   }
   if (tid < 64) d[L + tid] = 0x7fffffffu;  // spare slots: never near any k
@@ -2277,7 +2279,7 @@ __global__ __launch_bounds__(kTailThreads) void tail_kernel(PeelArgs a, int32_t 
         const int i = c0 + tid;
         int rb = 0, dg = 0;
         if (i < tail) {
-          const int32_t v = q[i];
+          const int32_t v = (int32_t)q[i];
           rb = (int)rows[2 * (long long)v];
           dg = (int)(rows[2 * (long long)v + 1] - rb);
         }

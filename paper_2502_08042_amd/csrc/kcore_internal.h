@@ -27,6 +27,7 @@ constexpr int kTailThreads = 1024;    // threads of the single-workgroup tail pe
 constexpr int kTailUnroll = 4;        //   short rows: adjacency entries in flight per thread
 constexpr int kTailBig = 256;         //   rows at least this long are streamed in tiles ...
 constexpr int kTailTile = 2048;       //   ... of this many entries (4 16-byte loads of 8 ids per lane)
+constexpr uint16_t kTailQEmpty = 0xffffu;  // unwritten slot of the tail's 16-bit queue (ids < 65,535)
 
 enum StatIdx {
   ST_ROUNDS = 0, ST_SUBROUNDS, ST_BARRIERS, ST_PEELED, ST_EDGES, ST_DECR, ST_COMBINED, ST_SCANNED,
