@@ -140,8 +140,10 @@ def test_residual_rows_do_not_change_results(mode):
 
 
 def _tail_cases():
+    # rmat16x4: 23,472 vertices are live at the boundary of round 2, so the largest handoff fills
+    # nearly the whole tail capacity (16-bit local ids and queue slots up to 23,471)
     return [("rmat13", gg.rmat(13, 16, 7)), ("road256", gg.grid_road(256, 0.05, 0.01, 3)),
-            ("hcns120", None), ("er5000", gg.erdos_renyi(5000, 0.01, 8))]
+            ("hcns120", None), ("er5000", gg.erdos_renyi(5000, 0.01, 8)), ("rmat16x4", gg.rmat(16, 4, 9))]
 
 
 @pytest.mark.parametrize("mode", MODES)
@@ -164,6 +166,8 @@ def test_tail_handoff_sizes(mode):
                 assert st["rounds"] == ls["nonempty_rounds"], (st, ls)
                 if mode == "levelsync":
                     assert st["subrounds"] == ls["subrounds"], (st, ls)
+                if name == "rmat16x4" and tail == 1 << 30:
+                    assert st["tail_vertices"] > 17408, st
 
 
 def test_tail_handoff_called_off(monkeypatch):
