@@ -189,6 +189,15 @@ def bench_batch(args):
     ms_loop = (t4 - t3) * 1000.0
     loop_parity = bool(np.array_equal(out.cpu().numpy(), want))
     B = alg_bytes(V, m, st)
+    # HBM bytes per batched launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs (calibrated
+    # against a plain copy), valid only for the kernel source they were taken on
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", "batched_kernel_batch4096_traffic.txt")
+    if os.path.exists(tfile):
+        with open(tfile) as f:
+            tj = json.load(f)
+        if tj.get("kernel_source_sha") == kernel_sha():
+            traffic = tj.get("bytes_per_launch")
     return {
         "metric": METRIC, "value": round(G / (ms_batch / 1000.0), 1), "unit": "graphs/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_batch, 4),
@@ -202,8 +211,9 @@ def bench_batch(args):
         "parity": parity and loop_parity,
         "roofline": {"bound": "hbm", "achieved": round(B / (kern_ms / 1000.0) / 1e9, 2),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(B / (kern_ms / 1000.0) / 1e9 / HBM_PEAK_GBS, 5), "traffic": None,
-                     "alg_bytes_per_launch": B, "kernel_ms_per_launch": round(kern_ms, 4)},
+                     "frac": round(B / (kern_ms / 1000.0) / 1e9 / HBM_PEAK_GBS, 5), "traffic": traffic,
+                     "alg_bytes_per_launch": B, "kernel": "batched_kernel",
+                     "kernel_ms_per_launch": round(kern_ms, 4)},
     }
 
 
