@@ -120,7 +120,8 @@ def bench_single(args):
                      "kernel_ms_per_launch": round(avg_ms, 4)},
     }
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(off, adj, m, out)
+        # the same oracle run also checks the last decomposition's coreness, vertex by vertex
+        res["cpu_baseline"], res["parity"] = cpu_baseline(off, adj, m, out)
     return res
 
 
@@ -132,9 +133,11 @@ def cpu_baseline(off, adj, m, out_dev):
     h_off = off.cpu().numpy()
     h_adj = adj.cpu().numpy()
     log(f"[bench] host copy {time.time() - t0:.1f}s; running the oracle once on one core")
-    secs = oracle.time_bz(h_off, h_adj, repeats=1)[0]
+    core = np.empty(len(h_off) - 1, dtype=np.int32)
+    secs = oracle.time_bz(h_off, h_adj, repeats=1, core_out=core)[0]
     return {"value": round(m / secs / 1e9, 5), "unit": "GTEPS", "cores": 1, "kind": "oracle",
-            "sample": f"whole graph, one run of the sequential oracle ({secs:.1f} s)"}
+            "sample": f"whole graph, one run of the sequential oracle ({secs:.1f} s)"}, \
+        bool(np.array_equal(out_dev.cpu().numpy(), core))
 
 
 def bench_batch(args):

@@ -118,10 +118,13 @@ def levelsync(offsets, adj, lib=None):
     return core, sub, dict(zip(LEVELSYNC_FIELDS, (int(x) for x in st)))
 
 
-def time_bz(offsets, adj, repeats: int = 1) -> list[float]:
-    """Wall-clock seconds of each of ``repeats`` oracle_bz runs on one host thread."""
+def time_bz(offsets, adj, repeats: int = 1, core_out=None) -> list[float]:
+    """Wall-clock seconds of each of ``repeats`` oracle_bz runs on one host thread; the coreness
+    of the runs lands in ``core_out`` (an int32 array of n entries) when one is given."""
     off, a, n = _prep(offsets, adj)
-    core = np.empty(n, dtype=np.int32)
+    core = np.empty(n, dtype=np.int32) if core_out is None else core_out
+    if core.dtype != np.int32 or core.shape != (n,) or not core.flags.c_contiguous:
+        raise ValueError("core_out must be a contiguous int32 array of n entries")
     lib = load()
     out = []
     for _ in range(repeats):
