@@ -119,8 +119,10 @@ typedef struct {
                             synchronise at workgroup level instead of grid-wide (the k-core
                             query never hands over); costs 4 bytes per vertex plus
                             min(m, tail^2) 16-bit entries of workspace; capped at what the
-                            workgroup's LDS holds at 6 bytes per vertex (23,552 on a 160 KB-LDS
-                            device); 0 = default, min(that cap, n / 8); -1 = never */
+                            workgroup's LDS holds at 6 bytes per vertex (on a 160 KB-LDS device
+                            26,624 in chained mode, 23,552 in the level-sync and offline modes,
+                            whose tail keeps 16 KB of scan arrays); 0 = default, min(that cap,
+                            n / 8); -1 = never */
 } kcore_options;
 
 /* Counters of one decomposition (filled when a kcore_stats* is passed; that call synchronises

@@ -42,7 +42,7 @@ struct DevInfo {
   int cus = 0;
   size_t lds_per_block = 0;
   int peel_bpc = 0;
-  int32_t tail_lcap = 0;  // vertices the tail peel's LDS holds
+  int32_t tail_lcap[2] = {0, 0};  // vertices the tail peel's LDS holds: level-sync, chained instance
 };
 
 std::mutex g_mu;
@@ -86,13 +86,17 @@ int dev_info(int dev, DevInfo& out) {
   HIP_TRY(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
   d.lds_per_block = (size_t)lds;
   HIP_TRY(kc::peel_occupancy(&d.peel_bpc));
-  size_t tail_static = 0;
-  HIP_TRY(kc::tail_static_lds(&tail_static));
-  // 6 bytes per vertex (induced degree and 16-bit queue slot) plus 64 spare slots, in whole
-  // 1024-vertex steps, below the 16-bit id limit
-  d.tail_lcap = lds > (int)tail_static + 256 ? (int32_t)(((size_t)lds - tail_static - 256) / 6 / 1024 * 1024) : 0;
-  d.tail_lcap = std::min<int32_t>(d.tail_lcap, 64512);
-  if (d.tail_lcap > 0) HIP_TRY(kc::tail_allow_lds(d.tail_lcap));
+  for (int ch = 0; ch < 2; ++ch) {
+    size_t tail_static = 0;
+    HIP_TRY(kc::tail_static_lds(ch, &tail_static));
+    // 6 bytes per vertex (induced degree and 16-bit queue slot) plus 64 spare slots, in whole
+    // 1024-vertex steps, below the 16-bit id limit; the chained instance has almost no static LDS
+    // (the level-sync one keeps four 1024-entry scan arrays), so it holds more vertices
+    int32_t lc = lds > (int)tail_static + 256 ? (int32_t)(((size_t)lds - tail_static - 256) / 6 / 1024 * 1024) : 0;
+    lc = std::min<int32_t>(lc, 64512);
+    if (lc > 0) HIP_TRY(kc::tail_allow_lds(ch, lc));
+    d.tail_lcap[ch] = lc;
+  }
   g_dev[dev] = d;
   out = d;
   return KCORE_OK;
@@ -417,11 +421,12 @@ static int peel_impl(const int64_t* offsets, const int32_t* adj, int64_t n, int3
   // tail handoff: the last live vertices (at most what the tail peel's LDS holds) are peeled by
   // one workgroup; their local rows hold at most min(m, L (L - 1)) entries (simple graph)
   const int32_t to = opt ? opt->tail : 0;
+  const int tail_ch = (mode == KCORE_MODE_CHAINED || sampling) ? 1 : 0;  // which tail instance runs
   // (default n / 8: one workgroup streams the rows of what it takes over from one CU, which pays on
   // a large graph's last few thousand rounds but not when the tail would hold much of the graph)
   int64_t tail_vmax = (to < 0 || k_query > 0 || sampling)
                           ? 0
-                          : std::min<int64_t>(to ? to : std::max<int64_t>(n / 8, 1), di.tail_lcap);
+                          : std::min<int64_t>(to ? to : std::max<int64_t>(n / 8, 1), di.tail_lcap[tail_ch]);
   // (local ids are 16-bit: at most 65,535 vertices, 0xffff pads the rows)
   tail_vmax = std::min<int64_t>(std::min<int64_t>(tail_vmax, n), 65535);
   // (plus up to 7 pad entries per row: rows start on 16-byte boundaries)

@@ -2361,24 +2361,18 @@ hipError_t launch_tail(const PeelArgs& a, int32_t lcap, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t tail_static_lds(size_t* bytes) {
+hipError_t tail_static_lds(int chained, size_t* bytes) {
   hipFuncAttributes fa;
-  size_t mx = 0;
-  for (const void* f : {reinterpret_cast<const void*>(tail_kernel<true>), reinterpret_cast<const void*>(tail_kernel<false>)}) {
-    hipError_t e = hipFuncGetAttributes(&fa, f);
-    if (e != hipSuccess) return e;
-    mx = fa.sharedSizeBytes > mx ? fa.sharedSizeBytes : mx;
-  }
-  *bytes = mx;
-  return hipSuccess;
+  const void* f = chained ? reinterpret_cast<const void*>(tail_kernel<true>)
+                          : reinterpret_cast<const void*>(tail_kernel<false>);
+  hipError_t e = hipFuncGetAttributes(&fa, f);
+  if (e == hipSuccess) *bytes = fa.sharedSizeBytes;
+  return e;
 }
-
-hipError_t tail_allow_lds(int32_t lcap) {
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(tail_kernel<true>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)tail_dyn_lds(lcap));
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(tail_kernel<false>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)tail_dyn_lds(lcap));
+hipError_t tail_allow_lds(int chained, int32_t lcap) {
+  const void* f = chained ? reinterpret_cast<const void*>(tail_kernel<true>)
+                          : reinterpret_cast<const void*>(tail_kernel<false>);
+  return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)tail_dyn_lds(lcap));
 }
 
 // Largest-first order of the graphs of a batch: counting sort on floor(log2(edges + 1)),

@@ -188,8 +188,9 @@ hipError_t launch_init_ctl(PeelCtl* c, hipStream_t s);
 // Single-workgroup peel of the live vertices handed over by peel_kernel (returns at once when none
 // were); lcap = vertices its LDS holds.
 hipError_t launch_tail(const PeelArgs& a, int32_t lcap, hipStream_t s);
-hipError_t tail_static_lds(size_t* bytes);
-hipError_t tail_allow_lds(int32_t lcap);
+// Static LDS of the chained (1) or level-sync (0) instance, and allowing it lcap vertices.
+hipError_t tail_static_lds(int chained, size_t* bytes);
+hipError_t tail_allow_lds(int chained, int32_t lcap);
 hipError_t launch_validate(const int64_t* off, const int32_t* adj, int64_t n, const int64_t* vptr,
                            int32_t G, unsigned* status, unsigned long long* xsum, hipStream_t s);
 
