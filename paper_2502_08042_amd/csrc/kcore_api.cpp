@@ -43,6 +43,8 @@ struct DevInfo {
   size_t lds_per_block = 0;
   int peel_bpc = 0;
   int32_t tail_lcap[2] = {0, 0};  // vertices the tail peel's LDS holds: level-sync, chained instance
+  size_t batch_lds = 0;           // dynamic LDS per batched workgroup
+  int batch_bpc = 0;              // batched workgroups resident per CU with it
 };
 
 std::mutex g_mu;
@@ -97,6 +99,21 @@ int dev_info(int dev, DevInfo& out) {
     if (lc > 0) HIP_TRY(kc::tail_allow_lds(ch, lc));
     d.tail_lcap[ch] = lc;
   }
+  // batched peel: its registers allow a fixed number of workgroups per CU; give each the most LDS
+  // that keeps that number (8 bytes per vertex held in LDS), at least 48 KB when the device has it
+  size_t bl = std::min<size_t>(48 * 1024, d.lds_per_block / 2);
+  int bb = 0;
+  HIP_TRY(kc::batched_occupancy(bl, &bb));
+  for (size_t c = d.lds_per_block / 2 / 512 * 512; c > bl; c -= 512) {
+    int b2 = 0;
+    HIP_TRY(kc::batched_occupancy(c, &b2));
+    if (b2 >= bb) {
+      bl = c;
+      break;
+    }
+  }
+  d.batch_lds = bl;
+  d.batch_bpc = bb;
   g_dev[dev] = d;
   out = d;
   return KCORE_OK;
@@ -708,11 +725,9 @@ static int batched_impl(const int64_t* graph_vptr, const int64_t* offsets, const
     if (int rc = run_validate(offsets, adj, total_vertices, graph_vptr, num_graphs, w->vstat, stream)) return rc;
   }
   // LDS per workgroup: induced degrees + peel queue, 8 bytes per vertex
-  size_t lds = 48 * 1024;
-  if (lds > di.lds_per_block / 2) lds = di.lds_per_block / 2;
+  const size_t lds = di.batch_lds;
   const int32_t cap = (int32_t)(lds / 8);
-  int bpc = 0;
-  HIP_TRY(kc::batched_occupancy(lds, &bpc));
+  int bpc = di.batch_bpc;
   if (opt && opt->blocks_per_cu && opt->blocks_per_cu < bpc) bpc = opt->blocks_per_cu;
   if (bpc < 1) return fail(KCORE_EDEVICE, "batched kernel cannot be resident on this device");
   int blocks = bpc * di.cus;

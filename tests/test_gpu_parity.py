@@ -309,11 +309,13 @@ def test_batched_equals_per_graph_and_handles_empty_graphs(mode):
 
 @pytest.mark.parametrize("mode", MODES)
 def test_batched_large_graph_in_global_memory(mode):
-    # graphs above the LDS capacity keep their state in the global workspace, with a peeled bitmap
-    # in LDS up to 393,216 vertices and without one above (R-MAT scale 19)
-    r15, r19 = gg.rmat(15, 8, 3), gg.rmat(19, 4, 12)
+    # graphs above the LDS capacity (6,144 to ~9,200 vertices, by what the device's LDS allows at
+    # the kernel's occupancy) keep their state in the global workspace, with a peeled bitmap in LDS
+    # up to 64 times that capacity (R-MAT scale 19) and without one above (scale 20)
+    r15, r19, r20 = gg.rmat(15, 8, 3), gg.rmat(19, 4, 12), gg.rmat(20, 2, 13)
     road = gg.grid_road(200, 0.05, 0.01, 9)
-    parts = [(r15.offsets, r15.adj), G.complete(40), (road.offsets, road.adj), (r19.offsets, r19.adj)]
+    parts = [(r15.offsets, r15.adj), G.complete(40), (road.offsets, road.adj), (r19.offsets, r19.adj),
+             (r20.offsets, r20.adj)]
     off, adj = G.union(parts)
     vptr = np.cumsum([0] + [len(p[0]) - 1 for p in parts]).astype(np.int64)
     say(f"[gpu] batched large graphs V={len(off) - 1} m={len(adj)} mode={mode}")
