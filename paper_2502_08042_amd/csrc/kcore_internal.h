@@ -9,7 +9,7 @@ constexpr int kPeelThreads = 1024;   // threads per persistent workgroup (16 wav
 constexpr int kWaves = kPeelThreads / 64;
 constexpr int kStage = 256;          // per-wave LDS staging entries for frontier appends
 constexpr int kLocalQ = 512;         // per-wave local queue (chained mode)
-constexpr int kCombBits = 12;
+constexpr int kCombBits = 13;
 constexpr int kCombSlots = 1 << kCombBits;  // per-workgroup LDS combining table for hub targets
 constexpr int kCombProbe = 4;               // linear-probe window of that table
 constexpr int kEdgeUnroll = 2;              // adjacency entries in flight per lane (rows)
