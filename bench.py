@@ -384,10 +384,12 @@ def bench_kquery(args, k: int = 1000):
 
 
 def kernel_sha() -> str:
+    """Hash of the kernel sources (the device code and the constants it is built with)."""
     import hashlib
     h = hashlib.sha1()
-    with open(os.path.join(ROOT, "paper_2502_08042_amd", "csrc", "kcore_device.hip"), "rb") as f:
-        h.update(f.read())
+    for name in ("kcore_device.hip", "kcore_internal.h"):
+        with open(os.path.join(ROOT, "paper_2502_08042_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 
