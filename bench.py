@@ -1,13 +1,21 @@
 #!/usr/bin/env python3
 """Benchmark of the MI355X k-core library.
 
-Default: single-graph peel of the 16M-vertex Chung-Lu power-law graph (gamma 2.1, ~1B directed
-entries, planted 5000-vertex G(n, 0.8) block; seed 3) — the headline workload. Reports peeled
-directed edges per second (GTEPS: adjacency entries m divided by the time of one decomposition,
-graph resident in HBM), the roofline position of the peel kernel and the CPU oracle's rate on the
-same graph.
+Default (``--workload all``): the headline single-graph peel of the 16M-vertex Chung-Lu power-law
+graph (gamma 2.1, ~1B directed entries, planted 5000-vertex G(n, 0.8) block; seed 3), reported as
+peeled directed edges per second (GTEPS: adjacency entries m over the time of one decomposition,
+graph resident in HBM) with its roofline position and the CPU oracle beside it; then every other
+workload, each checked against the oracle, as keys of the same line:
 
-    python bench.py [--steps K] [--warmup W] [--workload chunglu|grid|rmat16|batch|serve|kquery]
+  * ``rmat16``   R-MAT scale 16, edge factor 16 (single graph)
+  * ``grid``     4096 x 4096 road-like grid (single graph, deep peel chains)
+  * ``hcns``     staircase of coreness 20,000 (n = 40,000, 0.8B entries), with and without the
+                 multi-bucket active set
+  * ``batch``    4,096 graphs in one segmented CSR: one batched launch against a loop of the
+                 single-graph call over the same graphs
+  * ``serve``    Poisson arrivals at 20k requests/s (1% R-MAT scale 20), p50/p99 latency
+
+    python bench.py [--steps K] [--warmup W] [--workload all|chunglu|rmat16|grid|hcns|batch|serve|kquery]
 
 Prints exactly one JSON line. One GPU only: --gpus N with N > 1 exits with a message.
 """
@@ -17,6 +25,7 @@ import argparse
 import ctypes
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -25,6 +34,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "peeled directed edges/sec (GTEPS) + % HBM peak; batched graphs/sec & p99 latency"
 HBM_PEAK_GBS = 8000.0
+ORACLE_RUNS = 5          # timed oracle runs after one warm-up (the paper's protocol: mean of 5)
 
 
 def log(*a):
@@ -32,115 +42,227 @@ def log(*a):
 
 
 def alg_bytes(n: int, m: int, st: dict) -> int:
-    """Algorithmic bytes of one decomposition: adjacency read once (4m), one liveness probe per
-    entry (4m), one 4-byte read-modify-write per applied decrement, whether applied one at a time
-    or as a combined count (8 each), degree init from offsets (8(n+1)) and induced-degree init
-    (4n), the offsets pair of each peeled vertex (16n), coreness write plus frontier write and read
-    (12n), and 4 bytes per scanned active-set slot."""
-    return (4 * m + 4 * m + 8 * (st["decrements"] + st["combined"]) + 8 * (n + 1) + 4 * n
-            + 16 * n + 12 * n + 4 * st["scanned"])
+    """Algorithmic bytes of one decomposition (the work bound of Thm. 3.1 priced in bytes): every
+    adjacency entry read once (4m) with one read of its target's induced degree (4m), one 4-byte
+    write per live decrement (a decrement landing on a vertex still above k: at most m/2), degree
+    initialisation from the offsets (8(n+1)) into the induced degrees (4n), the offsets pair of each
+    peeled vertex (16n), its coreness write and frontier write and read (12n), and 4 bytes per
+    active-set slot scanned."""
+    return (4 * m + 4 * m + 4 * st["live_decrements"] + 8 * (n + 1) + 4 * n + 16 * n + 12 * n
+            + 4 * st["scanned"])
 
 
-def build_workload(name: str):
+def host_info() -> dict:
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cpus": usable}
+
+
+def timed_calls(fn, steps: int, warmup: int):
+    """Runs fn() warmup times, then steps times between HIP events recorded on the current
+    stream (the stream the library launches on). Returns (wall ms per call, per-call event ms)."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    stream = torch.cuda.current_stream()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for e0, e1 in evs:
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    return (t2 - t1) * 1000.0 / steps, [e0.elapsed_time(e1) for e0, e1 in evs]
+
+
+def summary(per):
+    return {"mean": round(statistics.fmean(per), 4), "median": round(statistics.median(per), 4),
+            "min": round(min(per), 4), "max": round(max(per), 4)}
+
+
+def oracle_timing(h_off, h_adj, runs: int = ORACLE_RUNS):
+    """The oracle (sequential Batagelj-Zaversnik, one host thread): one warm-up, then `runs`
+    timed runs. Returns (coreness of the last run, list of seconds)."""
     import numpy as np
+    import oracle
+    core = np.empty(len(h_off) - 1, dtype=np.int32)
+    secs = oracle.time_bz(h_off, h_adj, repeats=runs + 1, core_out=core)
+    return core, secs[1:]
+
+
+def cpu_baseline_entry(m: int, secs, sample: str) -> dict:
+    med = statistics.median(secs)
+    return {"value": round(m / med / 1e9, 5), "unit": "GTEPS", "cores": 1, "kind": "oracle",
+            "sample": sample, "median_s": round(med, 4), "mean_s": round(statistics.fmean(secs), 4),
+            "runs": len(secs), "warmup_runs": 1, **host_info()}
+
+
+def release():
+    import torch
+    import paper_2502_08042_amd as K
+    torch.cuda.synchronize()
+    K.release_workspaces()
+    torch.cuda.empty_cache()
+
+
+# ---------------------------------------------------------------------------------------------
+# single graph
+# ---------------------------------------------------------------------------------------------
+def build_workload(name: str):
     import torch
     import graphgen as gg
     if name == "chunglu":
         import graphgen.gpu as gp
         off, adj = gp.config_chung_lu_device()
-        desc = ("Chung-Lu n=2^24 gamma=2.1 32n endpoint pairs, degree cap 1e6, planted 5000-vertex "
-                "G(n,0.8) block, symmetric int32 CSR, seed 3")
-        return off, adj, desc
+        return off, adj, ("Chung-Lu n=2^24 gamma=2.1 32n endpoint pairs, degree cap 1e6, planted "
+                          "5000-vertex G(n,0.8) block, symmetric int32 CSR, seed 3")
+    if name == "hcns":
+        import graphgen.gpu as gp
+        off, adj = gp.hcns_device(20000)
+        return off, adj, ("staircase of coreness K=20000: clique on K+1 vertices plus u_i adjacent "
+                          "to clique vertices 0..i-1 (n=40000, 0.8B entries)")
     if name == "grid":
         g = gg.config_grid4096()
         desc = "road-like grid 4096x4096, 5% edges deleted, 1% unit-square diagonals, seed 2"
     elif name == "rmat16":
         g = gg.config_rmat16()
-        desc = "RMAT scale 16 edge factor 16 a=.57 b=.19 c=.19, symmetrized, seed 1"
+        desc = "RMAT scale 16 edge factor 16 a=.57 b=.19 c=.19, symmetrized, dedup'd, seed 1"
     else:
         raise ValueError(name)
-    return (torch.from_numpy(g.offsets).cuda(), torch.from_numpy(g.adj).cuda(), desc)
+    return torch.from_numpy(g.offsets).cuda(), torch.from_numpy(g.adj).cuda(), desc
 
 
-def bench_single(args):
-    import numpy as np
+def measure_single(off, adj, steps, warmup, mode="auto", **tuning):
+    """Times kcore_decompose on a resident graph. Returns (result dict, stats, coreness tensor)."""
     import torch
     import paper_2502_08042_amd as K
-    t0 = time.time()
-    off, adj, desc = build_workload(args.workload)
-    torch.cuda.synchronize()
     n, m = off.numel() - 1, adj.numel()
-    log(f"[bench] workload {args.workload}: n={n} m={m} built in {time.time() - t0:.1f}s")
     out = torch.empty(n, dtype=torch.int32, device=off.device)
-    for _ in range(args.warmup):
-        K.decompose(off, adj, out, mode=args.mode)
-    _, st = K.decompose(off, adj, out, mode=args.mode, stats=True)
-    log(f"[bench] stats {json.dumps(st)}")
-    stream = torch.cuda.current_stream()
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for e0, e1 in evs:
-        e0.record(stream)
-        K.decompose(off, adj, out, mode=args.mode)
-        e1.record(stream)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    per = [e0.elapsed_time(e1) for e0, e1 in evs]
-    ms_step = (t2 - t1) * 1000.0 / args.steps
-    avg_ms = sum(per) / len(per)
-    value = m / (ms_step / 1000.0) / 1e9
+    K.decompose(off, adj, out, mode=mode, **tuning)  # workspace allocation, outside the timing
+    _, st = K.decompose(off, adj, out, mode=mode, stats=True, **tuning)
+    wall_ms, per = timed_calls(lambda: K.decompose(off, adj, out, mode=mode, **tuning), steps, warmup)
+    K.check()  # device status of the timed calls
+    ev = summary(per)
     B = alg_bytes(n, m, st)
-    achieved = B / (avg_ms / 1000.0) / 1e9
-    # HBM bytes per decomposition (peel kernel + tail kernel) from the rocprofv3 FETCH_SIZE /
-    # WRITE_SIZE runs (calibrated against a plain copy), valid only for the kernel source they were
-    # taken on
-    traffic = None
-    tfile = os.path.join(ROOT, "profiles", f"peel_kernels_{args.workload}_traffic.txt")
-    if os.path.exists(tfile):
-        with open(tfile) as f:
-            tj = json.load(f)
-        if tj.get("kernel_source_sha") == kernel_sha() and tj.get("mode") == args.mode:
-            traffic = tj.get("bytes_per_launch")
+    res = {"n": n, "m": m, "mode": mode, "ms_per_step": round(wall_ms, 4), "event_ms": ev,
+           "gteps": round(m / (ev["median"] / 1000.0) / 1e9, 4),
+           "kmax": st["kmax"], "rounds": st["rounds"], "subrounds": st["subrounds"],
+           "barriers": st["barriers"], "tail_vertices": st["tail_vertices"],
+           "live_decrements": st["live_decrements"], "scanned": st["scanned"],
+           "bucket_inserts": st["bucket_inserts"],
+           "alg_bytes": B, "hbm_frac": round(B / (ev["mean"] / 1000.0) / 1e9 / HBM_PEAK_GBS, 5)}
+    if tuning:
+        res["options"] = tuning
+    return res, st, out
+
+
+def bench_chunglu(args):
+    """The headline: one decomposition of the Chung-Lu graph per step."""
+    import numpy as np
+    t0 = time.time()
+    off, adj, desc = build_workload("chunglu")
+    n, m = off.numel() - 1, adj.numel()
+    log(f"[bench] chunglu: n={n} m={m} built in {time.time() - t0:.1f}s")
+    r, st, out = measure_single(off, adj, args.steps, args.warmup, mode=args.mode)
+    log(f"[bench] chunglu stats {json.dumps(st)}")
+    ev = r["event_ms"]
+    B = r["alg_bytes"]
+    achieved = B / (ev["mean"] / 1000.0) / 1e9
     res = {
-        "metric": METRIC, "value": round(value, 4), "unit": "GTEPS", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+        "metric": METRIC, "value": round(m / (r["ms_per_step"] / 1000.0) / 1e9, 4), "unit": "GTEPS",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
         "higher_is_better": True, "scaling": "strong", "vs_baseline": None, "dtype": "int32",
         "data": "synthetic",
-        "config": {"workload": desc, "n": n, "m": m, "mode": args.mode,
-                   "kmax": st["kmax"], "rounds": st["rounds"], "subrounds": st["subrounds"],
-                   "barriers": st["barriers"], "tail_vertices": st["tail_vertices"]},
+        "config": {"workload": desc, "n": n, "m": m, "mode": args.mode, "kmax": r["kmax"],
+                   "rounds": r["rounds"], "subrounds": r["subrounds"], "barriers": r["barriers"],
+                   "tail_vertices": r["tail_vertices"]},
+        "gpu_event_ms": ev,
         # one decomposition = the persistent peel kernel, then the single-workgroup tail kernel on
         # the last live vertices (plus two tiny set-up kernels), all inside the events
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
-                     "traffic": traffic, "alg_bytes_per_launch": B,
-                     "kernel": "peel_kernel + tail_kernel",
-                     "kernel_ms_per_launch": round(avg_ms, 4)},
+                     "traffic": traffic_from_profile("peel_kernels_chunglu_traffic.txt", args.mode),
+                     "alg_bytes_per_launch": B, "live_decrements": r["live_decrements"],
+                     "scanned": r["scanned"], "kernel": "peel_kernel + tail_kernel",
+                     "kernel_ms_per_launch": ev["mean"]},
     }
     if not args.no_cpu_baseline:
-        # the same oracle run also checks the last decomposition's coreness, vertex by vertex
-        res["cpu_baseline"], res["parity"] = cpu_baseline(off, adj, m, out)
+        h_off, h_adj = off.cpu().numpy(), adj.cpu().numpy()
+        log(f"[bench] chunglu oracle: 1 warm-up + {ORACLE_RUNS} runs on one core")
+        core, secs = oracle_timing(h_off, h_adj)
+        res["cpu_baseline"] = cpu_baseline_entry(
+            m, secs, f"the whole graph, 1 warm-up + {len(secs)} timed runs of the sequential oracle "
+            f"(median {statistics.median(secs):.2f} s)")
+        res["parity"] = bool(np.array_equal(out.cpu().numpy(), core))
+    del off, adj, out
+    release()
     return res
 
 
-def cpu_baseline(off, adj, m, out_dev):
-    """The oracle (sequential Batagelj-Zaversnik, one host thread) on the same graph, once."""
+def bench_single_config(name, args, steps, warmup):
+    """One of the other single-graph workloads: timing, counters and parity with the oracle."""
     import numpy as np
-    import oracle
     t0 = time.time()
-    h_off = off.cpu().numpy()
-    h_adj = adj.cpu().numpy()
-    log(f"[bench] host copy {time.time() - t0:.1f}s; running the oracle once on one core")
-    core = np.empty(len(h_off) - 1, dtype=np.int32)
-    secs = oracle.time_bz(h_off, h_adj, repeats=1, core_out=core)[0]
-    return {"value": round(m / secs / 1e9, 5), "unit": "GTEPS", "cores": 1, "kind": "oracle",
-            "sample": f"whole graph, one run of the sequential oracle ({secs:.1f} s)"}, \
-        bool(np.array_equal(out_dev.cpu().numpy(), core))
+    off, adj, desc = build_workload(name)
+    n, m = off.numel() - 1, adj.numel()
+    log(f"[bench] {name}: n={n} m={m} built in {time.time() - t0:.1f}s")
+    r, st, out = measure_single(off, adj, steps, warmup, mode=args.mode)
+    r["workload"] = desc
+    if name == "hcns":
+        # the construction fixes every coreness: u_i has coreness i and the clique K
+        K_ = n // 2
+        want = np.concatenate([np.full(K_ + 1, K_, dtype=np.int32), np.arange(1, K_, dtype=np.int32)])
+        r["parity"] = bool(np.array_equal(out.cpu().numpy(), want))
+        r["parity_against"] = "closed form of the construction"
+        rb, _, outb = measure_single(off, adj, steps, warmup, mode=args.mode, buckets=1 << 30)
+        r["with_buckets"] = {k: rb[k] for k in ("ms_per_step", "event_ms", "gteps", "rounds",
+                                                "barriers", "scanned", "bucket_inserts",
+                                                "tail_vertices", "hbm_frac")}
+        r["with_buckets"]["parity"] = bool(np.array_equal(outb.cpu().numpy(), want))
+        r["buckets_speedup"] = round(r["event_ms"]["median"] / rb["event_ms"]["median"], 3)
+        del outb
+    else:
+        h_off, h_adj = off.cpu().numpy(), adj.cpu().numpy()
+        core, secs = oracle_timing(h_off, h_adj)
+        r["parity"] = bool(np.array_equal(out.cpu().numpy(), core))
+        r["cpu_oracle"] = {"median_s": round(statistics.median(secs), 5),
+                           "gteps": round(m / statistics.median(secs) / 1e9, 5), "runs": len(secs)}
+    del off, adj, out
+    release()
+    return r
 
 
-def bench_batch(args):
+def traffic_from_profile(fname: str, mode: str):
+    """HBM bytes per launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs kept in profiles/
+    (calibrated against a plain copy), valid only for the kernel source they were taken on."""
+    tfile = os.path.join(ROOT, "profiles", fname)
+    if not os.path.exists(tfile):
+        return None
+    with open(tfile) as f:
+        tj = json.load(f)
+    if tj.get("kernel_source_sha") == kernel_sha() and tj.get("mode", mode) == mode:
+        return tj.get("bytes_per_launch")
+    return None
+
+
+# ---------------------------------------------------------------------------------------------
+# batched and serving
+# ---------------------------------------------------------------------------------------------
+def bench_batch(args, steps, warmup):
     """4096 lognormal-sized graphs in one segmented CSR: one batched launch vs a loop of the
     single-graph call over the same graphs."""
     import numpy as np
@@ -156,68 +278,47 @@ def bench_batch(args):
     adj = torch.from_numpy(b.adj).cuda()
     log(f"[bench] batch G={G} V={V} m={m} built in {time.time() - t0:.1f}s")
     out = torch.empty(V, dtype=torch.int32, device="cuda")
-    for _ in range(args.warmup):
-        K.decompose_batched(vptr, off, adj, out)
+    K.decompose_batched(vptr, off, adj, out)
     _, st = K.decompose_batched(vptr, off, adj, out, stats=True)
     want = oracle.bz(b.offsets, b.adj)
     parity = bool(np.array_equal(out.cpu().numpy(), want))
-    stream = torch.cuda.current_stream()
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for e0, e1 in evs:
-        e0.record(stream)
-        K.decompose_batched(vptr, off, adj, out)
-        e1.record(stream)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    ms_batch = (t2 - t1) * 1000.0 / args.steps
-    kern_ms = sum(e0.elapsed_time(e1) for e0, e1 in evs) / args.steps
+    wall_ms, per = timed_calls(lambda: K.decompose_batched(vptr, off, adj, out), steps, warmup)
+    K.check()
+    ev = summary(per)
     # the same graphs, one single-graph call each (local ids)
     parts = []
     for g in range(G):
         lo, hi = int(b.vptr[g]), int(b.vptr[g + 1])
         e0_, e1_ = int(b.offsets[lo]), int(b.offsets[hi])
-        parts.append((off[lo:hi + 1] - e0_, adj[e0_:e1_] - lo, out[lo:hi], e1_ - e0_))
-    for o_, a_, c_, mm in parts[:64]:
+        parts.append((off[lo:hi + 1] - e0_, adj[e0_:e1_] - lo, out[lo:hi]))
+    for o_, a_, c_ in parts[:64]:
         K.decompose(o_, a_, c_)
     out.fill_(-1)
     torch.cuda.synchronize()
     t3 = time.perf_counter()
-    for o_, a_, c_, mm in parts:
+    for o_, a_, c_ in parts:
         K.decompose(o_, a_, c_)
     torch.cuda.synchronize()
-    t4 = time.perf_counter()
-    ms_loop = (t4 - t3) * 1000.0
+    ms_loop = (time.perf_counter() - t3) * 1000.0
+    K.check()
     loop_parity = bool(np.array_equal(out.cpu().numpy(), want))
     B = alg_bytes(V, m, st)
-    # HBM bytes per batched launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs (calibrated
-    # against a plain copy), valid only for the kernel source they were taken on
-    traffic = None
-    tfile = os.path.join(ROOT, "profiles", "batched_kernel_batch4096_traffic.txt")
-    if os.path.exists(tfile):
-        with open(tfile) as f:
-            tj = json.load(f)
-        if tj.get("kernel_source_sha") == kernel_sha():
-            traffic = tj.get("bytes_per_launch")
-    return {
-        "metric": METRIC, "value": round(G / (ms_batch / 1000.0), 1), "unit": "graphs/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_batch, 4),
-        "higher_is_better": True, "scaling": "strong", "vs_baseline": None, "dtype": "int32",
-        "data": "synthetic",
-        "config": {"workload": "4096 graphs, lognormal n (median 2000, sigma 1, 100..100000), even "
-                   "ER avg deg 8 / odd RMAT 8n draws, one segmented CSR, seed 4",
-                   "graphs": G, "vertices": V, "m": m},
-        "batched_gteps": round(m / (ms_batch / 1000.0) / 1e9, 4),
-        "per_graph_loop_ms": round(ms_loop, 3), "speedup_vs_loop": round(ms_loop / ms_batch, 2),
-        "parity": parity and loop_parity,
-        "roofline": {"bound": "hbm", "achieved": round(B / (kern_ms / 1000.0) / 1e9, 2),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(B / (kern_ms / 1000.0) / 1e9 / HBM_PEAK_GBS, 5), "traffic": traffic,
-                     "alg_bytes_per_launch": B, "kernel": "batched_kernel",
-                     "kernel_ms_per_launch": round(kern_ms, 4)},
-    }
+    res = {"workload": "4096 graphs, lognormal n (median 2000, sigma 1, 100..100000), even ER avg "
+                       "deg 8 / odd RMAT 8n draws, one segmented CSR, seed 4",
+           "graphs": G, "vertices": V, "m": m, "steps": steps, "ms_per_step": round(wall_ms, 4),
+           "event_ms": ev, "graphs_per_s": round(G / (wall_ms / 1000.0), 1),
+           "gteps": round(m / (wall_ms / 1000.0) / 1e9, 4),
+           "per_graph_loop_ms": round(ms_loop, 3), "speedup_vs_loop": round(ms_loop / wall_ms, 2),
+           "parity": parity and loop_parity,
+           "roofline": {"bound": "hbm", "achieved": round(B / (ev["mean"] / 1000.0) / 1e9, 2),
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(B / (ev["mean"] / 1000.0) / 1e9 / HBM_PEAK_GBS, 5),
+                        "traffic": traffic_from_profile("batched_kernel_batch4096_traffic.txt", "auto"),
+                        "alg_bytes_per_launch": B, "kernel": "batched_kernel",
+                        "kernel_ms_per_launch": ev["mean"]}}
+    del parts, vptr, off, adj, out
+    release()
+    return res
 
 
 def bench_serve(args, seconds: float = 5.0, rate: float = 20000.0, warm: float = 1.0):
@@ -268,7 +369,6 @@ def bench_serve(args, seconds: float = 5.0, rate: float = 20000.0, warm: float =
     tickets = [None] * nreq
     results = {}
     done_evt = threading.Event()
-
     lib = K.lib()
     n_of = [None] * nreq
 
@@ -297,7 +397,6 @@ def bench_serve(args, seconds: float = 5.0, rate: float = 20000.0, warm: float =
             pass
         g = big[pick[i] % 2] if is_big[i] else small[pick[i]]
         n_of[i] = g.n
-        # the inputs live in the pinned pool for the whole run (borrowed, never copied on submit)
         rc = lib.kcore_submit(srv._h, g.offsets.ctypes.data, g.adj.ctypes.data, g.n, ctypes.byref(tk))
         if rc != 0:
             raise K.KcoreError(rc, "kcore_submit", K.last_error())
@@ -328,19 +427,18 @@ def bench_serve(args, seconds: float = 5.0, rate: float = 20000.0, warm: float =
             per_class[name] = {"batches": len(b), "mean_graphs": round(float(b[:, 0].mean()), 1),
                                "mean_pack_ms": round(float(b[:, 1].mean()) / 1000, 3),
                                "mean_launch_to_done_ms": round(float(b[:, 2].mean()) / 1000, 3)}
+    del keep
+    release()
     return {
-        "metric": METRIC, "value": round(nmeas / span_s, 1), "unit": "graphs/s", "n_gpus": 1,
-        "steps": 1, "warmup": 0, "ms_per_step": round(span_s * 1000, 1), "higher_is_better": True,
-        "scaling": "strong", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
-        "config": {"workload": f"serving: Poisson {rate:.0f} req/s, {warm:g}s warm-up then {seconds:g}s "
-                   "measured, graphs from the batched distribution, 1% R-MAT scale 20 edge factor 16",
-                   "requests": nmeas},
+        "workload": f"serving: Poisson {rate:.0f} req/s, {warm:g}s warm-up then {seconds:g}s measured, "
+                    "graphs from the batched distribution, 1% R-MAT scale 20 edge factor 16",
+        "requests": nmeas, "offered_per_s": rate, "graphs_per_s": round(nmeas / span_s, 1),
+        "span_s": round(span_s, 3),
         "p50_ms": round(float(np.percentile(lat, 50)) / 1000, 3),
         "p99_ms": round(float(np.percentile(lat, 99)) / 1000, 3),
         "p99_small_ms": round(float(np.percentile(lat[~is_big], 99)) / 1000, 3),
         "p99_large_ms": round(float(np.percentile(lat[is_big], 99)) / 1000, 3) if is_big.any() else None,
-        "batches": per_class,
-        "parity": ok,
+        "batches": per_class, "parity": ok,
     }
 
 
@@ -355,32 +453,14 @@ def bench_kquery(args, k: int = 1000):
     torch.cuda.synchronize()
     n, m = off.numel() - 1, adj.numel()
     out = torch.empty(n, dtype=torch.int32, device=off.device)
-    for _ in range(args.warmup):
-        K.kcore_subgraph(off, adj, k, out)
-    _, st = K.kcore_subgraph(off, adj, k, out, stats=True)
-    stream = torch.cuda.current_stream()
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for e0, e1 in evs:
-        e0.record(stream)
-        K.kcore_subgraph(off, adj, k, out)
-        e1.record(stream)
-    torch.cuda.synchronize()
-    ms_step = (time.perf_counter() - t1) * 1000.0 / args.steps
-    kern_ms = sum(e0.elapsed_time(e1) for e0, e1 in evs) / args.steps
+    K.kcore_subgraph(off, adj, k, out)
+    wall_ms, per = timed_calls(lambda: K.kcore_subgraph(off, adj, k, out), args.steps, args.warmup)
+    K.check()
     got = out.cpu().numpy()
     want = (oracle.bz(off.cpu().numpy(), adj.cpu().numpy()) >= k).astype(np.int32)
-    return {
-        "metric": METRIC, "value": round(m / (ms_step / 1000.0) / 1e9, 4), "unit": "GTEPS", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
-        "higher_is_better": True, "scaling": "strong", "vs_baseline": None, "dtype": "int32",
-        "data": "synthetic",
-        "config": {"workload": f"maximum {k}-core subgraph of: {desc}", "n": n, "m": m, "k": k,
-                   "core_size": int(got.sum()), "peeled": int(n - got.sum())},
-        "kernel_ms_per_launch": round(kern_ms, 4), "parity": bool(np.array_equal(got, want)),
-    }
+    return {"workload": f"maximum {k}-core subgraph of: {desc}", "n": n, "m": m, "k": k,
+            "ms_per_step": round(wall_ms, 4), "event_ms": summary(per),
+            "core_size": int(got.sum()), "parity": bool(np.array_equal(got, want))}
 
 
 def kernel_sha() -> str:
@@ -393,12 +473,23 @@ def kernel_sha() -> str:
     return h.hexdigest()[:16]
 
 
+def wrap_single(name, r, args):
+    """A single-workload run printed on its own (``--workload X``)."""
+    return {"metric": METRIC, "value": r.get("gteps", r.get("graphs_per_s")),
+            "unit": "GTEPS" if "gteps" in r and name not in ("batch", "serve") else "graphs/s",
+            "n_gpus": 1, "steps": r.get("steps", args.steps), "warmup": args.warmup,
+            "ms_per_step": r.get("ms_per_step"), "higher_is_better": True, "scaling": "strong",
+            "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+            "config": {"workload": r.get("workload", name)}, name: r}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="chunglu", choices=["chunglu", "grid", "rmat16", "batch", "serve", "kquery"])
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="all",
+                    choices=["all", "chunglu", "grid", "rmat16", "hcns", "batch", "serve", "kquery"])
     ap.add_argument("--mode", default="auto", choices=["auto", "levelsync", "chained", "sampling", "offline"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -418,14 +509,32 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the single-graph, batched "
               "and serving paths each run on one device", file=sys.stderr)
         sys.exit(2)
-    if args.workload == "batch":
-        res = bench_batch(args)
+    # the secondary workloads use at most 10 timed steps each, so the whole run stays short
+    sub_steps, sub_warm = min(args.steps, 10), min(args.warmup, 2)
+    if args.workload == "chunglu":
+        res = bench_chunglu(args)
+    elif args.workload == "all":
+        res = bench_chunglu(args)
+        cfg = {}
+        for name in ("rmat16", "grid", "hcns"):
+            cfg[name] = bench_single_config(name, args, sub_steps if name != "hcns" else min(sub_steps, 3),
+                                            sub_warm if name != "hcns" else 1)
+            log(f"[bench] {name}: {json.dumps(cfg[name])}")
+        cfg["batch"] = bench_batch(args, sub_steps, sub_warm)
+        log(f"[bench] batch: {json.dumps(cfg['batch'])}")
+        cfg["serve"] = bench_serve(args)
+        log(f"[bench] serve: {json.dumps(cfg['serve'])}")
+        res["configs"] = cfg
+        res["parity_all"] = bool(res.get("parity", True)) and all(
+            bool(c.get("parity")) for c in cfg.values())
+    elif args.workload in ("rmat16", "grid", "hcns"):
+        res = wrap_single(args.workload, bench_single_config(args.workload, args, args.steps, args.warmup), args)
+    elif args.workload == "batch":
+        res = wrap_single("batch", bench_batch(args, args.steps, args.warmup), args)
     elif args.workload == "serve":
-        res = bench_serve(args)
-    elif args.workload == "kquery":
-        res = bench_kquery(args)
+        res = wrap_single("serve", bench_serve(args), args)
     else:
-        res = bench_single(args)
+        res = wrap_single("kquery", bench_kquery(args), args)
     print(json.dumps(res), flush=True)
 
 

@@ -131,3 +131,34 @@ def config_chung_lu_device(n=1 << 24, block_n=5000, device="cuda"):
 
 def to_host(offsets, adj, name="") -> Graph:
     return Graph(offsets.cpu().numpy(), adj.cpu().numpy(), None, name)
+
+
+def hcns_device(K: int, device="cuda", rows_per_chunk: int = 512):
+    """Staircase graph with coreness K (the shape of the paper's HCNS): a clique on vertices
+    0..K plus vertices u_i = K + i (1 <= i < K) adjacent to clique vertices 0..i-1, built on the
+    device as a CSR with sorted rows. n = 2K, 2K^2 directed entries; by construction u_i has
+    coreness i and the clique K (the same graph as the small test generator)."""
+    import torch
+    n = 2 * K
+    c = torch.arange(K + 1, dtype=torch.int64, device=device)
+    deg = torch.empty(n, dtype=torch.int64, device=device)
+    deg[:K + 1] = K + torch.clamp(K - 1 - c, min=0)
+    deg[K + 1:] = torch.arange(1, K, dtype=torch.int64, device=device)
+    offsets = torch.zeros(n + 1, dtype=torch.int64, device=device)
+    offsets[1:] = torch.cumsum(deg, 0)
+    m = int(offsets[-1])
+    adj = torch.empty(m, dtype=torch.int32, device=device)
+    t = torch.arange(2 * K, dtype=torch.int64, device=device)
+    for r0 in range(0, n, rows_per_chunk):
+        r1 = min(n, r0 + rows_per_chunk)
+        rows = torch.arange(r0, r1, dtype=torch.int64, device=device)[:, None]
+        d = deg[r0:r1][:, None]
+        w = int(deg[r0:r1].max())
+        tt = t[None, :w]
+        clique_row = rows <= K
+        # clique row c: 0..K without c, then K + c + 1, K + c + 2, ...; staircase row K + i: 0..i-1
+        v_clique = torch.where(tt < rows, tt, torch.where(tt < K, tt + 1, tt + 1 + rows))
+        v = torch.where(clique_row, v_clique, tt)
+        mask = tt < d
+        adj[int(offsets[r0]):int(offsets[r1])] = v[mask].to(torch.int32)
+    return offsets, adj

@@ -19,10 +19,14 @@
  * device reject them with KCORE_EBADGRAPH instead.
  *
  * Calls are stream-ordered and asynchronous unless stated: a return of KCORE_OK means the work is
- * enqueued on `stream`; coreness_out is valid once the stream reaches that point. Argument errors
- * are reported synchronously and enqueue nothing. The caller owns every buffer it passes; the
- * library owns its device workspace, cached per (device, stream) and reused across calls (see
- * kcore_release_workspaces). Calls on distinct streams may run concurrently; calls on one stream
+ * enqueued on `stream`; coreness_out is valid once the stream reaches that point, and the host
+ * never waits for the device. Argument errors are reported synchronously and enqueue nothing.
+ * Failures the device detects while peeling (a bounded wait that gave up, a list that overflowed,
+ * offsets[n] beyond what adj can hold) leave coreness_out incomplete and are reported through the
+ * device status word: read it with kcore_check(stream) after the work, have it copied to
+ * kcore_options.status_out in stream order, or pass a kcore_stats* (synchronous). The caller
+ * owns every buffer it passes; the library owns its device workspace, cached per (device, stream)
+ * and reused across calls (see kcore_release_workspaces). Calls on distinct streams may run concurrently; calls on one stream
  * are serialised by it. Exception: the single-graph peel (kcore_decompose*, kcore_kcore_subgraph)
  * runs a persistent grid that fills the device, so those grids run one at a time per device, each
  * after the one launched before it (ordered through the streams; the host does not block).
@@ -72,7 +76,7 @@ typedef enum {
                                subround each workgroup first counts the decrements per target in
                                an LDS table (the histogram), then applies each count once with the
                                batch rule old > k >= old - c; targets that find no free slot of the
-                               4,096 are decremented directly. Frontiers and rho are those of
+                               8,192 are decremented directly. Frontiers and rho are those of
                                KCORE_MODE_LEVELSYNC */
 } kcore_mode;
 
@@ -83,9 +87,14 @@ typedef struct {
   int32_t blocks_per_cu; /* persistent workgroups per compute unit; 0 = library choice */
   int32_t hub_degree;    /* vertices with at least this degree are split into tiles of
                             `tile_edges` adjacency entries when peeled; 0 = library choice */
-  int64_t num_entries;   /* offsets[n] when the caller knows it; 0 = unknown, in which case the
-                            single-graph call reads it with a blocking 8-byte copy on `stream`
-                            to size the tile lists */
+  int64_t num_entries;   /* offsets[n] when the caller knows it, to size the workspace exactly;
+                            0 = unknown: the workspace is then sized for the device allocation
+                            that holds adj (from its base and size as the HIP runtime reports
+                            them, at most n (n - 1) entries), with no host-device round trip; only
+                            for a pointer the runtime cannot attribute to an allocation is
+                            offsets[n] read with a blocking 8-byte copy. Either way the device
+                            checks offsets[n] against the size used before it reads any entry
+                            (a failure reported through the status word, see kcore_check) */
   int32_t local_budget;  /* chained mode: vertices one wavefront may peel from its local queue per
                             phase before handing the rest to the global frontier; 0 = default */
   int32_t tile_edges;    /* adjacency entries per hub tile (multiple of 64, at most 32768);
@@ -123,6 +132,27 @@ typedef struct {
                             26,624 in chained mode, 23,552 in the level-sync and offline modes,
                             whose tail keeps 16 KB of scan arrays); 0 = default, min(that cap,
                             n / 8); -1 = never */
+  int32_t buckets;       /* chained and level-sync modes: multi-bucket active set (Sec. 5.2, HBS).
+                            From the first round boundary with k >= 16 at which at most this many
+                            vertices are live, live vertices are kept in buckets by the highest bit
+                            in which their induced degree differs from k (ranges 1, 2, 4, ... above
+                            k, aligned to powers of two), so a round reads only the bucket that
+                            holds the new k and moves its other entries to lower buckets; a
+                            decrement that takes a vertex below its bucket's range moves it.
+                            Costs 2 x 31 int32 slots per such vertex plus 4 bytes per vertex of
+                            workspace. 0 = default (off), -1 = never, > 0 = that many vertices */
+  int32_t sample_threshold; /* sampling mode: vertices of degree above this start sampled;
+                            0 = default (1024) */
+  int32_t sample_mu;     /* sampling mode: hits expected before a resample (mu of Alg. 5);
+                            0 = default (4 (c + 2) ln n with c = 1, at least 16) */
+  int32_t debug_phase;   /* debugging: record every workgroup's timing in phases
+                            [debug_phase, debug_phase + 64) (read with kcore_debug_blocks, not
+                            part of this header); 0 = off */
+  int64_t test_tail_entries; /* testing: pretend the tail's local rows hold at most this many
+                            entries, so that handoffs are called off and retried; 0 = off */
+  uint32_t* status_out;  /* nullable, device or pinned host memory: receives the device status word
+                            of the call (0 = success, else internal failure bits) when `stream`
+                            reaches the end of the call */
 } kcore_options;
 
 /* Counters of one decomposition (filled when a kcore_stats* is passed; that call synchronises
@@ -147,6 +177,12 @@ typedef struct {
   int32_t sample_recounts; /* sampling mode: validations that recounted a vertex's live degree */
   int32_t sample_restarts; /* sampling mode: 1 if the sampled run failed and was repeated */
   int32_t reserved[1];
+  int64_t live_decrements; /* decrement units that landed on a vertex still above k (Alg. 1's
+                              test "induced degree > k"): one per peeled vertex and live neighbour,
+                              at most m / 2 on a simple graph; counted in the tail and in LDS
+                              combining too (a count of c on a vertex at d > k adds min(c, d - k)) */
+  int64_t bucket_inserts;  /* insertions into the multi-bucket active set (kcore_options.buckets):
+                              placements, moves to lower buckets and redistributions */
 } kcore_stats;
 
 /* Single graph. n == 0 is a no-op; adj may be null when offsets[n] == 0; KCORE_ETOOBIG when
@@ -180,8 +216,9 @@ int kcore_kcore_subgraph(const int64_t* offsets, const int32_t* adj, int64_t n, 
  *   coreness_out int32[total_vertices]
  * Options of the _ex form: mode LEVELSYNC (= AUTO) peels each round in barrier-separated
  * subrounds inside the graph's workgroup; CHAINED works each round off through a dynamic
- * workgroup queue. validate and blocks_per_cu apply; the other fields are ignored. A device failure
- * is reported only when stats_host is given. */
+ * workgroup queue. validate, blocks_per_cu and status_out apply; the other fields are ignored.
+ * A device failure is reported as for the single-graph calls (kcore_check, status_out, or
+ * stats_host). */
 int kcore_decompose_batched(const int64_t* graph_vptr, const int64_t* offsets, const int32_t* adj,
                             int32_t num_graphs, int64_t total_vertices, int32_t* coreness_out,
                             hipStream_t stream);
@@ -193,6 +230,12 @@ int kcore_decompose_batched_ex(const int64_t* graph_vptr, const int64_t* offsets
 
 /* Frees every cached workspace after synchronising the device. */
 int kcore_release_workspaces(void);
+
+/* Waits for `stream`, then reads the device status words of the last single-graph and the last
+ * batched call made on it (blocks the calling thread). KCORE_OK when neither reported a failure,
+ * KCORE_EDEVICE otherwise (kcore_last_error names the bits), KCORE_ENOTFOUND when no call ran on
+ * this stream of the current device. */
+int kcore_check(hipStream_t stream);
 
 /* ------------------------------------------------------------------------------------------------
  * Serving: continuous batching of independent graph requests on one device.

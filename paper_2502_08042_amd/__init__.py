@@ -33,6 +33,7 @@ LIB_PATH = os.path.join(_HERE, "libkcore.so")
 KCORE_OK, KCORE_PENDING = 0, 1
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ETOOBIG", -5: "ENOTFOUND",
           -6: "ECANCELED", -7: "EBADGRAPH"}
+ERRORS_BY_NAME = {v: k for k, v in ERRORS.items()}
 MODES = {"auto": 0, "levelsync": 1, "chained": 2, "sampling": 3, "offline": 4}
 
 
@@ -49,7 +50,10 @@ class Options(ctypes.Structure):
                 ("tile_edges", ctypes.c_int32), ("async_frontier", ctypes.c_int32),
                 ("async_scan", ctypes.c_int32), ("block_tiles", ctypes.c_int32),
                 ("block_queue", ctypes.c_int32), ("tile_probe", ctypes.c_int32),
-                ("residual", ctypes.c_int32), ("tail", ctypes.c_int32)]
+                ("residual", ctypes.c_int32), ("tail", ctypes.c_int32),
+                ("buckets", ctypes.c_int32), ("sample_threshold", ctypes.c_int32),
+                ("sample_mu", ctypes.c_int32), ("debug_phase", ctypes.c_int32),
+                ("test_tail_entries", ctypes.c_int64), ("status_out", ctypes.c_void_p)]
 
 
 class Stats(ctypes.Structure):
@@ -60,7 +64,8 @@ class Stats(ctypes.Structure):
                 ("kmax", ctypes.c_int32), ("device_status", ctypes.c_int32),
                 ("ms", ctypes.c_float), ("tail_vertices", ctypes.c_int32),
                 ("sampled_vertices", ctypes.c_int32), ("sample_recounts", ctypes.c_int32),
-                ("sample_restarts", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
+                ("sample_restarts", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1),
+                ("live_decrements", ctypes.c_int64), ("bucket_inserts", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
@@ -97,6 +102,7 @@ SIGNATURES = {
     "kcore_decompose_batched_ex": (ctypes.c_int, [P, P, P, I32, I64, P, P, ctypes.POINTER(Options),
                                                   ctypes.POINTER(Stats)]),
     "kcore_release_workspaces": (ctypes.c_int, []),
+    "kcore_check": (ctypes.c_int, [P]),
     "kcore_server_create": (P, [ctypes.POINTER(ServerConfig)]),
     "kcore_submit": (ctypes.c_int, [P, P, P, I64, U64P]),
     "kcore_poll": (ctypes.c_int, [P, ctypes.c_uint64, P, ctypes.POINTER(RequestStats)]),
@@ -129,8 +135,46 @@ def _load():
 _lib = _load()
 
 
+def _release_at_exit():
+    # Free the library's cached device workspaces, pinned blocks and events while the HIP runtime
+    # (and any profiler attached to it) is still fully alive, instead of leaving them to process
+    # teardown.
+    try:
+        import torch
+        if torch.cuda.is_initialized():
+            _lib.kcore_release_workspaces()
+    except Exception:
+        pass
+
+
+import atexit  # noqa: E402
+
+atexit.register(_release_at_exit)
+
+
 def lib():
     return _lib
+
+
+_lib_checked = None
+
+
+def lib_checked():
+    """The checked build of the same library (``libkcore_checked.so``): identical C ABI, but its
+    kernels verify while they run that every coreness is written exactly once and that no induced
+    degree goes below zero, reporting a violation through the device status word. For tests."""
+    global _lib_checked
+    if _lib_checked is None:
+        path = os.path.join(_HERE, "libkcore_checked.so")
+        if not os.path.exists(path):
+            raise ImportError(f"{path} is missing: build it first (it is built with libkcore.so)")
+        h = ctypes.CDLL(path)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(h, name)
+            f.restype = res
+            f.argtypes = args
+        _lib_checked = h
+    return _lib_checked
 
 
 def last_error() -> str:
@@ -150,7 +194,8 @@ def _stream_ptr(stream) -> int:
 
 def _options(mode, validate, num_entries, hub_degree=0, local_budget=0, tile_edges=0,
              blocks_per_cu=0, async_frontier=0, async_scan=0, block_tiles=0,
-             block_queue=0, tile_probe=0, residual=0, tail=0) -> Options:
+             block_queue=0, tile_probe=0, residual=0, tail=0, buckets=0, sample_threshold=0,
+             sample_mu=0, debug_phase=0, test_tail_entries=0, status_out=None) -> Options:
     o = Options()
     o.mode = MODES[mode] if isinstance(mode, str) else int(mode)
     o.validate = 1 if validate else 0
@@ -166,6 +211,12 @@ def _options(mode, validate, num_entries, hub_degree=0, local_budget=0, tile_edg
     o.tile_probe = tile_probe
     o.residual = residual
     o.tail = tail
+    o.buckets = buckets
+    o.sample_threshold = sample_threshold
+    o.sample_mu = sample_mu
+    o.debug_phase = debug_phase
+    o.test_tail_entries = test_tail_entries
+    o.status_out = status_out
     return o
 
 
@@ -249,6 +300,12 @@ def decompose_batched(vptr, offsets, adj, out=None, *, mode="auto", stats=False,
 
 def release_workspaces():
     _check(_lib.kcore_release_workspaces(), "kcore_release_workspaces")
+
+
+def check(stream=None):
+    """Waits for the stream and raises KcoreError if the last single-graph or batched call on it
+    reported a device failure (kcore_check)."""
+    _check(_lib.kcore_check(_stream_ptr(stream)), "kcore_check")
 
 
 class Server:

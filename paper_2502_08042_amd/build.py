@@ -8,6 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libkcore.so")
+LIB_CHECKED = os.path.join(HERE, "libkcore_checked.so")
 ARCH = os.environ.get("KCORE_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -26,23 +27,36 @@ def _run(cmd):
         print(err, file=sys.stderr)
 
 
-def build(verbose: bool = False) -> str:
-    """Compiles every source (always) and links libkcore.so atomically."""
-    objs = []
+def _build_one(lib: str, defines, verbose: bool) -> str:
+    from concurrent.futures import ThreadPoolExecutor
+    tag = os.path.basename(lib).replace(".so", "")
+    cmds, objs = [], []
     for src, hip in (("kcore_device.hip", True), ("kcore_api.cpp", False), ("kcore_server.cpp", False)):
-        obj = os.path.join(CSRC, src + ".o")
-        cmd = [HIPCC, f"--offload-arch={ARCH}", *COMMON, "-c", os.path.join(CSRC, src), "-o", obj]
+        obj = os.path.join(CSRC, f"{src}.{tag}.o")
+        cmd = [HIPCC, f"--offload-arch={ARCH}", *COMMON, *defines, "-c", os.path.join(CSRC, src), "-o", obj]
         if not hip:
             cmd.insert(1, "-xhip")
         if verbose:
             print(" ".join(cmd))
-        _run(cmd)
+        cmds.append(cmd)
         objs.append(obj)
-    tmp = LIB + ".tmp%d" % os.getpid()
+    with ThreadPoolExecutor(len(cmds)) as ex:
+        list(ex.map(_run, cmds))
+    tmp = lib + ".tmp%d" % os.getpid()
     _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread"])
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
     for o in objs:
         os.remove(o)
+    return lib
+
+
+def build(verbose: bool = False) -> str:
+    """Compiles every source (always) and links libkcore.so atomically; then the checked variant
+    libkcore_checked.so (run-time invariant checks in the kernels, for tests)."""
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(2) as ex:
+        list(ex.map(lambda x: _build_one(x[0], x[1], verbose),
+                    ((LIB, []), (LIB_CHECKED, ["-DKCORE_CHECKS=1"]))))
     return LIB
 
 

@@ -16,6 +16,12 @@
 #include "../../include/kcore.h"
 #include "kcore_internal.h"
 
+// Checked builds (a separate library for tests) start every output at -1, so that the kernels can
+// verify that each coreness is written exactly once.
+#ifndef KCORE_CHECKS
+#define KCORE_CHECKS 0
+#endif
+
 namespace {
 
 thread_local std::string g_err;
@@ -179,7 +185,8 @@ int peel_ws(int dev, hipStream_t s, int64_t n, int64_t tcap, int64_t rcap, int64
   PeelWs*& w = g_peel[Key(dev, s)];
   if (!w) {
     w = new PeelWs;
-    HIP_TRY(hipHostMalloc((void**)&w->host_stats, 16 * sizeof(unsigned long long) + 64, hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc((void**)&w->host_stats, kc::kStatWords * sizeof(unsigned long long) + 64,
+                          hipHostMallocDefault));
     HIP_TRY(hipEventCreate(&w->ev0));
     HIP_TRY(hipEventCreate(&w->ev1));
   }
@@ -284,7 +291,8 @@ int batch_ws(int dev, hipStream_t s, int64_t V, int32_t G, BatchWs*& out) {
   BatchWs*& w = g_batch[Key(dev, s)];
   if (!w) {
     w = new BatchWs;
-    HIP_TRY(hipHostMalloc((void**)&w->host_stats, 16 * sizeof(unsigned long long) + 64, hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc((void**)&w->host_stats, kc::kStatWords * sizeof(unsigned long long) + 64,
+                          hipHostMallocDefault));
     HIP_TRY(hipEventCreate(&w->ev0));
     HIP_TRY(hipEventCreate(&w->ev1));
   }
@@ -325,6 +333,37 @@ int batch_ws(int dev, hipStream_t s, int64_t V, int32_t G, BatchWs*& out) {
   return KCORE_OK;
 }
 
+// Entries the CSR of an n-vertex graph can hold when the caller did not say: what is left of the
+// device allocation holding adj after adj (the runtime's record of its base and size; no device
+// work), capped at n (n - 1). Only a pointer the runtime cannot attribute falls back to reading
+// offsets[n] from the device, which blocks.
+int entries_bound(const int64_t* offsets, const int32_t* adj, int64_t n, hipStream_t stream, int64_t& m) {
+  const int64_t simple = n > 3037000499LL ? INT64_MAX : n * (n - 1);
+  if (!adj) {
+    m = 0;
+    return KCORE_OK;
+  }
+  hipDeviceptr_t base = nullptr;
+  size_t size = 0;
+  if (hipMemGetAddressRange(&base, &size, const_cast<int32_t*>(adj)) == hipSuccess && base && size) {
+    const char* b = static_cast<const char*>(base);
+    const char* p = reinterpret_cast<const char*>(adj);
+    if (p >= b && p < b + size) {
+      m = std::min<int64_t>((int64_t)((b + size - p) / sizeof(int32_t)), simple);
+      return KCORE_OK;
+    }
+  }
+  (void)hipGetLastError();  // (the failed lookup must not surface in a later call)
+  int64_t* pin = nullptr;
+  HIP_TRY(hipHostMalloc((void**)&pin, sizeof(int64_t), hipHostMallocDefault));
+  hipError_t e1 = hipMemcpyAsync(pin, offsets + n, sizeof(int64_t), hipMemcpyDefault, stream);
+  hipError_t e2 = e1 == hipSuccess ? hipStreamSynchronize(stream) : e1;
+  m = *pin;
+  hipHostFree(pin);
+  if (e2 != hipSuccess) return fail(KCORE_EDEVICE, "reading offsets[n]: %s", hipGetErrorString(e2));
+  return KCORE_OK;
+}
+
 int check_opts(const kcore_options* o) {
   if (!o) return KCORE_OK;
   if (o->mode < 0 || o->mode > 4) return fail(KCORE_EINVAL, "mode %d unknown", o->mode);
@@ -338,6 +377,9 @@ int check_opts(const kcore_options* o) {
     return fail(KCORE_EINVAL, "block_queue must be in [0, %d]", kc::kBlockQ);
   if (o->async_frontier < -1 || o->async_scan < -1 || o->block_tiles < -1)
     return fail(KCORE_EINVAL, "async and block-tile thresholds must be >= -1");
+  if (o->buckets < -1) return fail(KCORE_EINVAL, "buckets must be >= -1");
+  if (o->sample_threshold < 0 || o->sample_mu < 0 || o->debug_phase < 0 || o->test_tail_entries < 0)
+    return fail(KCORE_EINVAL, "sampling parameters and test hooks must be >= 0");
   return KCORE_OK;
 }
 
@@ -368,6 +410,8 @@ void fill_stats(kcore_stats* st, const unsigned long long* hs, unsigned status, 
   st->tail_vertices = (int32_t)hs[kc::ST_TAIL];
   st->sampled_vertices = (int32_t)hs[kc::ST_SAMPLED];
   st->sample_recounts = (int32_t)hs[kc::ST_RECOUNTS];
+  st->live_decrements = (int64_t)hs[kc::ST_LIVE];
+  st->bucket_inserts = (int64_t)hs[kc::ST_BUCKET];
   st->device_status = (int32_t)status;
   st->ms = ms;
 }
@@ -378,7 +422,7 @@ void kc::set_error(const char* msg) { g_err = msg ? msg : ""; }
 
 extern "C" {
 
-int kcore_version(void) { return 10000; }
+int kcore_version(void) { return 10100; }
 
 const char* kcore_last_error(void) { return g_err.c_str(); }
 
@@ -409,15 +453,12 @@ static int peel_impl(const int64_t* offsets, const int32_t* adj, int64_t n, int3
   const uint32_t hub = (opt && opt->hub_degree) ? (uint32_t)opt->hub_degree : 256u;
   const int tile = (opt && opt->tile_edges) ? opt->tile_edges : 256;
   const int budget = (opt && opt->local_budget) ? opt->local_budget : 4096;
+  // m: the number of entries the workspace is sized for. The caller's num_entries when given;
+  // otherwise the room left in the device allocation that holds adj (no host-device round trip),
+  // at most n (n - 1), which a simple graph never exceeds. The kernel checks offsets[n] <= m.
   int64_t m = opt ? opt->num_entries : 0;
   if (m <= 0) {
-    int64_t* pin = nullptr;
-    HIP_TRY(hipHostMalloc((void**)&pin, sizeof(int64_t), hipHostMallocDefault));
-    hipError_t e1 = hipMemcpyAsync(pin, offsets + n, sizeof(int64_t), hipMemcpyDeviceToHost, stream);
-    hipError_t e2 = e1 == hipSuccess ? hipStreamSynchronize(stream) : e1;
-    m = *pin;
-    hipHostFree(pin);
-    if (e2 != hipSuccess) return fail(KCORE_EDEVICE, "reading offsets[n]: %s", hipGetErrorString(e2));
+    if (int rc = entries_bound(offsets, adj, n, stream, m)) return rc;
   }
   if (m < 0) return fail(KCORE_EINVAL, "offsets[n] = %lld is negative", (long long)m);
   if (m > 0 && !adj) return fail(KCORE_EINVAL, "adj is null but the graph has %lld entries", (long long)m);
@@ -469,6 +510,7 @@ static int peel_impl(const int64_t* offsets, const int32_t* adj, int64_t n, int3
   a.off = offsets;
   a.adj = adj;
   a.n = n;
+  a.m_bound = m;
   a.core = coreness_out;
   a.dt = w->dt;
   a.state = w->state;
@@ -489,7 +531,8 @@ static int peel_impl(const int64_t* offsets, const int32_t* adj, int64_t n, int3
   a.lq_budget = budget;
   a.big_phase = offline ? 0 : 16384;
   a.aq = w->aq;
-  a.qcap = w->q_cap;
+  // this call's share of the work queue (the cached workspace may be larger)
+  a.qcap = std::min<int64_t>(w->q_cap, n + tcap + 256 * 64 * 64);
   const int32_t af = opt ? opt->async_frontier : 0;
   const int32_t as = opt ? opt->async_scan : 0;
   a.async_small = af < 0 ? -1 : (af ? af : 65536);
@@ -512,9 +555,8 @@ static int peel_impl(const int64_t* offsets, const int32_t* adj, int64_t n, int3
   a.trow = w->trow;
   a.tadj = w->tadj;
   a.tail_ecap = tail_ecap;
-  // testing aid: KCORE_DEBUG_TAIL_ECAP=e pretends the local rows hold only e entries, so that
-  // handoffs are called off and retried
-  if (const char* te = getenv("KCORE_DEBUG_TAIL_ECAP")) a.tail_ecap = std::min<int64_t>(tail_ecap, atoll(te));
+  // testing aid: pretend the local rows hold fewer entries, so that handoffs are called off
+  if (opt && opt->test_tail_entries > 0) a.tail_ecap = std::min<int64_t>(tail_ecap, opt->test_tail_entries);
   a.sampling = sampling ? 1 : 0;
   a.s_threshold = a.s_mu = a.s_seed = 0;
   a.srate = a.scnt = a.sbase = a.scount = nullptr;
@@ -529,41 +571,36 @@ static int peel_impl(const int64_t* offsets, const int32_t* adj, int64_t n, int3
     a.srl = w->srl;
     // Alg. 5's parameters: mu = 4 (c + 2) ln n with c = 1, so that the scheme is correct with
     // probability at least 1 - 1/n (a failure is detected and answered by a second run), at least
-    // 16; vertices of degree above 1024 start in sample mode. Testing aid:
-    // KCORE_DEBUG_SAMPLE="threshold,mu" overrides both.
+    // 16; vertices of degree above 1024 start in sample mode (both can be set in the options)
     a.s_mu = (uint32_t)std::max(16.0, std::ceil(12.0 * std::log((double)std::max<int64_t>(n, 2))));
     a.s_threshold = 1024;
-    if (const char* ds = getenv("KCORE_DEBUG_SAMPLE")) {
-      unsigned th = 0, mu = 0;
-      if (sscanf(ds, "%u,%u", &th, &mu) == 2 && mu > 0) {
-        a.s_threshold = th;
-        a.s_mu = mu;
-      }
-    }
+    if (opt && opt->sample_mu > 0) a.s_mu = (uint32_t)opt->sample_mu;
+    if (opt && opt->sample_threshold > 0) a.s_threshold = (uint32_t)opt->sample_threshold;
     a.s_seed = 0x2545f491u;
   }
-  // debugging aid: KCORE_DEBUG_PHASE=p records every workgroup's timing in phases [p, p + 64)
-  const char* dp = getenv("KCORE_DEBUG_PHASE");
-  a.dbg_lo = dp ? atoll(dp) : -1;
-  if (a.dbg_lo < 0) a.dbg_lo = -(1ll << 40);
+  // debugging aid: record every workgroup's timing in phases [p, p + 64)
+  a.dbg_lo = (opt && opt->debug_phase > 0) ? opt->debug_phase : -(1ll << 40);
 
   HIP_TRY(kc::launch_init_ctl(w->ctl, stream));
-  if (a.chained) HIP_TRY(kc::launch_fill_u32(w->aq, 0xffffffffu, 2 * (size_t)w->q_cap, stream));
+  if (a.chained) HIP_TRY(kc::launch_fill_u32(w->aq, 0xffffffffu, 2 * (size_t)a.qcap, stream));
+  if (KCORE_CHECKS && k_query <= 0) HIP_TRY(kc::launch_fill_u32(coreness_out, 0xffffffffu, (size_t)n, stream));
   // sampling mode reads its outcome back before returning (a failed sampling run is repeated)
   kcore_stats local_stats;
   if (sampling && !stats_host) stats_host = &local_stats;
   if (stats_host) HIP_TRY(hipEventRecord(w->ev0, stream));
   if (int rc = launch_peel_ordered(dev, a, blocks, stream)) return rc;
   if (tail_vmax > 0) HIP_TRY(kc::launch_tail(a, (int32_t)tail_vmax, stream));
+  if (opt && opt->status_out)
+    HIP_TRY(hipMemcpyAsync(opt->status_out, &w->ctl->status, sizeof(unsigned), hipMemcpyDefault, stream));
   if (!stats_host) return KCORE_OK;
   HIP_TRY(hipEventRecord(w->ev1, stream));
-  HIP_TRY(hipMemcpyAsync(w->host_stats, w->ctl->stats, 16 * sizeof(unsigned long long),
+  HIP_TRY(hipMemcpyAsync(w->host_stats, w->ctl->stats, kc::kStatWords * sizeof(unsigned long long),
                          hipMemcpyDeviceToHost, stream));
   unsigned status = 0;
-  HIP_TRY(hipMemcpyAsync(w->host_stats + 16, &w->ctl->status, sizeof(unsigned), hipMemcpyDeviceToHost,
-                         stream));
+  HIP_TRY(hipMemcpyAsync(w->host_stats + kc::kStatWords, &w->ctl->status, sizeof(unsigned),
+                         hipMemcpyDeviceToHost, stream));
   HIP_TRY(hipStreamSynchronize(stream));
-  memcpy(&status, w->host_stats + 16, sizeof status);
+  memcpy(&status, w->host_stats + kc::kStatWords, sizeof status);
   float ms = 0;
   HIP_TRY(hipEventElapsedTime(&ms, w->ev0, w->ev1));
   fill_stats(stats_host, w->host_stats, status, ms);
@@ -585,7 +622,8 @@ static int peel_impl(const int64_t* offsets, const int32_t* adj, int64_t n, int3
   }
   if (status)
     return fail(KCORE_EDEVICE, "device reported failure bits 0x%x (diag %llu %llu %llu %llu)", status,
-                w->host_stats[12], w->host_stats[13], w->host_stats[14], w->host_stats[15]);
+                w->host_stats[kc::kDiagWord], w->host_stats[kc::kDiagWord + 1],
+                w->host_stats[kc::kDiagWord + 2], w->host_stats[kc::kDiagWord + 3]);
   return KCORE_OK;
 }
 
@@ -734,6 +772,7 @@ static int batched_impl(const int64_t* graph_vptr, const int64_t* offsets, const
   if (num_graphs < blocks) blocks = num_graphs;
 
   HIP_TRY(kc::launch_fill_u32(w->ctl, 0u, sizeof(kc::BatchCtl) / 4, stream));
+  if (KCORE_CHECKS) HIP_TRY(kc::launch_fill_u32(coreness_out, 0xffffffffu, (size_t)total_vertices, stream));
   HIP_TRY(kc::launch_order(graph_vptr, offsets, num_graphs, w->order, stream));
   kc::BatchArgs a;
   a.vptr = graph_vptr;
@@ -758,15 +797,17 @@ static int batched_impl(const int64_t* graph_vptr, const int64_t* offsets, const
   // the device status word (failure bits), for callers that check it after the stream
   if (status_out)
     HIP_TRY(hipMemcpyAsync(status_out, &w->ctl->status, sizeof(unsigned), hipMemcpyDeviceToHost, stream));
+  if (opt && opt->status_out)
+    HIP_TRY(hipMemcpyAsync(opt->status_out, &w->ctl->status, sizeof(unsigned), hipMemcpyDefault, stream));
   if (!stats_host) return KCORE_OK;
   HIP_TRY(hipEventRecord(w->ev1, stream));
-  HIP_TRY(hipMemcpyAsync(w->host_stats, w->ctl->stats, 16 * sizeof(unsigned long long),
+  HIP_TRY(hipMemcpyAsync(w->host_stats, w->ctl->stats, kc::kStatWords * sizeof(unsigned long long),
                          hipMemcpyDeviceToHost, stream));
-  HIP_TRY(hipMemcpyAsync(w->host_stats + 16, &w->ctl->status, sizeof(unsigned), hipMemcpyDeviceToHost,
-                         stream));
+  HIP_TRY(hipMemcpyAsync(w->host_stats + kc::kStatWords, &w->ctl->status, sizeof(unsigned),
+                         hipMemcpyDeviceToHost, stream));
   HIP_TRY(hipStreamSynchronize(stream));
   unsigned status = 0;
-  memcpy(&status, w->host_stats + 16, sizeof status);
+  memcpy(&status, w->host_stats + kc::kStatWords, sizeof status);
   float ms = 0;
   HIP_TRY(hipEventElapsedTime(&ms, w->ev0, w->ev1));
   fill_stats(stats_host, w->host_stats, status, ms);
@@ -783,6 +824,33 @@ int kcore_decompose_batched(const int64_t* graph_vptr, const int64_t* offsets, c
                             hipStream_t stream) {
   return kcore_decompose_batched_ex(graph_vptr, offsets, adj, num_graphs, total_vertices, coreness_out,
                                     stream, nullptr, nullptr);
+}
+
+int kcore_check(hipStream_t stream) {
+  g_err.clear();
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  PeelWs* pw = nullptr;
+  BatchWs* bw = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto ip = g_peel.find(Key(dev, stream));
+    if (ip != g_peel.end()) pw = ip->second;
+    auto ib = g_batch.find(Key(dev, stream));
+    if (ib != g_batch.end()) bw = ib->second;
+  }
+  if ((!pw || !pw->ctl) && (!bw || !bw->ctl))
+    return fail(KCORE_ENOTFOUND, "no decomposition ran on this stream of device %d", dev);
+  // the status words travel in stream order into each workspace's pinned block
+  unsigned* hp = pw && pw->ctl ? reinterpret_cast<unsigned*>(pw->host_stats + kc::kStatWords + 1) : nullptr;
+  unsigned* hb = bw && bw->ctl ? reinterpret_cast<unsigned*>(bw->host_stats + kc::kStatWords + 1) : nullptr;
+  if (hp) HIP_TRY(hipMemcpyAsync(hp, &pw->ctl->status, sizeof(unsigned), hipMemcpyDeviceToHost, stream));
+  if (hb) HIP_TRY(hipMemcpyAsync(hb, &bw->ctl->status, sizeof(unsigned), hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  const unsigned sp = hp ? *hp : 0u, sb = hb ? *hb : 0u;
+  if (sp || sb)
+    return fail(KCORE_EDEVICE, "device reported failure bits 0x%x (single graph), 0x%x (batched)", sp, sb);
+  return KCORE_OK;
 }
 
 int kcore_release_workspaces(void) {

@@ -20,6 +20,37 @@ namespace kc {
 constexpr uint32_t HUBBIT = 0x80000000u;
 constexpr uint32_t DMASK = 0x7fffffffu;
 
+// Checked builds (KCORE_CHECKS=1, a separate library used by tests) verify two invariants of the
+// online peel while it runs: every coreness is written exactly once (the output starts filled
+// with -1 and each write must find -1 there), and no induced degree is decremented below zero.
+// A violation sets KC_ERR_CHECK in the status word; nothing traps. Product builds compile both
+// checks away.
+#ifndef KCORE_CHECKS
+#define KCORE_CHECKS 0
+#endif
+
+__device__ __forceinline__ void put_core(int32_t* core, long long v, uint32_t k, unsigned* status) {
+  if constexpr (KCORE_CHECKS) {
+    if (__hip_atomic_exchange(&core[v], (int32_t)k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != -1)
+      __hip_atomic_fetch_or(status, (unsigned)KC_ERR_CHECK, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  } else {
+    (void)status;
+    core[v] = (int32_t)k;
+  }
+}
+
+// (checked builds) a decrement of c that found `before` (its value without flag bits) went below 0
+__device__ __forceinline__ void check_decrement(uint32_t before, uint32_t c, unsigned* status) {
+  if constexpr (KCORE_CHECKS) {
+    if (before < c)
+      __hip_atomic_fetch_or(status, (unsigned)KC_ERR_CHECK, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  } else {
+    (void)before;
+    (void)c;
+    (void)status;
+  }
+}
+
 template <class T>
 __device__ __forceinline__ T ald(const T* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -218,7 +249,7 @@ struct WaveCtx {
   int32_t* lq;         // local queue ring (chained mode)
   int lq_head, lq_cnt; // wave-uniform
   int lq_used;         // vertices peeled from the local queue this phase
-  long long edges, decr, scanned, peeled, comb;  // per-lane statistics
+  long long edges, decr, scanned, peeled, comb, live;  // per-lane statistics
   unsigned mymin;      // per-lane min over kept vertices
   int32_t* ckey;       // LDS combining table (block-shared): target id or -1
   uint32_t* ccnt;      //   decrements collected for it in this phase
@@ -510,6 +541,13 @@ __device__ __forceinline__ void edges_batch(const PeelArgs& a, WaveCtx& c, const
   }
 #pragma unroll
   for (int j = 0; j < U; ++j) {
+    // (a sampled target's flag keeps its value above any k: not counted as a live decrement)
+    const uint32_t xo = old[j] & (S ? (DMASK & ~SAMPLEBIT) : DMASK);
+    if (((did >> j) & 1u) && xo > k && !(S && (old[j] & SAMPLEBIT))) c.live += 1;
+    if (!S && ((did >> j) & 1u)) check_decrement(xo, 1u, &a.ctl->status);
+  }
+#pragma unroll
+  for (int j = 0; j < U; ++j) {
     bool crossed = ((did >> j) & 1u) && (old[j] & DMASK) == k + 1u;
     const bool hub = (old[j] & HUBBIT) != 0u;
     if (crossed) {
@@ -522,7 +560,7 @@ __device__ __forceinline__ void edges_batch(const PeelArgs& a, WaveCtx& c, const
         __hip_atomic_fetch_or(&a.state[u[j] >> 4], bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
       if (crossed) {
-        if (a.k_query <= 0) a.core[u[j]] = (int32_t)k;
+        if (a.k_query <= 0) put_core(a.core, u[j], k, &a.ctl->status);
         c.peeled += 1;
       }
     }
@@ -618,12 +656,14 @@ __device__ __forceinline__ void comb_flush(const PeelArgs& a, WaveCtx& c, const 
       const uint32_t old = asub(&a.dt[u], cnt);
       c.decr += 1;
       const uint32_t ox = old & DMASK;
+      if (ox > k) c.live += min(cnt, ox - k);
+      check_decrement(ox, cnt, &a.ctl->status);
       if (ox > k && ox - cnt <= k) {
         const uint32_t bit = 1u << (u & 15);
         if (!(aor(&a.state[u >> 4], bit) & bit)) {
           crossed = true;
           hub = (old & HUBBIT) != 0u;
-          if (a.k_query <= 0) a.core[u] = (int32_t)k;
+          if (a.k_query <= 0) put_core(a.core, u, k, &a.ctl->status);
           c.peeled += 1;
         }
       }
@@ -842,7 +882,7 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
   c.lq_head = 0;
   c.lq_cnt = 0;
   c.lq_used = 0;
-  c.edges = c.decr = c.scanned = c.peeled = c.comb = 0;
+  c.edges = c.decr = c.scanned = c.peeled = c.comb = c.live = 0;
   c.mymin = 0xffffffffu;
   c.ckey = s_ckey;
   c.ccnt = s_ccnt;
@@ -867,6 +907,9 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
 
   // ---- phase 0: induced degree = degree (Alg. 1 initialisation), hub flags, min degree
   {
+    // the workspace was sized for at most m_bound entries: a larger offsets[n] stops the run at the
+    // first barrier, before any adjacency entry is read
+    if (gt == 0 && a.off[n] > a.m_bound) aor(&C->status, (unsigned)KC_ERR_OVERFLOW);
     const long long nw = (n + 15) >> 4;
     unsigned mn = 0xffffffffu;
     for (long long wd = gt; wd < nw; wd += GT) {
@@ -1314,7 +1357,7 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
           if (aor(&a.state[v >> 4], bit) & bit) {
             ext = false;  // already peeled in this round by a chain (chained mode)
           } else {
-            if (a.k_query <= 0) a.core[v] = (int32_t)k;
+            if (a.k_query <= 0) put_core(a.core, v, k, &C->status);
             c.peeled += 1;
           }
         }
@@ -1482,10 +1525,10 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
         if (mv == 0xffffffffu) {
           if (threadIdx.x == 0) aor(&C->status, (unsigned)KC_ERR_PHASES);
           if (blockIdx.x == 0 && threadIdx.x == 0) {
-            ast(&C->stats[12], (unsigned long long)total_peeled);
-            ast(&C->stats[13], (unsigned long long)kx);
-            ast(&C->stats[14], (unsigned long long)p);
-            ast(&C->stats[15], (unsigned long long)asize);
+            ast(&C->stats[kDiagWord], (unsigned long long)total_peeled);
+            ast(&C->stats[kDiagWord + 1], (unsigned long long)kx);
+            ast(&C->stats[kDiagWord + 2], (unsigned long long)p);
+            ast(&C->stats[kDiagWord + 3], (unsigned long long)asize);
           }
           break;
         }
@@ -1526,8 +1569,8 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
 
   // ---- statistics: per-lane counters reduced per block, one atomic each per block
   {
-    long long v4[5] = {c.edges, c.decr, c.scanned, c.peeled, c.comb};
-    for (int q = 0; q < 5; ++q) {
+    long long v4[6] = {c.edges, c.decr, c.scanned, c.peeled, c.comb, c.live};
+    for (int q = 0; q < 6; ++q) {
       long long x = v4[q];
       for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
       if (l == 0) s_red64[w] = x;
@@ -1535,7 +1578,8 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
       if (threadIdx.x == 0) {
         long long t = 0;
         for (int i = 0; i < kWaves; ++i) t += s_red64[i];
-        const int idx = q == 0 ? ST_EDGES : q == 1 ? ST_DECR : q == 2 ? ST_SCANNED : q == 3 ? ST_PEELED : ST_COMBINED;
+        const int idx = q == 0 ? ST_EDGES : q == 1 ? ST_DECR : q == 2 ? ST_SCANNED : q == 3 ? ST_PEELED
+                      : q == 4 ? ST_COMBINED : ST_LIVE;
         if (t) aadd(&C->stats[idx], (unsigned long long)t);
       }
       __syncthreads();
@@ -1619,7 +1663,7 @@ __device__ __forceinline__ void team_push(bool p, int32_t v, QT* q, int* s_tail)
 __device__ __forceinline__ bool batch_chain(const BatchArgs& a, uint32_t* d, int32_t* q, uint32_t* pb,
                                             const int64_t* off, int64_t base, bool inl, uint32_t k,
                                             int* s_claim, int* s_tail, int* s_busy, long long& st_edges,
-                                            long long& st_decr) {
+                                            long long& st_decr, long long& st_live) {
   const int l = lane_id();
   const unsigned long long t_start = wall_clock64();
   for (;;) {
@@ -1702,12 +1746,14 @@ __device__ __forceinline__ bool batch_chain(const BatchArgs& a, uint32_t* d, int
         if (live) {
           const unsigned old = inl ? atomicSub(&d[ul], 1u) : wsub(&d[ul], 1u);
           st_decr++;
+          st_live += old > k ? 1 : 0;
+          check_decrement(old, 1u, &a.ctl->status);
           crossed = old == k + 1;
         }
       }
       if (crossed) {
         if (pb) atomicOr(&pb[ul >> 5], 1u << (ul & 31));
-        a.core[base + ul] = (int32_t)k;
+        put_core(a.core, base + ul, k, &a.ctl->status);
       }
       const unsigned long long m = __ballot(crossed);
       if (m) {
@@ -1730,7 +1776,7 @@ __global__ __launch_bounds__(kBatchThreads) void batched_kernel(BatchArgs a) {
   __shared__ int s_claim, s_busy;
   __shared__ long long s_g;
 
-  long long st_edges = 0, st_decr = 0, st_rounds = 0, st_sub = 0, st_scanned = 0;
+  long long st_edges = 0, st_decr = 0, st_rounds = 0, st_sub = 0, st_scanned = 0, st_live = 0;
   unsigned kmax_all = 0;
   const int tid = threadIdx.x, l = lane_id(), w = threadIdx.x >> 6;
 
@@ -1808,7 +1854,7 @@ __global__ __launch_bounds__(kBatchThreads) void batched_kernel(BatchArgs a) {
             ++nk;
           }
           if (ext[r]) {
-            a.core[base + vi[r]] = (int32_t)k;
+            put_core(a.core, base + vi[r], k, &a.ctl->status);
             if (pb) atomicOr(&pb[vi[r] >> 5], 1u << (vi[r] & 31));
           }
           team_push(ext[r], vi[r], q, &s_tail);
@@ -1848,7 +1894,7 @@ __global__ __launch_bounds__(kBatchThreads) void batched_kernel(BatchArgs a) {
           s_busy = kBatchThreads / 64;
         }
         __syncthreads();
-        if (!batch_chain(a, d, q, pb, off, base, inl, k, &s_claim, &s_tail, &s_busy, st_edges, st_decr) &&
+        if (!batch_chain(a, d, q, pb, off, base, inl, k, &s_claim, &s_tail, &s_busy, st_edges, st_decr, st_live) &&
             l == 0)
           aor(&a.ctl->status, (unsigned)KC_ERR_TIMEOUT);
         __syncthreads();
@@ -1889,12 +1935,14 @@ __global__ __launch_bounds__(kBatchThreads) void batched_kernel(BatchArgs a) {
               if (live) {
                 const unsigned old = inl ? atomicSub(&d[ul], 1u) : wsub(&d[ul], 1u);
                 st_decr++;
+                st_live += old > k ? 1 : 0;
+                check_decrement(old, 1u, &a.ctl->status);
                 crossed = old == k + 1;
               }
             }
             if (crossed && pb) atomicOr(&pb[ul >> 5], 1u << (ul & 31));
             team_push(crossed, ul, q, &s_tail);
-            if (crossed) a.core[base + ul] = (int32_t)k;
+            if (crossed) put_core(a.core, base + ul, k, &a.ctl->status);
           }
           __syncthreads();
         }
@@ -1908,11 +1956,13 @@ __global__ __launch_bounds__(kBatchThreads) void batched_kernel(BatchArgs a) {
     __syncthreads();
   }
   // statistics
-  long long v5[5] = {st_edges, st_decr, st_scanned, 0, 0};
-  for (int qd = 0; qd < 3; ++qd) {
+  long long v5[4] = {st_edges, st_decr, st_scanned, st_live};
+  for (int qd = 0; qd < 4; ++qd) {
     long long x = v5[qd];
     for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-    if (l == 0 && x) aadd(&a.ctl->stats[qd == 0 ? ST_EDGES : qd == 1 ? ST_DECR : ST_SCANNED], (unsigned long long)x);
+    if (l == 0 && x)
+      aadd(&a.ctl->stats[qd == 0 ? ST_EDGES : qd == 1 ? ST_DECR : qd == 2 ? ST_SCANNED : ST_LIVE],
+           (unsigned long long)x);
   }
   if (tid == 0) {
     if (st_rounds) aadd(&a.ctl->stats[ST_ROUNDS], (unsigned long long)st_rounds);
@@ -1950,20 +2000,24 @@ hipError_t batched_occupancy(size_t lds_bytes, int* blocks_per_cu) {
 // the batch is issued before any result is looked at. All lanes of the wavefront call.
 template <int N>
 __device__ __forceinline__ void tail_edges(const PeelArgs& a, uint32_t* d, uint16_t* q, int* s_tail, int L,
-                                           const int32_t (&u)[N], uint32_t k) {
+                                           const int32_t (&u)[N], uint32_t k, long long& live) {
   uint32_t old[N];
 #pragma unroll
   for (int j = 0; j < N; ++j) old[j] = atomicSub(&d[u[j]], 1u);
   unsigned cm = 0;  // this lane's crossings
 #pragma unroll
-  for (int j = 0; j < N; ++j) cm |= (old[j] == k + 1 ? 1u : 0u) << j;
+  for (int j = 0; j < N; ++j) {
+    cm |= (old[j] == k + 1 ? 1u : 0u) << j;
+    live += (u[j] < L && old[j] > k) ? 1 : 0;
+    if (u[j] < L) check_decrement(old[j], 1u, &a.ctl->status);
+  }
   if (!__ballot(cm != 0)) return;
 #pragma unroll
   for (int j = 0; j < N; ++j) {
     const bool crossed = (cm >> j) & 1u;
     const unsigned long long m = __ballot(crossed);
     if (!m) continue;
-    if (crossed) a.core[a.tgid[u[j]]] = (int32_t)k;
+    if (crossed) put_core(a.core, a.tgid[u[j]], k, &a.ctl->status);
     int b = 0;
     if (lane_id() == 0) b = atomicAdd(s_tail, __popcll(m));
     b = __shfl(b, 0, 64);
@@ -1976,7 +2030,8 @@ __device__ __forceinline__ void tail_edges(const PeelArgs& a, uint32_t* d, uint1
 // the lane's spare slot. Ids are unpacked where they are used, so the packed words are all that
 // stays live. All lanes of the wavefront call.
 __device__ __forceinline__ void tail_edges16(const PeelArgs& a, uint32_t* d, uint16_t* q, int* s_tail, int L,
-                                             const uint32_t (&w)[8], const int (&lim)[2], uint32_t k) {
+                                             const uint32_t (&w)[8], const int (&lim)[2], uint32_t k,
+                                             long long& live) {
   const int spare = L + lane_id();
   uint32_t old[16];
 #pragma unroll
@@ -1986,7 +2041,11 @@ __device__ __forceinline__ void tail_edges16(const PeelArgs& a, uint32_t* d, uin
   }
   unsigned cm = 0;
 #pragma unroll
-  for (int e = 0; e < 16; ++e) cm |= (old[e] == k + 1 ? 1u : 0u) << e;
+  for (int e = 0; e < 16; ++e) {
+    cm |= (old[e] == k + 1 ? 1u : 0u) << e;
+    live += ((e & 7) < lim[e >> 3] && old[e] > k) ? 1 : 0;
+    if ((e & 7) < lim[e >> 3]) check_decrement(old[e], 1u, &a.ctl->status);
+  }
   if (!__ballot(cm != 0)) return;
 #pragma unroll
   for (int e = 0; e < 16; ++e) {
@@ -1994,7 +2053,7 @@ __device__ __forceinline__ void tail_edges16(const PeelArgs& a, uint32_t* d, uin
     const unsigned long long m = __ballot(crossed);
     if (!m) continue;
     const int32_t u = (int32_t)((w[e >> 1] >> (16 * (e & 1))) & 0xffffu);
-    if (crossed) a.core[a.tgid[u]] = (int32_t)k;
+    if (crossed) put_core(a.core, a.tgid[u], k, &a.ctl->status);
     int b = 0;
     if (lane_id() == 0) b = atomicAdd(s_tail, __popcll(m));
     b = __shfl(b, 0, 64);
@@ -2007,7 +2066,7 @@ __device__ __forceinline__ void tail_edges16(const PeelArgs& a, uint32_t* d, uin
 // 16-byte boundary; rows are padded to whole 16-byte words); the decrements go in two halves of
 // 16 entries per lane. All lanes call with the same range.
 __device__ __forceinline__ void tail_tile(const PeelArgs& a, uint32_t* d, uint16_t* q, int* s_tail, int L, int tb,
-                                          int len, uint32_t k) {
+                                          int len, uint32_t k, long long& live) {
   static_assert(kTailTile == 2048, "four 16-byte loads of 8 entries per lane");
   const int l = lane_id();
   uint4 x[4];
@@ -2021,7 +2080,7 @@ __device__ __forceinline__ void tail_tile(const PeelArgs& a, uint32_t* d, uint16
     const uint32_t w[8] = {x[2 * h].x, x[2 * h].y, x[2 * h].z, x[2 * h].w,
                            x[2 * h + 1].x, x[2 * h + 1].y, x[2 * h + 1].z, x[2 * h + 1].w};
     const int lim[2] = {len - (1024 * h + 8 * l), len - (1024 * h + 512 + 8 * l)};
-    tail_edges16(a, d, q, s_tail, L, w, lim, k);
+    tail_edges16(a, d, q, s_tail, L, w, lim, k, live);
   }
 }
 
@@ -2033,7 +2092,8 @@ __device__ __forceinline__ void tail_tile(const PeelArgs& a, uint32_t* d, uint16
 // are written, so a claimed slot is read once it is no longer -1. False on a timeout. All threads
 // call.
 __device__ __forceinline__ bool tail_chain(const PeelArgs& a, uint32_t* d, uint16_t* q, int L, uint32_t k,
-                                           int* s_claim, int* s_tail, int* s_busy, long long& st_edges) {
+                                           int* s_claim, int* s_tail, int* s_busy, long long& st_edges,
+                                           long long& st_live) {
   constexpr int nw = kTailThreads / 64;
   const int l = lane_id();
   const unsigned long long t_start = wall_clock64();
@@ -2114,7 +2174,8 @@ __device__ __forceinline__ bool tail_chain(const PeelArgs& a, uint32_t* d, uint1
       if (l == 0) st_edges += len;
       if (l == 0) full = lds_ld(s_tail) >= L;
       if (__shfl(full, 0, 64)) continue;  // (as above, row by row)
-      for (int o = 0; o < len; o += kTailTile) tail_tile(a, d, q, s_tail, L, rs + o, min(len - o, kTailTile), k);
+      for (int o = 0; o < len; o += kTailTile)
+        tail_tile(a, d, q, s_tail, L, rs + o, min(len - o, kTailTile), k, st_live);
     }
     const int sd = dg >= kTailBig ? 0 : dg;
     const int incl = wave_incl_scan(sd);
@@ -2138,7 +2199,7 @@ __device__ __forceinline__ bool tail_chain(const PeelArgs& a, uint32_t* d, uint1
         const int pos = __shfl(rb, j, 64) + (t - __shfl(excl, j, 64));
         u[r] = t < total ? (int32_t)a.tadj[pos] : L + l;
       }
-      tail_edges(a, d, q, s_tail, L, u, k);
+      tail_edges(a, d, q, s_tail, L, u, k, st_live);
     }
   }
 }
@@ -2195,7 +2256,7 @@ __global__ __launch_bounds__(kTailThreads) void tail_kernel(PeelArgs a, int32_t 
   // frontier extracted, round peeled; then k, first frontier size, vertices peeled so far
   unsigned long long* trc = nullptr;
   int ntr = 0;
-  long long st_edges = 0, st_scanned = 0, st_rounds = 0, st_sub = 0;
+  long long st_edges = 0, st_scanned = 0, st_rounds = 0, st_sub = 0, st_live = 0;
 
   // induced degree = length of the local row (its live neighbours); k = the smallest
   unsigned mn = 0xffffffffu;
@@ -2232,7 +2293,7 @@ __global__ __launch_bounds__(kTailThreads) void tail_kernel(PeelArgs a, int32_t 
         const int i = i0 + r * kTailThreads + tid;
         const bool ext = i < L && x[r] == k;
         if (x[r] > k) nm = min(nm, x[r]);
-        if (ext) a.core[a.tgid[i]] = (int32_t)k;
+        if (ext) put_core(a.core, a.tgid[i], k, &a.ctl->status);
         team_push(ext, i, q, &s_tail);
       }
     }
@@ -2262,7 +2323,7 @@ __global__ __launch_bounds__(kTailThreads) void tail_kernel(PeelArgs a, int32_t 
         s_busy = kTailThreads / 64;
       }
       __syncthreads();
-      if (!tail_chain(a, d, q, L, k, &s_claim, &s_tail, &s_busy, st_edges) && l == 0)
+      if (!tail_chain(a, d, q, L, k, &s_claim, &s_tail, &s_busy, st_edges, st_live) && l == 0)
         aor(&a.ctl->status, (unsigned)KC_ERR_TIMEOUT);
       __syncthreads();
       st_sub++;
@@ -2309,7 +2370,7 @@ __global__ __launch_bounds__(kTailThreads) void tail_kernel(PeelArgs a, int32_t 
               u[r] = (int32_t)a.tadj[s_rb[lo] + (t - s_pref[lo])];
             }
           }
-          tail_edges(a, d, q, &s_tail, L, u, k);
+          tail_edges(a, d, q, &s_tail, L, u, k, st_live);
         }
         for (int tt = w; !full && tt < tiles; tt += kTailThreads / 64) {
           int lo = 0, hi = kTailThreads - 1;  // largest j with s_tpref[j] <= tt (wave-uniform)
@@ -2319,7 +2380,7 @@ __global__ __launch_bounds__(kTailThreads) void tail_kernel(PeelArgs a, int32_t 
           }
           // the row starts on a 16-byte boundary and is padded to whole 16-byte words
           const int o = (tt - s_tpref[lo]) * kTailTile;
-          tail_tile(a, d, q, &s_tail, L, s_rb[lo] + o, min(s_len[lo] - o, kTailTile), k);
+          tail_tile(a, d, q, &s_tail, L, s_rb[lo] + o, min(s_len[lo] - o, kTailTile), k, st_live);
         }
         __syncthreads();
       }
@@ -2337,11 +2398,11 @@ __global__ __launch_bounds__(kTailThreads) void tail_kernel(PeelArgs a, int32_t 
   }
   // statistics: the tail's share of the decomposition's counters (its decrements are LDS
   // operations, not counted with the global ones)
-  long long v5[2] = {st_edges, st_scanned};
-  for (int qd = 0; qd < 2; ++qd) {
+  long long v5[3] = {st_edges, st_scanned, st_live};
+  for (int qd = 0; qd < 3; ++qd) {
     long long x = v5[qd];
     for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-    if (l == 0 && x) aadd(&a.ctl->stats[qd == 0 ? ST_EDGES : ST_SCANNED], (unsigned long long)x);
+    if (l == 0 && x) aadd(&a.ctl->stats[qd == 0 ? ST_EDGES : qd == 1 ? ST_SCANNED : ST_LIVE], (unsigned long long)x);
   }
   if (tid == 0) {
     aadd(&a.ctl->stats[ST_PEELED], (unsigned long long)L);

@@ -29,10 +29,15 @@ constexpr int kTailBig = 256;         //   rows at least this long are streamed 
 constexpr int kTailTile = 2048;       //   ... of this many entries (4 16-byte loads of 8 ids per lane)
 constexpr uint16_t kTailQEmpty = 0xffffu;  // unwritten slot of the tail's 16-bit queue (ids < 65,535)
 
+// ST_LIVE: decrement units that landed on a vertex still above k (one per peeled vertex and live
+// neighbour; a combined count of c on a vertex at d > k contributes min(c, d - k)).
+// ST_BUCKET: insertions into the multi-bucket active set (placements and moves).
 enum StatIdx {
   ST_ROUNDS = 0, ST_SUBROUNDS, ST_BARRIERS, ST_PEELED, ST_EDGES, ST_DECR, ST_COMBINED, ST_SCANNED,
-  ST_KMAX, ST_TAIL, ST_SAMPLED, ST_RECOUNTS, ST_NUM
+  ST_KMAX, ST_TAIL, ST_SAMPLED, ST_RECOUNTS, ST_LIVE, ST_BUCKET, ST_NUM
 };
+constexpr int kStatWords = 24;   // statistics words of a control block
+constexpr int kDiagWord = 20;    // [20, 24): diagnostics of a failed run
 
 // Counters produced during one phase (three-way rotation, see the peel kernel).
 struct alignas(128) PhaseSlot {
@@ -65,7 +70,7 @@ struct alignas(128) PeelCtl {
   unsigned int s_valk;
   unsigned int s_ncand;
   unsigned long long pad3[13];
-  unsigned long long stats[16];
+  unsigned long long stats[kStatWords];
   // survivors each workgroup wrote into its segment of active list 0 / 1 (see the peel kernel)
   unsigned int acnt[2][kMaxPeelBlocks];
   // phase timeline of workgroup 0, not cleared between launches: 100 MHz wall clock at start,
@@ -79,13 +84,17 @@ struct alignas(128) PeelCtl {
 
 // KC_ERR_SAMPLE: a sampled vertex was found below k at a round boundary (the Las Vegas check of
 // the sampling scheme); the host then runs the decomposition again without sampling.
+// KC_ERR_CHECK: (checked builds only) a coreness written twice or an induced degree decremented
+// below zero.
 enum : unsigned { KC_ERR_TIMEOUT = 1u, KC_ERR_OVERFLOW = 2u, KC_ERR_PHASES = 4u, KC_ERR_BADGRAPH = 8u,
-                  KC_ERR_SAMPLE = 16u };
+                  KC_ERR_SAMPLE = 16u, KC_ERR_CHECK = 32u };
 
 struct PeelArgs {
   const int64_t* off;
   const int32_t* adj;
   int64_t n;
+  int64_t m_bound;     // entries adj holds at most; the kernel stops with KC_ERR_OVERFLOW when
+                       // offsets[n] exceeds it (the workspace was sized from it)
   int32_t* core;
   uint32_t* dt;        // induced degree, bit 31 = hub flag
   uint32_t* state;     // per 16 vertices: bits 0..15 peeled, 16..31 hub
@@ -144,7 +153,7 @@ struct BatchCtl {
   unsigned long long next;
   unsigned int status;
   unsigned int pad[29];
-  unsigned long long stats[16];
+  unsigned long long stats[kStatWords];
 };
 
 struct BatchArgs {

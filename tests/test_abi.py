@@ -35,13 +35,39 @@ def test_library_exports_every_declared_symbol():
         assert name in K.SIGNATURES, f"{name} has no binding signature"
 
 
-def test_struct_layouts_match_header_sizes():
+def test_struct_layouts_match_header(tmp_path):
+    """Every field of the binding's ctypes structures sits at the offset the C compiler gives the
+    header's field of the same name, and the sizes agree (gcc compiles a probe of kcore.h)."""
+    import shutil
+    import subprocess
     import paper_2502_08042_amd as K
-    # sizes implied by the header's field lists (natural alignment on x86-64)
-    assert ctypes.sizeof(K.Options) == 64
-    assert ctypes.sizeof(K.Stats) == 8 * 8 + 4 * 3 + 4 * 5
-    assert ctypes.sizeof(K.ServerConfig) == 16 + 8 * 3 + 8 + 8 + 16 + 8
-    assert ctypes.sizeof(K.RequestStats) == 8 * 4 + 8 + 8
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    structs = {"kcore_options": K.Options, "kcore_stats": K.Stats,
+               "kcore_server_config": K.ServerConfig, "kcore_request_stats": K.RequestStats}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "kcore.h"', "int main(void) {"]
+    for cname, cls in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in cls._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "probe.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "probe"
+    r = subprocess.run(["gcc", "-x", "c", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include",
+                        "-I" + os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                       capture_output=True, text=True)
+    if r.returncode != 0 and "hip_runtime_api.h" in r.stderr:
+        pytest.skip("HIP headers not available")
+    assert r.returncode == 0, r.stderr
+    got = {}
+    for line in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.splitlines():
+        cname, field, val = line.split()
+        got[(cname, field)] = int(val)
+    for cname, cls in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert got[(cname, f)] == getattr(cls, f).offset, (cname, f)
 
 
 def test_argument_errors_without_device_work():

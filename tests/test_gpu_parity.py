@@ -170,20 +170,18 @@ def test_tail_handoff_sizes(mode):
                     assert st["tail_vertices"] > 17408, st
 
 
-def test_tail_handoff_called_off(monkeypatch):
+def test_tail_handoff_called_off():
     """A handoff whose local rows do not fit is called off and retried when half as many
     vertices are live (or never happens): the grid keeps peeling and the result is unchanged."""
     for name, g in _tail_cases():
         off, adj = (g.offsets, g.adj) if g is not None else G.hcns(120)
         want = oracle.bz(off, adj)
-        for ecap in (0, 50, 2000):
-            monkeypatch.setenv("KCORE_DEBUG_TAIL_ECAP", str(ecap))
+        for ecap in (1, 50, 2000):
             say(f"[gpu] tail called off {name} ecap={ecap}")
-            got, st = run_single(off, adj, mode="chained")
+            got, st = run_single(off, adj, mode="chained", test_tail_entries=ecap)
             assert not first_mismatch(got, want), first_mismatch(got, want)
             assert st["peeled"] == len(off) - 1 and st["edges"] == len(adj), st
             assert st["device_status"] == 0
-    monkeypatch.delenv("KCORE_DEBUG_TAIL_ECAP")
 
 
 @pytest.mark.parametrize("tail", [0, -1])
@@ -208,22 +206,26 @@ def test_offline_mode_keeps_levelsync_frontiers(tail):
             assert st["combined"] > 0, st
 
 
-@pytest.mark.parametrize("mode,knobs", [("offline", None), ("sampling", None), ("sampling", "2,4")])
-def test_small_graphs_other_modes(monkeypatch, mode, knobs):
+def _sample_knobs(knobs):
+    if knobs is None:
+        return {}
+    th, mu = knobs
+    return {"sample_threshold": th, "sample_mu": mu}
+
+
+@pytest.mark.parametrize("mode,knobs", [("offline", None), ("sampling", None), ("sampling", (2, 4))])
+def test_small_graphs_other_modes(mode, knobs):
     """Exact graph families and golden fixtures in offline and sampling mode (with nearly every
     vertex in sample mode for threshold 2)."""
-    if knobs:
-        monkeypatch.setenv("KCORE_DEBUG_SAMPLE", knobs)
     for name, (off, adj) in small_cases():
         say(f"[gpu] small {name} mode={mode} knobs={knobs}")
-        got, st = run_single(off, adj, mode=mode)
+        got, st = run_single(off, adj, mode=mode, **_sample_knobs(knobs))
         want = oracle.bz(off, adj)
         assert not first_mismatch(got, want), f"{name}: {first_mismatch(got, want)}"
         assert st["peeled"] == len(off) - 1 and st["device_status"] == 0, (name, st)
-    monkeypatch.delenv("KCORE_DEBUG_SAMPLE", raising=False)
 
 
-def test_sampling_mode_is_exact(monkeypatch):
+def test_sampling_mode_is_exact():
     """Sampling mode (Alg. 4/5): hubs count hits instead of decrementing and are validated and
     recounted at round boundaries; the coreness must still be the oracle's, every vertex peeled
     and every entry expanded once. Low thresholds put many vertices in sample mode."""
@@ -233,31 +235,24 @@ def test_sampling_mode_is_exact(monkeypatch):
     for name, g in cases:
         off, adj = (g.offsets, g.adj) if g is not None else G.hcns(120)
         want = oracle.bz(off, adj)
-        for knobs in (None, "128,100", "16,32", "8,400"):
-            if knobs is None:
-                monkeypatch.delenv("KCORE_DEBUG_SAMPLE", raising=False)
-            else:
-                monkeypatch.setenv("KCORE_DEBUG_SAMPLE", knobs)
+        for knobs in (None, (128, 100), (16, 32), (8, 400)):
             say(f"[gpu] sampling {name} threshold,mu={knobs}")
-            got, st = run_single(off, adj, mode="sampling")
+            got, st = run_single(off, adj, mode="sampling", **_sample_knobs(knobs))
             assert not first_mismatch(got, want), first_mismatch(got, want)
             assert st["peeled"] == len(off) - 1 and st["edges"] == len(adj), st
             assert st["device_status"] == 0 and st["kmax"] == int(want.max())
-            thr = 1024 if knobs is None else int(knobs.split(",")[0])
+            thr = 1024 if knobs is None else knobs[0]
             assert st["sampled_vertices"] == int((np.diff(off) > thr).sum()), st
-    monkeypatch.delenv("KCORE_DEBUG_SAMPLE", raising=False)
 
 
-def test_sampling_failure_is_detected_and_repeated(monkeypatch):
+def test_sampling_failure_is_detected_and_repeated():
     """A star's centre in sample mode with one expected hit (mu = 1) loses every neighbour in
     round 1 unseen: the recount at a later round boundary finds it below k, the run is void and
     is repeated without sampling, and the result is still exact."""
     off, adj = G.star(64)
     want = oracle.bz(off, adj)
-    monkeypatch.setenv("KCORE_DEBUG_SAMPLE", "4,1")
     say("[gpu] sampling failure on star64")
-    got, st = run_single(off, adj, mode="sampling")
-    monkeypatch.delenv("KCORE_DEBUG_SAMPLE")
+    got, st = run_single(off, adj, mode="sampling", sample_threshold=4, sample_mu=1)
     assert not first_mismatch(got, want), first_mismatch(got, want)
     assert st["sample_restarts"] == 1 and st["sampled_vertices"] == 1, st
     assert st["device_status"] == 0 and st["peeled"] == len(off) - 1
