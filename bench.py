@@ -173,6 +173,7 @@ def measure_single(off, adj, steps, warmup, mode="auto", **tuning):
 def bench_chunglu(args):
     """The headline: one decomposition of the Chung-Lu graph per step."""
     import numpy as np
+    import torch
     t0 = time.time()
     off, adj, desc = build_workload("chunglu")
     n, m = off.numel() - 1, adj.numel()
@@ -200,6 +201,14 @@ def bench_chunglu(args):
                      "scanned": r["scanned"], "kernel": "peel_kernel + tail_kernel",
                      "kernel_ms_per_launch": ev["mean"]},
     }
+    if args.workload == "all":
+        # the same graph with the multi-bucket active set (from n/8 live vertices at k >= 16)
+        rb, _, outb = measure_single(off, adj, min(args.steps, 5), 1, mode=args.mode, buckets=n // 8)
+        res["with_buckets"] = {k: rb[k] for k in ("ms_per_step", "event_ms", "gteps", "rounds", "barriers",
+                                                  "scanned", "bucket_inserts", "tail_vertices", "hbm_frac")}
+        res["with_buckets"]["options"] = {"buckets": n // 8}
+        res["with_buckets"]["same_coreness"] = bool(torch.equal(outb, out))
+        del outb
     if not args.no_cpu_baseline:
         h_off, h_adj = off.cpu().numpy(), adj.cpu().numpy()
         log(f"[bench] chunglu oracle: 1 warm-up + {ORACLE_RUNS} runs on one core")

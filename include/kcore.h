@@ -150,6 +150,14 @@ typedef struct {
                             part of this header); 0 = off */
   int64_t test_tail_entries; /* testing: pretend the tail's local rows hold at most this many
                             entries, so that handoffs are called off and retried; 0 = off */
+  int32_t steal;         /* chained mode: in a round's scan phase, hub tiles beyond this many waiting
+                            in a workgroup's queue (and the tiles of hubs too large for it) go to a
+                            queue shared by the grid, which every workgroup helps to drain once its
+                            own share is done (the phase ends when that queue is quiescent), instead
+                            of waiting for the next phase; 0 = default, -1 = never */
+  int32_t batch_teams;   /* batched peel (level-sync): a graph with more adjacency entries than this
+                            is peeled by a team of workgroups; 0 = default (half a workgroup's
+                            average share of the batch's entries), -1 = never */
   uint32_t* status_out;  /* nullable, device or pinned host memory: receives the device status word
                             of the call (0 = success, else internal failure bits) when `stream`
                             reaches the end of the call */
@@ -177,10 +185,11 @@ typedef struct {
   int32_t sample_recounts; /* sampling mode: validations that recounted a vertex's live degree */
   int32_t sample_restarts; /* sampling mode: 1 if the sampled run failed and was repeated */
   int32_t reserved[1];
-  int64_t live_decrements; /* decrement units that landed on a vertex still above k (Alg. 1's
-                              test "induced degree > k"): one per peeled vertex and live neighbour,
-                              at most m / 2 on a simple graph; counted in the tail and in LDS
-                              combining too (a count of c on a vertex at d > k adds min(c, d - k)) */
+  int64_t live_decrements; /* decrements that land on a vertex still above k (Alg. 1's test
+                              "induced degree > k"): one per peeled vertex and live neighbour, at
+                              most m / 2 on a simple graph. A vertex receives exactly deg - coreness
+                              of them whatever the order, so this is computed after the run as
+                              offsets[n] - sum of coreness (0 for the k-core query) */
   int64_t bucket_inserts;  /* insertions into the multi-bucket active set (kcore_options.buckets):
                               placements, moves to lower buckets and redistributions */
 } kcore_stats;

@@ -53,7 +53,8 @@ class Options(ctypes.Structure):
                 ("residual", ctypes.c_int32), ("tail", ctypes.c_int32),
                 ("buckets", ctypes.c_int32), ("sample_threshold", ctypes.c_int32),
                 ("sample_mu", ctypes.c_int32), ("debug_phase", ctypes.c_int32),
-                ("test_tail_entries", ctypes.c_int64), ("status_out", ctypes.c_void_p)]
+                ("test_tail_entries", ctypes.c_int64), ("steal", ctypes.c_int32),
+                ("batch_teams", ctypes.c_int32), ("status_out", ctypes.c_void_p)]
 
 
 class Stats(ctypes.Structure):
@@ -195,7 +196,7 @@ def _stream_ptr(stream) -> int:
 def _options(mode, validate, num_entries, hub_degree=0, local_budget=0, tile_edges=0,
              blocks_per_cu=0, async_frontier=0, async_scan=0, block_tiles=0,
              block_queue=0, tile_probe=0, residual=0, tail=0, buckets=0, sample_threshold=0,
-             sample_mu=0, debug_phase=0, test_tail_entries=0, status_out=None) -> Options:
+             sample_mu=0, debug_phase=0, test_tail_entries=0, steal=0, batch_teams=0, status_out=None) -> Options:
     o = Options()
     o.mode = MODES[mode] if isinstance(mode, str) else int(mode)
     o.validate = 1 if validate else 0
@@ -216,6 +217,8 @@ def _options(mode, validate, num_entries, hub_degree=0, local_budget=0, tile_edg
     o.sample_mu = sample_mu
     o.debug_phase = debug_phase
     o.test_tail_entries = test_tail_entries
+    o.steal = steal
+    o.batch_teams = batch_teams
     o.status_out = status_out
     return o
 
@@ -228,14 +231,19 @@ def _dev_tensor(t, dtype, name):
 
 
 def decompose(offsets, adj, out=None, *, mode="auto", stats=False, validate=False, stream=None,
-              **tuning):
+              tuned=False, **tuning):
     """Coreness of every vertex of one graph (device CSR: int64 offsets[n+1], int32 adj[m]).
 
     Returns the int32 coreness tensor (``out`` if given), plus a dict of counters when
-    ``stats=True`` (that call synchronises the stream)."""
+    ``stats=True`` (that call synchronises the stream). ``tuned=True`` applies the autotuner's
+    cached options for this device and the graph's workload class (explicit ``tuning`` keywords
+    win)."""
     import torch
     _dev_tensor(offsets, torch.int64, "offsets")
     _dev_tensor(adj, torch.int32, "adj")
+    if tuned:
+        from . import autotune
+        tuning = {**autotune.tuned_options(offsets), **tuning}
     n = offsets.numel() - 1
     if out is None:
         out = torch.empty(max(n, 0), dtype=torch.int32, device=offsets.device)
@@ -273,11 +281,18 @@ def kcore_subgraph(offsets, adj, k, out=None, *, mode="auto", stats=False, valid
 
 
 def decompose_batched(vptr, offsets, adj, out=None, *, mode="auto", stats=False, validate=False,
-                      stream=None):
+                      stream=None, tuned=False, blocks_per_cu=0, batch_teams=0):
     """Coreness for a segmented batch of independent graphs (device tensors, global ids).
     ``mode``: "auto"/"levelsync" (barrier-separated subrounds inside each graph's workgroup) or
-    "chained" (each round peeled through a dynamic workgroup queue)."""
+    "chained" (each round peeled through a dynamic workgroup queue). ``tuned=True`` applies the
+    autotuner's cached mode and workgroups per CU for this device and batch size."""
     import torch
+    if tuned:
+        from . import autotune
+        t = autotune.tuned_options(offsets, batched=True)
+        mode = t.get("mode", mode)
+        blocks_per_cu = t.get("blocks_per_cu", blocks_per_cu)
+        batch_teams = t.get("batch_teams", batch_teams)
     _dev_tensor(vptr, torch.int64, "vptr")
     _dev_tensor(offsets, torch.int64, "offsets")
     _dev_tensor(adj, torch.int32, "adj")
@@ -288,7 +303,7 @@ def decompose_batched(vptr, offsets, adj, out=None, *, mode="auto", stats=False,
     if out is None:
         out = torch.empty(max(V, 0), dtype=torch.int32, device=offsets.device)
     _dev_tensor(out, torch.int32, "out")
-    opt = _options(mode, validate, adj.numel())
+    opt = _options(mode, validate, adj.numel(), blocks_per_cu=blocks_per_cu, batch_teams=batch_teams)
     st = Stats() if stats else None
     rc = _lib.kcore_decompose_batched_ex(vptr.data_ptr(), offsets.data_ptr(), adj.data_ptr(), G, V,
                                          out.data_ptr() if V else None, _stream_ptr(stream),

@@ -69,16 +69,22 @@ struct GridOrder {
 std::mutex g_grid_mu;
 std::map<int, GridOrder> g_grid;
 
-int launch_peel_ordered(int dev, const kc::PeelArgs& a, int blocks, hipStream_t stream) {
+// (also the batched peel when it runs teams: a cooperative grid whose teams wait for each other)
+template <class F>
+int launch_ordered(int dev, hipStream_t stream, F&& launch) {
   std::lock_guard<std::mutex> lk(g_grid_mu);
   GridOrder& o = g_grid[dev];
   if (!o.ev) HIP_TRY(hipEventCreateWithFlags(&o.ev, hipEventDisableTiming));
   if (o.any && o.last != stream) HIP_TRY(hipStreamWaitEvent(stream, o.ev, 0));
-  HIP_TRY(kc::launch_peel(a, blocks, stream));
+  HIP_TRY(launch());
   HIP_TRY(hipEventRecord(o.ev, stream));
   o.last = stream;
   o.any = true;
   return KCORE_OK;
+}
+
+int launch_peel_ordered(int dev, const kc::PeelArgs& a, int blocks, hipStream_t stream) {
+  return launch_ordered(dev, stream, [&] { return kc::launch_peel(a, blocks, stream); });
 }
 
 int dev_info(int dev, DevInfo& out) {
@@ -153,6 +159,12 @@ struct PeelWs {
   uint32_t* scount = nullptr;
   int32_t* scand = nullptr;
   int32_t* srl = nullptr;
+  // multi-bucket active set (allocated on first use): slots x cap bucket entries, then the
+  // per-vertex tags
+  void* hblock = nullptr;
+  size_t h_bytes = 0;
+  int32_t* hbl = nullptr;
+  uint32_t* hlo = nullptr;
   kc::PeelCtl* ctl = nullptr;
   unsigned long long* host_stats = nullptr;  // pinned
   unsigned* vstat = nullptr;                 // validation status + xor sum (device)
@@ -286,6 +298,33 @@ int sample_ws(PeelWs* w, hipStream_t s, int64_t n) {
   return KCORE_OK;
 }
 
+// Multi-bucket arrays of a single-graph workspace: slots x cap entries and n tags.
+int bucket_ws(PeelWs* w, hipStream_t s, int64_t n, int32_t slots, int64_t cap) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  const size_t lists = align_up(4 * (size_t)slots * (size_t)cap);
+  const size_t need = lists + align_up(4 * (size_t)n);
+  if (w->hblock && w->h_bytes >= need) {
+    w->hbl = static_cast<int32_t*>(w->hblock);
+    w->hlo = reinterpret_cast<uint32_t*>(static_cast<char*>(w->hblock) + lists);
+    return KCORE_OK;
+  }
+  if (w->hblock) {
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipFree(w->hblock));
+    w->hblock = nullptr;
+    w->h_bytes = 0;
+  }
+  hipError_t e = hipMalloc(&w->hblock, need);
+  if (e != hipSuccess) {
+    w->hblock = nullptr;
+    return fail(KCORE_ENOMEM, "bucket workspace of %zu bytes: %s", need, hipGetErrorString(e));
+  }
+  w->h_bytes = need;
+  w->hbl = static_cast<int32_t*>(w->hblock);
+  w->hlo = reinterpret_cast<uint32_t*>(static_cast<char*>(w->hblock) + lists);
+  return KCORE_OK;
+}
+
 int batch_ws(int dev, hipStream_t s, int64_t V, int32_t G, BatchWs*& out) {
   std::lock_guard<std::mutex> lk(g_mu);
   BatchWs*& w = g_batch[Key(dev, s)];
@@ -378,6 +417,8 @@ int check_opts(const kcore_options* o) {
   if (o->async_frontier < -1 || o->async_scan < -1 || o->block_tiles < -1)
     return fail(KCORE_EINVAL, "async and block-tile thresholds must be >= -1");
   if (o->buckets < -1) return fail(KCORE_EINVAL, "buckets must be >= -1");
+  if (o->steal < -1 || o->steal > kc::kBlockQ) return fail(KCORE_EINVAL, "steal must be in [-1, %d]", kc::kBlockQ);
+  if (o->batch_teams < -1) return fail(KCORE_EINVAL, "batch_teams must be >= -1");
   if (o->sample_threshold < 0 || o->sample_mu < 0 || o->debug_phase < 0 || o->test_tail_entries < 0)
     return fail(KCORE_EINVAL, "sampling parameters and test hooks must be >= 0");
   return KCORE_OK;
@@ -543,6 +584,8 @@ static int peel_impl(const int64_t* offsets, const int32_t* adj, int64_t n, int3
   const int32_t bt = opt ? opt->block_tiles : 0;
   a.bq_max_tiles = bt < 0 ? 0 : (bt ? bt : 32);
   a.bq_backlog = (opt && opt->block_queue) ? opt->block_queue : 64;
+  const int32_t so = opt ? opt->steal : 0;
+  a.steal_backlog = so < 0 ? 0 : (so ? so : 0);
   a.tile_probe_always = !(opt && opt->tile_probe < 0);
   a.k_query = k_query;
   a.rrow = w->rrow;
@@ -557,6 +600,27 @@ static int peel_impl(const int64_t* offsets, const int32_t* adj, int64_t n, int3
   a.tail_ecap = tail_ecap;
   // testing aid: pretend the local rows hold fewer entries, so that handoffs are called off
   if (opt && opt->test_tail_entries > 0) a.tail_ecap = std::min<int64_t>(tail_ecap, opt->test_tail_entries);
+  // multi-bucket active set (Sec. 5.2): once at most hbs_vmax vertices are live (k >= 16); each
+  // slot holds up to twice that many entries (a vertex enters a slot's range once; a scan that
+  // races with a decrement can list it a second time), values below 2^hslots (degrees < n)
+  a.hbl = nullptr;
+  a.hlo = nullptr;
+  a.hcap = 0;
+  a.hslots = 0;
+  a.hbs_vmax = -1;
+  const int32_t bo = opt ? opt->buckets : 0;
+  if (bo > 0 && !sampling && k_query <= 0) {
+    const int64_t vmax = std::min<int64_t>(bo, n);
+    int32_t slots = 1;
+    while (slots < 31 && ((int64_t)1 << slots) <= n - 1) ++slots;
+    const int64_t cap = 2 * vmax + 1024;
+    if (int rc = bucket_ws(w, stream, n, slots, cap)) return rc;
+    a.hbl = w->hbl;
+    a.hlo = w->hlo;
+    a.hcap = cap;
+    a.hslots = slots;
+    a.hbs_vmax = vmax;
+  }
   a.sampling = sampling ? 1 : 0;
   a.s_threshold = a.s_mu = a.s_seed = 0;
   a.srate = a.scnt = a.sbase = a.scount = nullptr;
@@ -594,6 +658,8 @@ static int peel_impl(const int64_t* offsets, const int32_t* adj, int64_t n, int3
     HIP_TRY(hipMemcpyAsync(opt->status_out, &w->ctl->status, sizeof(unsigned), hipMemcpyDefault, stream));
   if (!stats_host) return KCORE_OK;
   HIP_TRY(hipEventRecord(w->ev1, stream));
+  // (after the timed region: live decrements from the finished coreness)
+  if (k_query <= 0) HIP_TRY(kc::launch_live_count(offsets, coreness_out, n, &w->ctl->stats[kc::ST_LIVE], stream));
   HIP_TRY(hipMemcpyAsync(w->host_stats, w->ctl->stats, kc::kStatWords * sizeof(unsigned long long),
                          hipMemcpyDeviceToHost, stream));
   unsigned status = 0;
@@ -697,7 +763,7 @@ int kcore_decompose(const int64_t* offsets, const int32_t* adj, int64_t n, int32
 static int batched_impl(const int64_t* graph_vptr, const int64_t* offsets, const int32_t* adj,
                         int32_t num_graphs, int64_t total_vertices, int32_t* coreness_out,
                         hipStream_t stream, const kcore_options* opt, kcore_stats* stats_host,
-                        bool local_ids, unsigned* status_out = nullptr);
+                        bool local_ids, unsigned* status_out = nullptr, int32_t team_wgs = 0);
 
 int kcore_decompose_batched_ex(const int64_t* graph_vptr, const int64_t* offsets, const int32_t* adj,
                                int32_t num_graphs, int64_t total_vertices, int32_t* coreness_out,
@@ -734,15 +800,23 @@ void kc::release_batched(hipStream_t stream) {
 
 int kc::decompose_batched_local(const int64_t* graph_vptr, const int64_t* offsets, const int32_t* adj,
                                 int32_t num_graphs, int64_t total_vertices, int32_t* coreness_out,
-                                hipStream_t stream, unsigned* status_out) {
+                                hipStream_t stream, unsigned* status_out, int32_t team_wgs) {
   return batched_impl(graph_vptr, offsets, adj, num_graphs, total_vertices, coreness_out, stream, nullptr,
-                      nullptr, true, status_out);
+                      nullptr, true, status_out, team_wgs);
+}
+
+int kc::batched_resident_wgs() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  DevInfo di;
+  if (dev_info(dev, di)) return 0;
+  return di.batch_bpc * di.cus;
 }
 
 static int batched_impl(const int64_t* graph_vptr, const int64_t* offsets, const int32_t* adj,
                         int32_t num_graphs, int64_t total_vertices, int32_t* coreness_out,
                         hipStream_t stream, const kcore_options* opt, kcore_stats* stats_host,
-                        bool local_ids, unsigned* status_out) {
+                        bool local_ids, unsigned* status_out, int32_t team_wgs) {
   g_err.clear();
   if (num_graphs < 0 || total_vertices < 0)
     return fail(KCORE_EINVAL, "negative num_graphs or total_vertices");
@@ -792,8 +866,27 @@ static int batched_impl(const int64_t* graph_vptr, const int64_t* offsets, const
   if (opt && (opt->mode == KCORE_MODE_SAMPLING || opt->mode == KCORE_MODE_OFFLINE))
     return fail(KCORE_EINVAL, "the batched peel has neither sampling nor offline mode (its degrees live in LDS)");
   a.chained = (opt && opt->mode == KCORE_MODE_CHAINED) ? 1 : 0;
+  // The largest graphs may get teams of workgroups (level-sync mode). A caller's batch runs in a
+  // cooperative grid (teams wait for each other, so all must be resident); the serving runtime's
+  // large batches (team_wgs > 0) put every graph in a team, in a grid of only the team workgroups
+  // whose total over its concurrent batches it keeps within what the device holds.
+  const int32_t bt = opt ? opt->batch_teams : 0;
+  const bool coop_teams = !local_ids && !a.chained && bt >= 0 && blocks >= 4 * kc::kTeamSize &&
+                          !(opt && opt->blocks_per_cu);
+  const bool serve_teams = local_ids && team_wgs >= kc::kTeamSize;
+  a.teams = (coop_teams || serve_teams) ? 1 : 0;
+  if (serve_teams) blocks = std::min(blocks, std::min(team_wgs, num_graphs * kc::kTeamSize));
+  if (a.teams)
+    HIP_TRY(kc::launch_team_plan(graph_vptr, offsets, num_graphs, w->order, blocks,
+                                 serve_teams ? blocks : blocks / 2, serve_teams ? 1 : 0, bt > 0 ? bt : 0,
+                                 w->ctl, stream));
   if (stats_host) HIP_TRY(hipEventRecord(w->ev0, stream));
-  HIP_TRY(kc::launch_batched(a, blocks, lds, stream));
+  if (coop_teams) {
+    if (int rc = launch_ordered(dev, stream, [&] { return kc::launch_batched_coop(a, blocks, lds, stream); }))
+      return rc;
+  } else {
+    HIP_TRY(kc::launch_batched(a, blocks, lds, stream));
+  }
   // the device status word (failure bits), for callers that check it after the stream
   if (status_out)
     HIP_TRY(hipMemcpyAsync(status_out, &w->ctl->status, sizeof(unsigned), hipMemcpyDeviceToHost, stream));
@@ -801,6 +894,7 @@ static int batched_impl(const int64_t* graph_vptr, const int64_t* offsets, const
     HIP_TRY(hipMemcpyAsync(opt->status_out, &w->ctl->status, sizeof(unsigned), hipMemcpyDefault, stream));
   if (!stats_host) return KCORE_OK;
   HIP_TRY(hipEventRecord(w->ev1, stream));
+  HIP_TRY(kc::launch_live_count(offsets, coreness_out, total_vertices, &w->ctl->stats[kc::ST_LIVE], stream));
   HIP_TRY(hipMemcpyAsync(w->host_stats, w->ctl->stats, kc::kStatWords * sizeof(unsigned long long),
                          hipMemcpyDeviceToHost, stream));
   HIP_TRY(hipMemcpyAsync(w->host_stats + kc::kStatWords, &w->ctl->status, sizeof(unsigned),
@@ -861,6 +955,7 @@ int kcore_release_workspaces(void) {
     if (!w) continue;
     if (w->block) hipFree(w->block);
     if (w->sblock) hipFree(w->sblock);
+    if (w->hblock) hipFree(w->hblock);
     if (w->host_stats) hipHostFree(w->host_stats);
     if (w->ev0) hipEventDestroy(w->ev0);
     if (w->ev1) hipEventDestroy(w->ev1);

@@ -249,7 +249,7 @@ struct WaveCtx {
   int32_t* lq;         // local queue ring (chained mode)
   int lq_head, lq_cnt; // wave-uniform
   int lq_used;         // vertices peeled from the local queue this phase
-  long long edges, decr, scanned, peeled, comb, live;  // per-lane statistics
+  long long edges, decr, scanned, peeled, comb, binserts;  // per-lane statistics
   unsigned mymin;      // per-lane min over kept vertices
   int32_t* ckey;       // LDS combining table (block-shared): target id or -1
   uint32_t* ccnt;      //   decrements collected for it in this phase
@@ -258,12 +258,16 @@ struct WaveCtx {
   bool async;          // phase-uniform: pushes go to the async work queue
   bool arbitrate;      // phase-uniform: crossings may race with a scan (chained scan phases)
   bool bq_open;        // phase-uniform: small hubs go to the workgroup's tile queue
+  bool steal;          // phase-uniform: hub tiles the workgroup queue refuses go to the phase's
+                       // shared work queue, which every workgroup helps to drain after its share
   unsigned long long* bq;  // LDS, kBlockQ entries: (tile << 32) | vertex, kQEmpty or kQSkip
   int* bqc;            // LDS: claimed, reserved, busy waves, [4..5] debug counts
   const int32_t* adj;  // adjacency the rows point into: the input, or the residual rows
   const long long* rows;  // row bounds: offsets (stride 1) or residual (start, end) pairs (stride 2)
   int rstride;
   bool resid;          // rows come from the residual rows
+  bool hbs;            // phase-uniform: the multi-bucket active set is kept (decrements move vertices)
+  long long* hlen;     // LDS: entries in each bucket slot before this phase (same in every workgroup)
 };
 
 // Row of v: [b, b + d) in c.adj.
@@ -303,6 +307,80 @@ struct PhaseOut {
   int32_t* fr;  // frontier list written in this phase
   unsigned long long* tl;  // tile list written in this phase (span words)
 };
+
+// ------------------------------------------------------------------------------------------
+// Multi-bucket active set (HBS, Sec. 5.2). Relative to the current round k, a live vertex with
+// induced degree x > k belongs to bucket b = the highest bit in which x and k differ (x has a 1
+// there, k a 0): the ranges above k are aligned blocks of 1, 2, 4, ... values, so the bucket of a
+// value only changes for values in the block that k itself enters. When k moves to k' > k, the
+// buckets above H = the highest bit of k ^ k' keep their ranges, bucket H holds exactly the values
+// from k' up to its block's end (redistributed by the next scan into lower buckets, with the
+// vertices at k' extracted), and the buckets below H held only values below k' (all peeled), so
+// they start empty. Buckets are append-only lists; a vertex whose induced degree drops into a
+// lower bucket is appended there (the old copy goes stale and is dropped when read). A per-vertex
+// tag (the lower end of the range it was last filed into) keeps a vertex from being appended
+// twice to one range: every change of the tag comes with an append, so a vertex is always listed
+// in the bucket of its current value.
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ int hbs_bucket(uint32_t x, uint32_t k) { return 31 - __clz(x ^ k); }
+__device__ __forceinline__ uint32_t hbs_lo(uint32_t k, int b) { return ((k >> b) | 1u) << b; }
+
+// Appends v to bucket slot b for the lanes with want: one reservation per distinct slot in the
+// wave. All lanes call.
+__device__ __forceinline__ void hbs_append(const PeelArgs& a, WaveCtx& c, const PhaseOut& o, bool want,
+                                           int32_t v, int b) {
+  unsigned long long pend = __ballot(want);
+  while (pend) {
+    const int leader = __ffsll((long long)pend) - 1;
+    const int bl = __shfl(b, leader, 64);
+    const bool mine = want && b == bl;
+    const unsigned long long mm = __ballot(mine);
+    unsigned long long base = 0;
+    if (lane_id() == leader && bl < a.hslots) base = aadd(&o.slot->hadd[bl], (unsigned long long)__popcll(mm));
+    base = __shfl(base, leader, 64);
+    if (mine) {
+      const long long pos = c.hlen[bl] + (long long)base + rank_in(mm);
+      if (bl < a.hslots && pos < a.hcap) {
+        ast(&a.hbl[(long long)bl * a.hcap + pos], v);
+        c.binserts += 1;
+      } else {
+        aor(&a.ctl->status, (unsigned)KC_ERR_OVERFLOW);
+      }
+    }
+    pend &= ~mm;
+  }
+}
+
+// A decrement took u from xo to xn in round k: if xn > k lies in a lower bucket than xo, u is
+// filed there unless its tag says it already is. All lanes call.
+__device__ __forceinline__ void hbs_move(const PeelArgs& a, WaveCtx& c, const PhaseOut& o, bool did, int32_t u,
+                                         uint32_t xo, uint32_t xn, uint32_t k) {
+  bool want = false;
+  int b = 0;
+  if (did && xn > k && xn < xo) {
+    b = hbs_bucket(xn, k);
+    if (b < hbs_bucket(xo, k)) {
+      const uint32_t lo = hbs_lo(k, b);
+      want = __hip_atomic_exchange(&a.hlo[u], lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != lo;
+    }
+  }
+  hbs_append(a, c, o, want, u, b);
+}
+
+// A scan read v live with x > k (keep) after reading its tag t: file it into its bucket, unless
+// the tag already names that range or changed meanwhile (then whoever changed it filed v). All
+// lanes call.
+__device__ __forceinline__ void hbs_file(const PeelArgs& a, WaveCtx& c, const PhaseOut& o, bool keep, int32_t v,
+                                         uint32_t x, uint32_t t, uint32_t k) {
+  bool want = false;
+  int b = 0;
+  if (keep) {
+    b = hbs_bucket(x, k);
+    const uint32_t lo = hbs_lo(k, b);
+    if (t != lo) want = atomicCAS(&a.hlo[v], t, lo) == t;
+  }
+  hbs_append(a, c, o, want, v, b);
+}
 
 // Pushes crossed/extracted vertices: hubs are split into tiles on the global tile list, small
 // vertices go to the wave's local queue (chained mode, while it has room) or the staged frontier.
@@ -412,10 +490,15 @@ __device__ __forceinline__ void push_vertices(const PeelArgs& a, WaveCtx& c, con
       return;
     }
     bool pg = ph;
-    if (c.bq_open && block_push(c, rb, deg, a.tile, (ph && nt <= a.bq_max_tiles) ? nt : 0, a.bq_backlog))
+    if (c.bq_open && block_push(c, rb, deg, a.tile, (ph && nt <= a.bq_max_tiles) ? nt : 0,
+                                c.steal ? a.steal_backlog : a.bq_backlog))
       pg = false;
     if (!pg) nt = 0;
     if (__ballot(pg) == 0) return;
+    if (c.steal) {
+      queue_push(a, o, v, nt, true);
+      return;
+    }
     const long long incl = wave_incl_scan(nt);
     const long long tot = __shfl(incl, 63, 64);
     unsigned long long base = 0;
@@ -539,12 +622,19 @@ __device__ __forceinline__ void edges_batch(const PeelArgs& a, WaveCtx& c, const
     for (int j = 0; j < U; ++j)
       if (((did >> j) & 1u) && (old[j] & SAMPLEBIT)) sample_hit(a, c, u[j]);
   }
+  if constexpr (!S && KCORE_CHECKS) {
 #pragma unroll
-  for (int j = 0; j < U; ++j) {
-    // (a sampled target's flag keeps its value above any k: not counted as a live decrement)
-    const uint32_t xo = old[j] & (S ? (DMASK & ~SAMPLEBIT) : DMASK);
-    if (((did >> j) & 1u) && xo > k && !(S && (old[j] & SAMPLEBIT))) c.live += 1;
-    if (!S && ((did >> j) & 1u)) check_decrement(xo, 1u, &a.ctl->status);
+    for (int j = 0; j < U; ++j)
+      if ((did >> j) & 1u) check_decrement(old[j] & DMASK, 1u, &a.ctl->status);
+  }
+  if constexpr (!S) {
+    if (c.hbs) {
+#pragma unroll
+      for (int j = 0; j < U; ++j) {
+        const uint32_t xo = old[j] & DMASK;
+        hbs_move(a, c, o, ((did >> j) & 1u) != 0u, u[j], xo, xo - 1u, k);
+      }
+    }
   }
 #pragma unroll
   for (int j = 0; j < U; ++j) {
@@ -649,6 +739,7 @@ __device__ __forceinline__ void comb_flush(const PeelArgs& a, WaveCtx& c, const 
     const int s = s0 + threadIdx.x;
     const int32_t u = c.ckey[s];
     bool crossed = false, hub = false;
+    uint32_t hxo = 0, hxn = 0;
     if (u >= 0) {
       const uint32_t cnt = c.ccnt[s];
       c.ckey[s] = -1;
@@ -656,7 +747,8 @@ __device__ __forceinline__ void comb_flush(const PeelArgs& a, WaveCtx& c, const 
       const uint32_t old = asub(&a.dt[u], cnt);
       c.decr += 1;
       const uint32_t ox = old & DMASK;
-      if (ox > k) c.live += min(cnt, ox - k);
+      hxo = ox;
+      hxn = ox - cnt;
       check_decrement(ox, cnt, &a.ctl->status);
       if (ox > k && ox - cnt <= k) {
         const uint32_t bit = 1u << (u & 15);
@@ -668,6 +760,7 @@ __device__ __forceinline__ void comb_flush(const PeelArgs& a, WaveCtx& c, const 
         }
       }
     }
+    if (c.hbs) hbs_move(a, c, o, u >= 0 && hxo >= hxn, u, hxo, hxn, k);
     push_vertices(a, c, o, crossed, u, hub);
   }
   __syncthreads();
@@ -861,6 +954,7 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
   __shared__ int s_bqc[8];
   __shared__ int s_apref[kMaxPeelBlocks + 1];  // segment prefix of the current active list
   __shared__ int s_anew;                        // survivors this workgroup appended in this phase
+  __shared__ long long s_hlen[kBucketSlots];    // entries in each bucket slot (multi-bucket mode)
 
   const int w = threadIdx.x >> 6;
   const int l = lane_id();
@@ -882,7 +976,10 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
   c.lq_head = 0;
   c.lq_cnt = 0;
   c.lq_used = 0;
-  c.edges = c.decr = c.scanned = c.peeled = c.comb = c.live = 0;
+  c.edges = c.decr = c.scanned = c.peeled = c.comb = c.binserts = 0;
+  c.hbs = false;
+  c.hlen = s_hlen;
+  if (threadIdx.x < kBucketSlots) s_hlen[threadIdx.x] = 0;
   c.mymin = 0xffffffffu;
   c.ckey = s_ckey;
   c.ccnt = s_ccnt;
@@ -893,6 +990,7 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
   c.bq = s_bq;
   c.bqc = s_bqc;
   c.bq_open = false;
+  c.steal = false;
   if (threadIdx.x == 0) s_anew = 0;
   c.adj = a.adj;
   c.rows = reinterpret_cast<const long long*>(a.off);
@@ -938,6 +1036,7 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
           }
         }
         ast(&a.dt[v], (uint32_t)d | (hub ? HUBBIT : 0u) | sbit);
+        if (a.hlo) ast(&a.hlo[v], 0u);  // filed nowhere yet
         bits |= (hot ? 1u : 0u) << (16 + j);
         mn = min(mn, (unsigned)d);
       }
@@ -982,6 +1081,11 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
   // called off for lack of room is tried again when half as many remain
   long long tail_limit = a.k_query > 0 ? -1 : a.tail_vmax;
   const long long max_phases = 4 * n + 64;
+  // multi-bucket active set: on from the round it starts at; hk = the round the buckets are
+  // relative to; hscan = the slot the current scan reads (-1: the active list, when it starts)
+  bool hbs_on = false;
+  uint32_t hk = 0;
+  int hscan = -1;
 
   for (long long p = 1;; ++p) {
     if (p > max_phases) {
@@ -1005,6 +1109,7 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
       ast(&r->bdone, 0u);
       ast(&r->minv, 0xffffffffu);
     }
+    if (blockIdx.x == 0 && threadIdx.x < kBucketSlots) ast(&C->slot[(p + 1) % 3].hadd[threadIdx.x], 0ull);
     const uint32_t k = (uint32_t)kx;
     const bool tr = blockIdx.x == 0 && threadIdx.x == 0 && p < kTracePhases;
     if (tr) C->trace[p][0] = wall_clock64();
@@ -1301,45 +1406,76 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
         c.rstride = 2;
         resid_limit = -1;
       } else {
-        resid_limit = asize / 2 > 0 ? asize / 2 : -1;
+        const long long aset = hbs_on ? n - total_peeled : asize;
+        resid_limit = aset / 2 > 0 ? aset / 2 : -1;
       }
       kind = PH_SCAN;
       continue;
     }
     c.lq_used = 0;
+    if (kind == PH_SCAN && a.hbs_vmax > 0) {
+      if (!hbs_on && kx >= (long long)kBucketMinK && n - total_peeled <= a.hbs_vmax) {
+        // the multi-bucket set starts: this scan files every live vertex of the active list
+        // (frozen from now on; the row rewrite and the tail handoff still read it, with the
+        // peeled bits telling which entries are live)
+        hbs_on = true;
+        hscan = -1;
+        hk = (uint32_t)kx;
+        compact = false;
+        if (threadIdx.x < kBucketSlots) s_hlen[threadIdx.x] = 0;
+        __syncthreads();
+      } else if (hbs_on && (uint32_t)kx != hk) {
+        // a new round: read the bucket that holds kx; the buckets below it held only values
+        // below kx (every such vertex is peeled) and start empty
+        hscan = hbs_bucket((uint32_t)kx, hk);
+        hk = (uint32_t)kx;
+        if (threadIdx.x < hscan) s_hlen[threadIdx.x] = 0;
+        __syncthreads();
+      }
+    }
+    c.hbs = hbs_on;
+    // the list a scan reads: the active list, or (multi-bucket mode) one bucket slot
+    const bool hb_list = kind == PH_SCAN && hbs_on && hscan >= 0;
+    // (a slot that overflowed has already stopped the run at the barrier; never read past it)
+    const long long slen = hb_list ? min(s_hlen[hscan], (long long)a.hcap) : asize;
     // large phases are bandwidth bound: probe peeled bits and combine hub decrements; small ones
     // are latency bound: skip the probe and spread the frontier over as many waves as possible
-    c.precheck = kind == PH_SCAN ? asize >= a.big_phase * 16 : (fs + ft * (a.tile / 16)) >= a.big_phase;
+    c.precheck = kind == PH_SCAN ? slen >= a.big_phase * 16 : (fs + ft * (a.tile / 16)) >= a.big_phase;
     // chained mode folds the round's whole peel into its scan phase once the active set is small
-    const bool async_scan = kind == PH_SCAN && a.chained && asize <= a.async_scan_max;
+    const bool async_scan = kind == PH_SCAN && a.chained && !hbs_on && asize <= a.async_scan_max;
     // deferred (combined) decrements would hide work from the async quiescence test
     c.async = kind == PH_ASYNC || async_scan;
     c.combine = c.precheck && !c.async;
     c.arbitrate = kind == PH_SCAN && a.chained;
     c.bq_open = a.chained && a.bq_max_tiles > 0 && !c.async;
+    c.steal = c.bq_open && kind == PH_SCAN && a.steal_backlog > 0;
     if (tr) {
       C->trace[p][4] = (unsigned long long)kind | (c.precheck ? 16ull : 0ull) | (c.async ? 32ull : 0ull) |
                        ((unsigned long long)k << 8);
       C->trace[p][5] = (unsigned long long)fs;
       C->trace[p][6] = (unsigned long long)ft;
-      C->trace[p][7] = (unsigned long long)asize;
+      C->trace[p][7] = (unsigned long long)slen;
     }
     long long peeled_before = c.peeled;
     if (kind == PH_SCAN) {
-      // Alg. 1: F = {v in A : induced degree <= k}; survivors refine A.
+      // Alg. 1: F = {v in A : induced degree <= k}; survivors refine A (or, in multi-bucket
+      // mode, move to the bucket of their induced degree: GetNextBucket of Sec. 5.2).
       int32_t* alist = a.act[acur];
+      const int32_t* hlist = hb_list ? a.hbl + (long long)hscan * a.hcap : nullptr;
       // this workgroup's segment of the next list: at most the items it scans (64-entry chunks
       // dealt round-robin over workgroups)
       const long long nseg = 64 * (((asize + 63) / 64 + nb - 1) / nb);
       int32_t* myseg = a.act[acur ^ 1] + (long long)blockIdx.x * nseg;
-      for (long long i0 = gw * 64; i0 < asize; i0 += W * 64) {
+      for (long long i0 = gw * 64; i0 < slen; i0 += W * 64) {
         const long long i = i0 + l;
-        const bool valid = i < asize;
+        const bool valid = i < slen;
         int32_t v = -1;
-        if (valid) v = active_item(alist, dense, i, aseg, s_apref, nb);
-        uint32_t word = 0, x = 0;
+        if (valid) v = hb_list ? ald(&hlist[i]) : active_item(alist, dense, i, aseg, s_apref, nb);
+        uint32_t word = 0, x = 0, tag = 0;
         bool alive = false;
         if (valid) {
+          // (multi-bucket mode: the tag is read before the induced degree, see hbs_file)
+          if (hbs_on) tag = ald(&a.hlo[v]);
           // liveness comes from the peeled bit, not from the induced degree: in chained mode a
           // chain of this round may already have taken a vertex due for extraction below k
           const uint32_t sw = ald(&a.state[v >> 4]);
@@ -1352,6 +1488,7 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
         const bool keep = alive && (long long)x > kx;
         if (keep) c.mymin = min(c.mymin, x);
         if (compact) seg_push(c.sa, keep, v, myseg, &s_anew);
+        if (hbs_on) hbs_file(a, c, o, keep, v, x, tag, (uint32_t)kx);
         if (ext) {
           const uint32_t bit = 1u << (v & 15);
           if (aor(&a.state[v >> 4], bit) & bit) {
@@ -1388,6 +1525,9 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
       block_loop<S>(a, c, o, k);
       c.bq_open = false;
     }
+    // work stealing: what the workgroup queues refused is drained by everyone, as in an
+    // asynchronous phase (pushes made meanwhile go to the shared queue too)
+    if (c.steal) c.async = true;
     if (c.async) {
       if (threadIdx.x == 0) s_quiet = 0;
       __syncthreads();
@@ -1399,6 +1539,9 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
       // shared counter, so thousands of claimers would serialise there
       if ((threadIdx.x >> 6) < kAsyncWaves) async_loop<S>(a, c, o, k, &s_quiet);
     }
+    // (after quiescence nothing may be added to the shared queue: the combined decrements below
+    // push to the next phase)
+    if (c.steal) c.async = false;
     comb_flush(a, c, o, k);
     // every wave has left the tile queue (comb_flush starts with a workgroup barrier): reset it for
     // the next phase; the barriers of the flushes below order this before its next use
@@ -1471,6 +1614,14 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
     const unsigned mv = (unsigned)s_out[3];
     const long long npeel = s_out[4];
     const long long valk = S ? s_out[5] : (long long)0xffffffffu;  // next validation (sampling)
+    if (hbs_on) {
+      // bucket lengths after the phase (the same in every workgroup); a scanned slot has been
+      // redistributed into lower ones and is empty
+      if (threadIdx.x < kBucketSlots) {
+        s_hlen[threadIdx.x] += (long long)ald(&o.slot->hadd[threadIdx.x]);
+        if (hb_list && (int)threadIdx.x == hscan) s_hlen[threadIdx.x] = 0;
+      }
+    }
     __syncthreads();
     if (nfs > a.fcap || nft > a.tcap || nact > n) {
       // a list overflowed (its entries were not written): stop before reading them
@@ -1519,10 +1670,20 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
       } else if (npeel > 0) {
         // the round completed inside the scan (chained mode)
         kx = kx + 1;
-        compact = removed_since * 8 >= asize;
+        compact = !hbs_on && removed_since * 8 >= asize;
       } else {
         // no live vertex has induced degree <= kx: jump to the smallest one (next non-empty round)
-        if (mv == 0xffffffffu) {
+        long long jump = (long long)mv;
+        if (hbs_on && mv == 0xffffffffu) {
+          // nothing live in the bucket just read: the next round starts at the lowest range that
+          // still lists vertices (its entries may all be stale: its scan then moves on again)
+          for (int b = 0; b < kBucketSlots; ++b)
+            if (s_hlen[b] > 0) {
+              jump = (long long)hbs_lo(hk, b);
+              break;
+            }
+        }
+        if (jump == 0xffffffffll) {
           if (threadIdx.x == 0) aor(&C->status, (unsigned)KC_ERR_PHASES);
           if (blockIdx.x == 0 && threadIdx.x == 0) {
             ast(&C->stats[kDiagWord], (unsigned long long)total_peeled);
@@ -1533,7 +1694,7 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
           break;
         }
         // (in sampling mode not past the next validation)
-        kx = S ? min((long long)mv, max(valk, kx + 1)) : (long long)mv;
+        kx = S ? min(jump, max(valk, kx + 1)) : jump;
         compact = false;
       }
     } else {
@@ -1546,7 +1707,7 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
       } else {
         kx = kx + 1;
         kind = PH_SCAN;
-        compact = removed_since * 8 >= asize;
+        compact = !hbs_on && removed_since * 8 >= asize;
       }
     }
     // a k-core query ends with its one round: the survivors are the k-core
@@ -1557,7 +1718,7 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
     // small active set whose live rows fit: rewrite the rows once
     if (kind == PH_SCAN && tail_limit > 0 && n - total_peeled <= tail_limit)
       kind = PH_TAIL;
-    else if (kind == PH_SCAN && resid_limit >= 0 && asize <= resid_limit)
+    else if (kind == PH_SCAN && resid_limit >= 0 && (hbs_on ? n - total_peeled : asize) <= resid_limit)
       kind = PH_RESIDUAL;
   }
   if (a.k_query > 0) {
@@ -1569,7 +1730,7 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
 
   // ---- statistics: per-lane counters reduced per block, one atomic each per block
   {
-    long long v4[6] = {c.edges, c.decr, c.scanned, c.peeled, c.comb, c.live};
+    long long v4[6] = {c.edges, c.decr, c.scanned, c.peeled, c.comb, c.binserts};
     for (int q = 0; q < 6; ++q) {
       long long x = v4[q];
       for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
@@ -1579,7 +1740,7 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
         long long t = 0;
         for (int i = 0; i < kWaves; ++i) t += s_red64[i];
         const int idx = q == 0 ? ST_EDGES : q == 1 ? ST_DECR : q == 2 ? ST_SCANNED : q == 3 ? ST_PEELED
-                      : q == 4 ? ST_COMBINED : ST_LIVE;
+                      : q == 4 ? ST_COMBINED : ST_BUCKET;
         if (t) aadd(&C->stats[idx], (unsigned long long)t);
       }
       __syncthreads();
@@ -1663,7 +1824,7 @@ __device__ __forceinline__ void team_push(bool p, int32_t v, QT* q, int* s_tail)
 __device__ __forceinline__ bool batch_chain(const BatchArgs& a, uint32_t* d, int32_t* q, uint32_t* pb,
                                             const int64_t* off, int64_t base, bool inl, uint32_t k,
                                             int* s_claim, int* s_tail, int* s_busy, long long& st_edges,
-                                            long long& st_decr, long long& st_live) {
+                                            long long& st_decr) {
   const int l = lane_id();
   const unsigned long long t_start = wall_clock64();
   for (;;) {
@@ -1746,7 +1907,6 @@ __device__ __forceinline__ bool batch_chain(const BatchArgs& a, uint32_t* d, int
         if (live) {
           const unsigned old = inl ? atomicSub(&d[ul], 1u) : wsub(&d[ul], 1u);
           st_decr++;
-          st_live += old > k ? 1 : 0;
           check_decrement(old, 1u, &a.ctl->status);
           crossed = old == k + 1;
         }
@@ -1766,6 +1926,179 @@ __device__ __forceinline__ bool batch_chain(const BatchArgs& a, uint32_t* d, int
   }
 }
 
+// ------------------------------------------------------------------------------------------
+// Teams: a graph too large for one workgroup's share of the batch is peeled by kTeamSize
+// workgroups together (the launch is cooperative, so they are all resident). Induced degrees and
+// the peel queue live in global memory at the graph's own vertex range; decrements are agent-scope
+// atomics, and the team synchronises at every round scan and subround with a counter barrier
+// (fence-free, as the grid barrier of the single-graph peel). Level-synchronous Alg. 1 + Alg. 3:
+// a round's scan reads every vertex (x == k: extract; x > k: min for a jump; x < k: peeled), each
+// subround splits the frontier into one contiguous share per member, expanded edge-balanced over
+// the member's threads.
+// ------------------------------------------------------------------------------------------
+// Team barrier. The last arrival records the queue tail (every push of the phase has landed: each
+// member waited for its memory operations before arriving) and then releases the team, so all
+// members see the same tail even though the fastest may start pushing again at once. Waits are
+// bounded (~4 s, or any failure bit set). Returns false when the team must stop; `tail` receives
+// the recorded tail.
+__device__ bool team_sync(TeamCtl* T, unsigned size, unsigned& epoch, unsigned* status, long long& tail) {
+  __shared__ int s_tok;
+  __shared__ long long s_tail;
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned target = epoch + 1;
+    int ok = 1;
+    if (aadd(&T->bar, 1u) == target * size - 1) {
+      ast(&T->snap[epoch & 1], ald(&T->tail));
+      __builtin_amdgcn_s_waitcnt(0);
+      ast(&T->gen, target);
+    } else {
+      const unsigned long long t0 = wall_clock64();
+      while (ald(&T->gen) < target) {
+        __builtin_amdgcn_s_sleep(1);
+        if (wall_clock64() - t0 > 400000000ull) {  // 100 MHz clock: 4 s
+          aor(status, (unsigned)KC_ERR_TIMEOUT);
+          ok = 0;
+          break;
+        }
+      }
+    }
+    if (ald(status) != 0u) ok = 0;
+    s_tok = ok;
+    s_tail = (long long)ald(&T->snap[epoch & 1]);
+  }
+  __syncthreads();
+  epoch += 1;
+  tail = s_tail;
+  return s_tok != 0;
+}
+
+__device__ __forceinline__ void team_push(bool p, int32_t v, int32_t* q, unsigned long long* tail) {
+  const unsigned long long m = __ballot(p);
+  if (!m) return;
+  unsigned long long b = 0;
+  if (lane_id() == 0) b = aadd(tail, (unsigned long long)__popcll(m));
+  b = __shfl(b, 0, 64);
+  if (p) ast(&q[b + rank_in(m)], v);
+}
+
+__device__ __forceinline__ void team_peel(const BatchArgs& a, int team, int member, long long* s_pref, long long* s_rb,
+                                       long long* s_w, unsigned* s_min, long long& st_edges, long long& st_decr,
+                                       long long& st_rounds, long long& st_sub, long long& st_scanned,
+                                       unsigned& kmax_all) {
+  TeamCtl* T = &a.ctl->team[team];
+  unsigned* status = &a.ctl->status;
+  const int32_t g = a.order[team];
+  const int64_t base = a.vptr[g];
+  const int64_t ng = a.vptr[g + 1] - base;
+  const int64_t* off = a.off + base;
+  uint32_t* d = a.gdt + base;
+  int32_t* q = a.gq + base;
+  const int tid = threadIdx.x, l = lane_id(), w = threadIdx.x >> 6;
+  const long long gtid = (long long)member * kBatchThreads + tid;
+  const long long GT = (long long)kTeamSize * kBatchThreads;
+  unsigned epoch = 0;
+  const bool lead = member == 0;
+
+  // induced degree = degree; k = min degree
+  unsigned mn = 0xffffffffu;
+  for (long long i = gtid; i < ng; i += GT) {
+    const unsigned dg = (unsigned)(off[i + 1] - off[i]);
+    ast(&d[i], dg);
+    mn = min(mn, dg);
+  }
+  mn = wave_min(mn);
+  if (l == 0) s_min[w] = mn;
+  __syncthreads();
+  if (tid == 0) {
+    unsigned m = 0xffffffffu;
+    for (int i = 0; i < kBatchThreads / 64; ++i) m = min(m, s_min[i]);
+    if (m != 0xffffffffu) __hip_atomic_fetch_max(&T->rmx[2], ~m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  long long tail = 0;
+  if (!team_sync(T, kTeamSize, epoch, status, tail)) return;
+  unsigned k = ~ald(&T->rmx[2]);
+  long long head = 0;
+  for (long long r = 0;; ++r) {
+    unsigned* rmx = &T->rmx[r % 3];
+    if (lead && tid == 0) ast(&T->rmx[(r + 1) % 3], 0u);  // (last read two rounds ago)
+    // the round's first frontier, and the min over the others
+    unsigned nm = 0xffffffffu;
+    for (long long i = gtid; i < ng; i += GT) {
+      const unsigned x = ald(&d[i]);
+      st_scanned++;
+      const bool ext = x == k;
+      if (x > k) nm = min(nm, x);
+      if (ext) put_core(a.core, base + i, k, status);
+      team_push(ext, (int32_t)i, q, &T->tail);
+    }
+    nm = wave_min(nm);
+    if (l == 0) s_min[w] = nm;
+    __syncthreads();
+    if (tid == 0) {
+      unsigned m = 0xffffffffu;
+      for (int i = 0; i < kBatchThreads / 64; ++i) m = min(m, s_min[i]);
+      if (m != 0xffffffffu) __hip_atomic_fetch_max(rmx, ~m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (!team_sync(T, kTeamSize, epoch, status, tail)) return;
+    if (tail == head) {
+      const unsigned mv = ~ald(rmx);
+      if (mv == 0xffffffffu || tail >= ng) return;  // (nothing live: cannot happen before tail == ng)
+      k = mv;
+      continue;
+    }
+    if (lead) st_rounds++;
+    kmax_all = max(kmax_all, k);
+    while (head < tail) {
+      if (lead) st_sub++;
+      const long long c0 = head + (tail - head) * member / kTeamSize;
+      const long long c1 = head + (tail - head) * (member + 1) / kTeamSize;
+      for (long long cb = c0; cb < c1; cb += kBatchThreads) {
+        const long long i = cb + tid;
+        long long dg = 0, rb = 0;
+        if (i < c1) {
+          const int32_t v = ald(&q[i]);
+          rb = off[v];
+          dg = off[v + 1] - rb;
+        }
+        long long total;
+        const long long ex = block_excl_scan(dg, s_w, total);
+        s_pref[tid] = ex;
+        s_rb[tid] = rb;
+        __syncthreads();
+        for (long long e0 = 0; e0 < total; e0 += kBatchThreads) {
+          const long long t = e0 + tid;
+          bool crossed = false;
+          int32_t ul = 0;
+          if (t < total) {
+            int lo = 0, hi = kBatchThreads - 1;  // largest j with s_pref[j] <= t
+            while (lo < hi) {
+              const int mid = (lo + hi + 1) >> 1;
+              if (s_pref[mid] <= t) lo = mid; else hi = mid - 1;
+            }
+            ul = a.adj[s_rb[lo] + (t - s_pref[lo])] - (a.local_ids ? 0 : (int32_t)base);
+            st_edges++;
+            if (ald(&d[ul]) > k) {
+              const unsigned old = asub(&d[ul], 1u);
+              st_decr++;
+              check_decrement(old, 1u, status);
+              crossed = old == k + 1;
+            }
+          }
+          if (crossed) put_core(a.core, base + ul, k, status);
+          team_push(crossed, ul, q, &T->tail);
+        }
+        __syncthreads();
+      }
+      head = tail;
+      if (!team_sync(T, kTeamSize, epoch, status, tail)) return;
+    }
+    if (tail >= ng) return;
+    k = k + 1;
+  }
+}
+
 __global__ __launch_bounds__(kBatchThreads) void batched_kernel(BatchArgs a) {
   extern __shared__ uint32_t s_dyn[];
   __shared__ long long s_pref[kBatchThreads];
@@ -1776,12 +2109,17 @@ __global__ __launch_bounds__(kBatchThreads) void batched_kernel(BatchArgs a) {
   __shared__ int s_claim, s_busy;
   __shared__ long long s_g;
 
-  long long st_edges = 0, st_decr = 0, st_rounds = 0, st_sub = 0, st_scanned = 0, st_live = 0;
+  long long st_edges = 0, st_decr = 0, st_rounds = 0, st_sub = 0, st_scanned = 0;
   unsigned kmax_all = 0;
   const int tid = threadIdx.x, l = lane_id(), w = threadIdx.x >> 6;
+  // the leading nteams graphs of the order are peeled by teams of the first workgroups
+  const int nteams = a.teams ? (int)a.ctl->nteams : 0;
+  if ((int)blockIdx.x < nteams * kTeamSize)
+    team_peel(a, blockIdx.x / kTeamSize, blockIdx.x % kTeamSize, s_pref, s_rb, s_w, s_min, st_edges, st_decr,
+              st_rounds, st_sub, st_scanned, kmax_all);
 
   for (;;) {
-    if (tid == 0) s_g = (long long)aadd(&a.ctl->next, 1ull);
+    if (tid == 0) s_g = (long long)aadd(&a.ctl->next, 1ull) + nteams;
     __syncthreads();
     const long long gi = s_g;
     __syncthreads();
@@ -1894,7 +2232,7 @@ __global__ __launch_bounds__(kBatchThreads) void batched_kernel(BatchArgs a) {
           s_busy = kBatchThreads / 64;
         }
         __syncthreads();
-        if (!batch_chain(a, d, q, pb, off, base, inl, k, &s_claim, &s_tail, &s_busy, st_edges, st_decr, st_live) &&
+        if (!batch_chain(a, d, q, pb, off, base, inl, k, &s_claim, &s_tail, &s_busy, st_edges, st_decr) &&
             l == 0)
           aor(&a.ctl->status, (unsigned)KC_ERR_TIMEOUT);
         __syncthreads();
@@ -1935,7 +2273,6 @@ __global__ __launch_bounds__(kBatchThreads) void batched_kernel(BatchArgs a) {
               if (live) {
                 const unsigned old = inl ? atomicSub(&d[ul], 1u) : wsub(&d[ul], 1u);
                 st_decr++;
-                st_live += old > k ? 1 : 0;
                 check_decrement(old, 1u, &a.ctl->status);
                 crossed = old == k + 1;
               }
@@ -1956,13 +2293,11 @@ __global__ __launch_bounds__(kBatchThreads) void batched_kernel(BatchArgs a) {
     __syncthreads();
   }
   // statistics
-  long long v5[4] = {st_edges, st_decr, st_scanned, st_live};
-  for (int qd = 0; qd < 4; ++qd) {
+  long long v5[3] = {st_edges, st_decr, st_scanned};
+  for (int qd = 0; qd < 3; ++qd) {
     long long x = v5[qd];
     for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-    if (l == 0 && x)
-      aadd(&a.ctl->stats[qd == 0 ? ST_EDGES : qd == 1 ? ST_DECR : qd == 2 ? ST_SCANNED : ST_LIVE],
-           (unsigned long long)x);
+    if (l == 0 && x) aadd(&a.ctl->stats[qd == 0 ? ST_EDGES : qd == 1 ? ST_DECR : ST_SCANNED], (unsigned long long)x);
   }
   if (tid == 0) {
     if (st_rounds) aadd(&a.ctl->stats[ST_ROUNDS], (unsigned long long)st_rounds);
@@ -1974,6 +2309,42 @@ __global__ __launch_bounds__(kBatchThreads) void batched_kernel(BatchArgs a) {
 
 hipError_t launch_batched(const BatchArgs& a, int blocks, size_t lds_bytes, hipStream_t s) {
   hipLaunchKernelGGL(batched_kernel, dim3(blocks), dim3(kBatchThreads), lds_bytes, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_batched_coop(const BatchArgs& a, int blocks, size_t lds_bytes, hipStream_t s) {
+  void* args[] = {const_cast<BatchArgs*>(&a)};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(batched_kernel), dim3(blocks), dim3(kBatchThreads),
+                                    args, (unsigned)lds_bytes, s);
+}
+
+// Team plan: the leading graphs of the order (largest first by power of two of their entries)
+// with more entries than min_entries (default: half a workgroup's average share of the batch; every
+// leading graph when `all`) get a team; at most kMaxTeams, and at most team_wgs workgroups in teams.
+// One workgroup peels a graph held in global memory several times slower per entry than the
+// LDS-resident small graphs that make up most of a batch, hence the low default threshold.
+__global__ __launch_bounds__(64) void team_plan_kernel(const int64_t* vptr, const int64_t* off, int32_t G,
+                                                       const int32_t* order, int32_t blocks, int32_t team_wgs,
+                                                       int32_t all, long long min_entries, BatchCtl* ctl) {
+  if (threadIdx.x != 0) return;
+  const long long total = off[vptr[G]] - off[vptr[0]];
+  const long long share = total / (blocks > 0 ? blocks : 1);
+  const long long thr = min_entries > 0 ? min_entries : share / 2;
+  int nt = 0;
+  while (nt < kMaxTeams && nt < G && (nt + 1) * kTeamSize <= team_wgs) {
+    const int32_t g = order[nt];
+    const long long e = off[vptr[g + 1]] - off[vptr[g]];
+    if (!all && e <= thr) break;
+    ++nt;
+  }
+  ctl->nteams = (unsigned)nt;
+}
+
+hipError_t launch_team_plan(const int64_t* vptr, const int64_t* off, int32_t G, const int32_t* order,
+                            int32_t blocks, int32_t team_wgs, int32_t all, int64_t min_entries, BatchCtl* ctl,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(team_plan_kernel, dim3(1), dim3(64), 0, s, vptr, off, G, order, blocks, team_wgs, all,
+                     (long long)min_entries, ctl);
   return hipGetLastError();
 }
 
@@ -2000,7 +2371,7 @@ hipError_t batched_occupancy(size_t lds_bytes, int* blocks_per_cu) {
 // the batch is issued before any result is looked at. All lanes of the wavefront call.
 template <int N>
 __device__ __forceinline__ void tail_edges(const PeelArgs& a, uint32_t* d, uint16_t* q, int* s_tail, int L,
-                                           const int32_t (&u)[N], uint32_t k, long long& live) {
+                                           const int32_t (&u)[N], uint32_t k) {
   uint32_t old[N];
 #pragma unroll
   for (int j = 0; j < N; ++j) old[j] = atomicSub(&d[u[j]], 1u);
@@ -2008,8 +2379,7 @@ __device__ __forceinline__ void tail_edges(const PeelArgs& a, uint32_t* d, uint1
 #pragma unroll
   for (int j = 0; j < N; ++j) {
     cm |= (old[j] == k + 1 ? 1u : 0u) << j;
-    live += (u[j] < L && old[j] > k) ? 1 : 0;
-    if (u[j] < L) check_decrement(old[j], 1u, &a.ctl->status);
+    if (KCORE_CHECKS && u[j] < L) check_decrement(old[j], 1u, &a.ctl->status);
   }
   if (!__ballot(cm != 0)) return;
 #pragma unroll
@@ -2030,8 +2400,7 @@ __device__ __forceinline__ void tail_edges(const PeelArgs& a, uint32_t* d, uint1
 // the lane's spare slot. Ids are unpacked where they are used, so the packed words are all that
 // stays live. All lanes of the wavefront call.
 __device__ __forceinline__ void tail_edges16(const PeelArgs& a, uint32_t* d, uint16_t* q, int* s_tail, int L,
-                                             const uint32_t (&w)[8], const int (&lim)[2], uint32_t k,
-                                             long long& live) {
+                                             const uint32_t (&w)[8], const int (&lim)[2], uint32_t k) {
   const int spare = L + lane_id();
   uint32_t old[16];
 #pragma unroll
@@ -2043,8 +2412,7 @@ __device__ __forceinline__ void tail_edges16(const PeelArgs& a, uint32_t* d, uin
 #pragma unroll
   for (int e = 0; e < 16; ++e) {
     cm |= (old[e] == k + 1 ? 1u : 0u) << e;
-    live += ((e & 7) < lim[e >> 3] && old[e] > k) ? 1 : 0;
-    if ((e & 7) < lim[e >> 3]) check_decrement(old[e], 1u, &a.ctl->status);
+    if (KCORE_CHECKS && (e & 7) < lim[e >> 3]) check_decrement(old[e], 1u, &a.ctl->status);
   }
   if (!__ballot(cm != 0)) return;
 #pragma unroll
@@ -2066,7 +2434,7 @@ __device__ __forceinline__ void tail_edges16(const PeelArgs& a, uint32_t* d, uin
 // 16-byte boundary; rows are padded to whole 16-byte words); the decrements go in two halves of
 // 16 entries per lane. All lanes call with the same range.
 __device__ __forceinline__ void tail_tile(const PeelArgs& a, uint32_t* d, uint16_t* q, int* s_tail, int L, int tb,
-                                          int len, uint32_t k, long long& live) {
+                                          int len, uint32_t k) {
   static_assert(kTailTile == 2048, "four 16-byte loads of 8 entries per lane");
   const int l = lane_id();
   uint4 x[4];
@@ -2080,7 +2448,7 @@ __device__ __forceinline__ void tail_tile(const PeelArgs& a, uint32_t* d, uint16
     const uint32_t w[8] = {x[2 * h].x, x[2 * h].y, x[2 * h].z, x[2 * h].w,
                            x[2 * h + 1].x, x[2 * h + 1].y, x[2 * h + 1].z, x[2 * h + 1].w};
     const int lim[2] = {len - (1024 * h + 8 * l), len - (1024 * h + 512 + 8 * l)};
-    tail_edges16(a, d, q, s_tail, L, w, lim, k, live);
+    tail_edges16(a, d, q, s_tail, L, w, lim, k);
   }
 }
 
@@ -2092,8 +2460,7 @@ __device__ __forceinline__ void tail_tile(const PeelArgs& a, uint32_t* d, uint16
 // are written, so a claimed slot is read once it is no longer -1. False on a timeout. All threads
 // call.
 __device__ __forceinline__ bool tail_chain(const PeelArgs& a, uint32_t* d, uint16_t* q, int L, uint32_t k,
-                                           int* s_claim, int* s_tail, int* s_busy, long long& st_edges,
-                                           long long& st_live) {
+                                           int* s_claim, int* s_tail, int* s_busy, long long& st_edges) {
   constexpr int nw = kTailThreads / 64;
   const int l = lane_id();
   const unsigned long long t_start = wall_clock64();
@@ -2175,7 +2542,7 @@ __device__ __forceinline__ bool tail_chain(const PeelArgs& a, uint32_t* d, uint1
       if (l == 0) full = lds_ld(s_tail) >= L;
       if (__shfl(full, 0, 64)) continue;  // (as above, row by row)
       for (int o = 0; o < len; o += kTailTile)
-        tail_tile(a, d, q, s_tail, L, rs + o, min(len - o, kTailTile), k, st_live);
+        tail_tile(a, d, q, s_tail, L, rs + o, min(len - o, kTailTile), k);
     }
     const int sd = dg >= kTailBig ? 0 : dg;
     const int incl = wave_incl_scan(sd);
@@ -2199,7 +2566,7 @@ __device__ __forceinline__ bool tail_chain(const PeelArgs& a, uint32_t* d, uint1
         const int pos = __shfl(rb, j, 64) + (t - __shfl(excl, j, 64));
         u[r] = t < total ? (int32_t)a.tadj[pos] : L + l;
       }
-      tail_edges(a, d, q, s_tail, L, u, k, st_live);
+      tail_edges(a, d, q, s_tail, L, u, k);
     }
   }
 }
@@ -2256,7 +2623,7 @@ __global__ __launch_bounds__(kTailThreads) void tail_kernel(PeelArgs a, int32_t 
   // frontier extracted, round peeled; then k, first frontier size, vertices peeled so far
   unsigned long long* trc = nullptr;
   int ntr = 0;
-  long long st_edges = 0, st_scanned = 0, st_rounds = 0, st_sub = 0, st_live = 0;
+  long long st_edges = 0, st_scanned = 0, st_rounds = 0, st_sub = 0;
 
   // induced degree = length of the local row (its live neighbours); k = the smallest
   unsigned mn = 0xffffffffu;
@@ -2323,7 +2690,7 @@ __global__ __launch_bounds__(kTailThreads) void tail_kernel(PeelArgs a, int32_t 
         s_busy = kTailThreads / 64;
       }
       __syncthreads();
-      if (!tail_chain(a, d, q, L, k, &s_claim, &s_tail, &s_busy, st_edges, st_live) && l == 0)
+      if (!tail_chain(a, d, q, L, k, &s_claim, &s_tail, &s_busy, st_edges) && l == 0)
         aor(&a.ctl->status, (unsigned)KC_ERR_TIMEOUT);
       __syncthreads();
       st_sub++;
@@ -2370,7 +2737,7 @@ __global__ __launch_bounds__(kTailThreads) void tail_kernel(PeelArgs a, int32_t 
               u[r] = (int32_t)a.tadj[s_rb[lo] + (t - s_pref[lo])];
             }
           }
-          tail_edges(a, d, q, &s_tail, L, u, k, st_live);
+          tail_edges(a, d, q, &s_tail, L, u, k);
         }
         for (int tt = w; !full && tt < tiles; tt += kTailThreads / 64) {
           int lo = 0, hi = kTailThreads - 1;  // largest j with s_tpref[j] <= tt (wave-uniform)
@@ -2380,7 +2747,7 @@ __global__ __launch_bounds__(kTailThreads) void tail_kernel(PeelArgs a, int32_t 
           }
           // the row starts on a 16-byte boundary and is padded to whole 16-byte words
           const int o = (tt - s_tpref[lo]) * kTailTile;
-          tail_tile(a, d, q, &s_tail, L, s_rb[lo] + o, min(s_len[lo] - o, kTailTile), k, st_live);
+          tail_tile(a, d, q, &s_tail, L, s_rb[lo] + o, min(s_len[lo] - o, kTailTile), k);
         }
         __syncthreads();
       }
@@ -2398,11 +2765,11 @@ __global__ __launch_bounds__(kTailThreads) void tail_kernel(PeelArgs a, int32_t 
   }
   // statistics: the tail's share of the decomposition's counters (its decrements are LDS
   // operations, not counted with the global ones)
-  long long v5[3] = {st_edges, st_scanned, st_live};
-  for (int qd = 0; qd < 3; ++qd) {
+  long long v5[2] = {st_edges, st_scanned};
+  for (int qd = 0; qd < 2; ++qd) {
     long long x = v5[qd];
     for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-    if (l == 0 && x) aadd(&a.ctl->stats[qd == 0 ? ST_EDGES : qd == 1 ? ST_SCANNED : ST_LIVE], (unsigned long long)x);
+    if (l == 0 && x) aadd(&a.ctl->stats[qd == 0 ? ST_EDGES : ST_SCANNED], (unsigned long long)x);
   }
   if (tid == 0) {
     aadd(&a.ctl->stats[ST_PEELED], (unsigned long long)L);
@@ -2466,6 +2833,36 @@ __global__ __launch_bounds__(1024) void order_kernel(const int64_t* vptr, const 
 hipError_t launch_order(const int64_t* vptr, const int64_t* off, int32_t G, int32_t* order,
                         hipStream_t s) {
   hipLaunchKernelGGL(order_kernel, dim3(1), dim3(1024), 0, s, vptr, off, G, order);
+  return hipGetLastError();
+}
+
+// Live decrements of a finished decomposition: a vertex receives exactly deg(v) - coreness(v)
+// decrements while its induced degree is above the round's k (those taking it from deg(v) down to
+// k, whatever the order), so their total is offsets[n] - sum of coreness. Adds that to *out.
+__global__ __launch_bounds__(1024) void live_count_kernel(const int64_t* off, const int32_t* core, int64_t n,
+                                                          unsigned long long* out) {
+  __shared__ long long s_w[16];
+  long long acc = 0;
+  for (long long v = blockIdx.x * 1024ll + threadIdx.x; v < n; v += (long long)gridDim.x * 1024)
+    acc += core[v];
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if (lane_id() == 0) s_w[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long t = 0;
+    for (int i = 0; i < 16; ++i) t += s_w[i];
+    if (blockIdx.x == 0) t = off[n] - off[0] - t;
+    else t = -t;
+    aadd(out, (unsigned long long)t);
+  }
+}
+
+hipError_t launch_live_count(const int64_t* off, const int32_t* core, int64_t n, unsigned long long* out,
+                             hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  long long blocks = (n + 1023) / 1024;
+  if (blocks > 1024) blocks = 1024;
+  hipLaunchKernelGGL(live_count_kernel, dim3((unsigned)blocks), dim3(1024), 0, s, off, core, n, out);
   return hipGetLastError();
 }
 

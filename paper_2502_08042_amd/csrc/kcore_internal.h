@@ -28,9 +28,11 @@ constexpr int kTailUnroll = 4;        //   short rows: adjacency entries in flig
 constexpr int kTailBig = 256;         //   rows at least this long are streamed in tiles ...
 constexpr int kTailTile = 2048;       //   ... of this many entries (4 16-byte loads of 8 ids per lane)
 constexpr uint16_t kTailQEmpty = 0xffffu;  // unwritten slot of the tail's 16-bit queue (ids < 65,535)
+constexpr int kBucketSlots = 32;      // multi-bucket active set: one slot per bit of an induced degree
+constexpr uint32_t kBucketMinK = 16;  //   kept from the first round with k >= 16 (Sec. 5.2's threshold)
 
-// ST_LIVE: decrement units that landed on a vertex still above k (one per peeled vertex and live
-// neighbour; a combined count of c on a vertex at d > k contributes min(c, d - k)).
+// ST_LIVE: decrements that landed on a vertex still above k (one per peeled vertex and live
+// neighbour), computed after the run as offsets[n] - sum of coreness.
 // ST_BUCKET: insertions into the multi-bucket active set (placements and moves).
 enum StatIdx {
   ST_ROUNDS = 0, ST_SUBROUNDS, ST_BARRIERS, ST_PEELED, ST_EDGES, ST_DECR, ST_COMBINED, ST_SCANNED,
@@ -52,6 +54,7 @@ struct alignas(128) PhaseSlot {
   unsigned int bdone;         //   workgroups done with their static share
   unsigned int minv;          // min induced degree over vertices kept by a scan
   unsigned int pad[6];
+  unsigned long long hadd[kBucketSlots];  // entries appended to each bucket slot in the phase
 };
 
 struct alignas(128) PeelCtl {
@@ -117,6 +120,8 @@ struct PeelArgs {
   int64_t async_scan_max; // chained mode: active sets up to this size scan and peel in one phase
   int32_t bq_max_tiles;   // chained mode: hubs of at most this many tiles stay in the workgroup (0 = off)
   int32_t bq_backlog;     //   while at most this many tiles wait unclaimed in the workgroup's queue
+  int32_t steal_backlog;  // chained scan phases: > 0 = tiles beyond this backlog go to the shared
+                          // queue that all workgroups drain (0 = off)
   int64_t dbg_lo;         // first phase of the per-workgroup debug record (-1 = none)
   int32_t tile_probe_always; // hub tiles probe peeled bits in every phase (else in large ones only)
   long long* rrow;        // residual rows: [2v] first entry, [2v + 1] end, in radj
@@ -133,6 +138,16 @@ struct PeelArgs {
   long long* trow;
   uint16_t* tadj;         // 16-bit local ids (the tail holds fewer than 65,535 vertices)
   int64_t tail_ecap;      // entries tadj holds
+  // multi-bucket active set (Sec. 5.2): slot b holds the vertices whose induced degree x > k has
+  // its highest bit differing from k at bit b, entries [b * hcap, b * hcap + length) of hbl;
+  // hlo[v] is the lower bound of the range v was last filed into (0 = none), hslots the slots in
+  // use (values below 2^hslots); started at the first round boundary with k >= kBucketMinK and at
+  // most hbs_vmax live vertices (-1 = never)
+  int32_t* hbl;
+  uint32_t* hlo;
+  int64_t hcap;
+  int32_t hslots;
+  int64_t hbs_vmax;
   // sampling mode (Alg. 4/5): vertices of degree above s_threshold start in sample mode; per vertex
   // the hit threshold of the counter-based coin (rate x 2^32, 0 = not sampled), the hits, the
   // induced degree at the last (re)initialisation and a recount accumulator; the candidates list
@@ -149,11 +164,29 @@ struct PeelArgs {
   int32_t* srl;
 };
 
+constexpr int kMaxTeams = 16;       // batched peel: largest graphs peeled by a team of workgroups
+constexpr int kTeamSize = 8;        //   workgroups per team
+
+// One team's control block: barrier arrivals, the graph's peel-queue tail, and the per-round
+// minimum of the kept induced degrees (three-way rotation, stored complemented so that zero
+// initialisation and atomic max give "no value yet").
+struct alignas(128) TeamCtl {
+  unsigned int bar;               // arrivals (monotone)
+  unsigned int gen;               // barriers released (written by the last arrival)
+  unsigned int pad0[30];
+  unsigned long long tail;        // the graph's peel-queue tail
+  unsigned long long snap[2];     // tail as the last arrival of barrier e saw it, in snap[e & 1]
+  unsigned int rmx[3];
+  unsigned int pad1[23];
+};
+
 struct BatchCtl {
   unsigned long long next;
   unsigned int status;
-  unsigned int pad[29];
+  unsigned int nteams;    // leading graphs of the processing order peeled by teams
+  unsigned int pad[28];
   unsigned long long stats[kStatWords];
+  TeamCtl team[kMaxTeams];
 };
 
 struct BatchArgs {
@@ -170,6 +203,8 @@ struct BatchArgs {
   BatchCtl* ctl;
   int32_t lds_cap;        // vertices per graph held in LDS
   int32_t chained;        // 1: each round is peeled through a dynamic workgroup queue (no subround barriers)
+  int32_t teams;          // 1: the plan kernel may give the largest graphs a team of kTeamSize
+                          // workgroups (the launch is then cooperative: teams wait for each other)
 };
 
 // Error text returned by kcore_last_error (thread-local; defined in kcore_api.cpp).
@@ -181,18 +216,36 @@ void set_error(const char* msg);
 int reserve_batched(hipStream_t stream, int64_t V, int32_t G);
 // Frees the batched-peel workspace of (current device, stream), if any (before the stream goes).
 void release_batched(hipStream_t stream);
+// team_wgs > 0: every graph of the batch (up to kMaxTeams, within team_wgs workgroups) is peeled
+// by a team, in a grid of team_wgs workgroups launched without co-residency guarantee; the caller
+// keeps the team workgroups of all such batches that may run at once within what the device holds
+// resident (other kernels' workgroups do not wait on anything, so teams then always complete).
 int decompose_batched_local(const int64_t* graph_vptr, const int64_t* offsets, const int32_t* adj,
                             int32_t num_graphs, int64_t total_vertices, int32_t* coreness_out,
-                            hipStream_t stream, unsigned* status_out);
+                            hipStream_t stream, unsigned* status_out, int32_t team_wgs = 0);
+// Workgroups of the batched peel resident on the current device at once (0 if unknown).
+int batched_resident_wgs();
 
 // Launch helpers (defined in kcore_device.hip).
 hipError_t launch_peel(const PeelArgs& a, int blocks, hipStream_t s);
 hipError_t peel_occupancy(int* blocks_per_cu);
 hipError_t launch_batched(const BatchArgs& a, int blocks, size_t lds_bytes, hipStream_t s);
+hipError_t launch_batched_coop(const BatchArgs& a, int blocks, size_t lds_bytes, hipStream_t s);
 hipError_t batched_occupancy(size_t lds_bytes, int* blocks_per_cu);
 hipError_t launch_order(const int64_t* vptr, const int64_t* off, int32_t G, int32_t* order,
                         hipStream_t s);
+// Picks the leading graphs of `order` whose entries exceed half a workgroup's average share
+// (blocks workgroups; every leading graph when `all`) for teams of kTeamSize workgroups, using at
+// most team_wgs workgroups; writes ctl->nteams.
+// min_entries > 0 replaces the size rule: graphs with more entries than that get teams.
+hipError_t launch_team_plan(const int64_t* vptr, const int64_t* off, int32_t G, const int32_t* order,
+                            int32_t blocks, int32_t team_wgs, int32_t all, int64_t min_entries, BatchCtl* ctl,
+                            hipStream_t s);
 hipError_t launch_fill_u32(void* p, uint32_t v, size_t count, hipStream_t s);
+// Adds offsets[n] - offsets[0] - sum(core[0..n)) (the live decrements of a finished decomposition)
+// to *out.
+hipError_t launch_live_count(const int64_t* off, const int32_t* core, int64_t n, unsigned long long* out,
+                             hipStream_t s);
 hipError_t launch_init_ctl(PeelCtl* c, hipStream_t s);
 // Single-workgroup peel of the live vertices handed over by peel_kernel (returns at once when none
 // were); lcap = vertices its LDS holds.

@@ -110,6 +110,9 @@ struct kcore_server {
   int64_t next_batch = 1;
   bool stop = false;
   bool log = false;  // KCORE_SERVER_LOG set: one line per batch on stderr
+  // workgroups a large batch may put in teams: the team workgroups of all large batches that can
+  // run at once (every slot but one) fit on the device together, so their teams always complete
+  int32_t team_wgs = 0;
   std::thread th;
 
   double now_us() const {
@@ -251,8 +254,9 @@ int launch_slot(kcore_server* s, Slot* sl) {
       hipHostMalloc((void**)&sl->status_h, sizeof(unsigned), hipHostMallocDefault) != hipSuccess)
     return KCORE_ENOMEM;
   *sl->status_h = 0u;
+  // a large batch peels each of its graphs with a team of workgroups
   int rc = kc::decompose_batched_local(sl->vptr_d, sl->off_d, sl->adj_d, (int32_t)G, V, sl->core_d, st,
-                                       sl->status_h);
+                                       sl->status_h, sl->large ? s->team_wgs : 0);
   if (rc) return rc;
   if (hipMemcpyAsync(sl->core_h, sl->core_d, 4 * V, hipMemcpyDeviceToHost, st) != hipSuccess)
     return KCORE_EDEVICE;
@@ -343,6 +347,8 @@ void dispatcher(kcore_server* s) {
           continue;
         }
         if ((int64_t)take.size() >= s->cfg.max_batch_graphs) break;
+        // (a large batch holds at most as many graphs as it has teams)
+        if (large && s->team_wgs > 0 && (int64_t)take.size() * kc::kTeamSize >= s->team_wgs) break;
         if (!take.empty() && (r->solo || take.front()->solo)) break;
         if (!take.empty() && V + r->n > s->cfg.max_batch_vertices) break;
         if (s->bytes_in_use + bytes + r->bytes > s->cfg.hbm_budget_bytes) break;
@@ -433,6 +439,13 @@ kcore_server* kcore_server_create(const kcore_server_config* cfg) {
   s->cfg = c;
   s->t0 = std::chrono::steady_clock::now();
   s->log = getenv("KCORE_SERVER_LOG") != nullptr;
+  {
+    const int res = kc::batched_resident_wgs();
+    const int large_slots = c.max_inflight > 1 ? c.max_inflight - 1 : 1;
+    int tw = res / large_slots / kc::kTeamSize * kc::kTeamSize;
+    if (tw > kc::kMaxTeams * kc::kTeamSize) tw = kc::kMaxTeams * kc::kTeamSize;
+    s->team_wgs = tw >= kc::kTeamSize ? tw : 0;
+  }
   for (int i = 0; i < c.max_inflight; ++i) {
     Slot* sl = new Slot;
     if (hipStreamCreateWithFlags(&sl->stream, hipStreamNonBlocking) != hipSuccess) {

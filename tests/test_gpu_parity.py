@@ -82,6 +82,8 @@ def test_medium_graphs(mode, which, tail):
     assert st["peeled"] == len(off) - 1 and st["edges"] == len(adj)
     assert st["rounds"] == ls["nonempty_rounds"], (st, ls)
     assert st["kmax"] == int(want.max())
+    # each vertex takes deg - coreness decrements while above k: m - sum of the oracle's coreness
+    assert st["live_decrements"] == len(adj) - int(want.astype(np.int64).sum()), st
     if mode == "levelsync":
         # Alg. 1 + Alg. 3 frontiers are order independent: the subround count must equal the
         # sequential framework's rho
@@ -367,3 +369,69 @@ def test_validate_rejects_bad_csr():
     d_off, d_adj = to_dev(off, loop)
     with pytest.raises(K.KcoreError):
         K.decompose(d_off, d_adj, validate=True)
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("tail", [0, -1])
+def test_multi_bucket_active_set(mode, tail):
+    """Multi-bucket active set (Sec. 5.2): rounds read only the bucket holding the new k, and
+    decrements move vertices to lower buckets. Coreness must be the oracle's; in level-sync mode
+    the frontiers do not change, so rho must still be the sequential framework's."""
+    cases = [("hcns300", None), ("hcns2000", None), ("rmat16", gg.config_rmat16()),
+             ("road1024", gg.grid_road(1024, 0.05, 0.01, 2)), ("er5000", gg.erdos_renyi(5000, 0.02, 8)),
+             ("rmat14", gg.rmat(14, 32, 3))]
+    for name, g in cases:
+        off, adj = (g.offsets, g.adj) if g is not None else G.hcns(int(name[4:]))
+        want, sub, ls = oracle.levelsync(off, adj)
+        for thr in (1 << 30, 1000):
+            say(f"[gpu] buckets {name} mode={mode} tail={tail} threshold={thr}")
+            got, st = run_single(off, adj, mode=mode, tail=tail, buckets=thr)
+            assert not first_mismatch(got, want), f"{name}: {first_mismatch(got, want)}"
+            assert st["peeled"] == len(off) - 1 and st["edges"] == len(adj), (name, st)
+            assert st["device_status"] == 0, (name, st)
+            assert st["rounds"] == ls["nonempty_rounds"], (name, st, ls)
+            if mode == "levelsync":
+                assert st["subrounds"] == ls["subrounds"], (name, st, ls)
+            if int(want.max()) >= 16 and thr == 1 << 30 and tail == -1:
+                assert st["bucket_inserts"] > 0, (name, st)
+                assert st["live_decrements"] == len(adj) - int(want.astype(np.int64).sum())
+
+
+def test_batched_teams_for_the_largest_graphs():
+    """A batch whose few largest graphs each hold far more than a workgroup's share of the entries:
+    those are peeled by teams of workgroups (cooperative launch, team barriers); every graph must
+    still match the oracle, alone and with the small ones."""
+    import torch
+    parts = [gg.rmat(15, 16, 21), gg.rmat(14, 16, 22), gg.grid_road(256, 0.05, 0.01, 3)]
+    small = gg.batch(300, 6, hi=3000)
+    offs = [(p.offsets, p.adj) for p in parts] + [small.subgraph(g) for g in range(300)]
+    offs = [(o.offsets, o.adj) if hasattr(o, "offsets") else o for o in offs]
+    off, adj = G.union(offs)
+    sizes = [len(o) - 1 for o, _ in offs]
+    vptr = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    want = oracle.bz(off, adj)
+    for mode in ("levelsync", "auto"):
+        say(f"[gpu] batched teams mode={mode} G={len(sizes)} V={len(off) - 1} m={len(adj)}")
+        got, st = run_batched(off, adj, vptr, mode=mode)
+        assert not first_mismatch(got, want), first_mismatch(got, want)
+        assert st["device_status"] == 0, st
+        assert st["edges"] == len(adj), st
+
+
+@pytest.mark.parametrize("steal", [1, 8, 64])
+def test_work_stealing_does_not_change_results(steal):
+    """Chained scan phases with work stealing: hub tiles beyond the workgroup backlog go to the
+    shared queue that every workgroup drains (quiescence ends the phase). Every vertex must be
+    peeled once with the oracle's coreness, also with tiny hub thresholds (many tiles shared)."""
+    cases = [("rmat13", gg.rmat(13, 16, 7), {}), ("rmat16", gg.config_rmat16(), {}),
+             ("road256", gg.grid_road(256, 0.05, 0.01, 3), {}), ("hcns200", None, {}),
+             ("rmat13-small-tiles", gg.rmat(13, 16, 7), {"hub_degree": 16, "tile_edges": 64}),
+             ("rmat14-notail", gg.rmat(14, 32, 3), {"tail": -1})]
+    for name, g, kw in cases:
+        off, adj = (g.offsets, g.adj) if g is not None else G.hcns(200)
+        want = oracle.bz(off, adj)
+        say(f"[gpu] steal={steal} {name} {kw}")
+        got, st = run_single(off, adj, mode="chained", steal=steal, **kw)
+        assert not first_mismatch(got, want), first_mismatch(got, want)
+        assert st["peeled"] == len(off) - 1 and st["edges"] == len(adj), (name, st)
+        assert st["device_status"] == 0, (name, st)

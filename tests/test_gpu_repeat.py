@@ -89,3 +89,14 @@ def test_checked_build_batched():
         assert rc == 0, (lib.kcore_last_error() or b"").decode()
         assert st.device_status == 0
         assert not first_mismatch(out.cpu().numpy(), want)
+
+
+def test_checked_build_multi_bucket():
+    for name, off, adj in _cases():
+        want = oracle.bz(off, adj)
+        for mode in ("chained", "levelsync"):
+            say(f"[gpu] checked build buckets {name} mode={mode}")
+            rc, msg, got, st = _checked_single(off, adj, mode, buckets=1 << 30, tail=-1)
+            assert rc == 0, (name, msg, st)
+            assert st["device_status"] == 0, (name, st)
+            assert not first_mismatch(got, want), f"{name}: {first_mismatch(got, want)}"
