@@ -330,7 +330,7 @@ def bench_batch(args, steps, warmup):
     return res
 
 
-def bench_serve(args, seconds: float = 5.0, rate: float = 20000.0, warm: float = 1.0):
+def bench_serve(args, seconds: float = 5.0, rate: float = 20000.0, warm: float = 1.0, **server_kw):
     """Open-loop Poisson arrivals (20k req/s) of graphs from the batched distribution, 1% replaced
     by R-MAT scale 20 edge factor 16; latency = result visible - scheduled arrival. The first
     `warm` seconds of arrivals (buffers growing to their working sizes) are served but not counted."""
@@ -374,7 +374,7 @@ def bench_serve(args, seconds: float = 5.0, rate: float = 20000.0, warm: float =
     # four slots, one per hardware queue of the process (streams beyond that share queues, and a
     # small batch would wait behind a large one); slot buffers sized up front for full small batches
     srv = K.Server(device=0, max_inflight=4, hbm_budget_bytes=64 << 30, max_batch_vertices=1 << 25,
-                   borrow_inputs=True, reserve_vertices=1 << 24, reserve_entries=160 << 20)
+                   borrow_inputs=True, reserve_vertices=1 << 24, reserve_entries=160 << 20, **server_kw)
     tickets = [None] * nreq
     results = {}
     done_evt = threading.Event()

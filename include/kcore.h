@@ -150,11 +150,8 @@ typedef struct {
                             part of this header); 0 = off */
   int64_t test_tail_entries; /* testing: pretend the tail's local rows hold at most this many
                             entries, so that handoffs are called off and retried; 0 = off */
-  int32_t steal;         /* chained mode: in a round's scan phase, hub tiles beyond this many waiting
-                            in a workgroup's queue (and the tiles of hubs too large for it) go to a
-                            queue shared by the grid, which every workgroup helps to drain once its
-                            own share is done (the phase ends when that queue is quiescent), instead
-                            of waiting for the next phase; 0 = default, -1 = never */
+  int32_t team_size;     /* batched peel: workgroups per team (see batch_teams); 0 = default (4),
+                            at most 32 */
   int32_t batch_teams;   /* batched peel (level-sync): a graph with more adjacency entries than this
                             is peeled by a team of workgroups; 0 = default (half a workgroup's
                             average share of the batch's entries), -1 = never */
@@ -262,7 +259,10 @@ typedef struct {
   int32_t device;              /* HIP device ordinal */
   int32_t max_inflight;        /* concurrent batches on the device (>= 1; 0 = 4) */
   int32_t max_batch_graphs;    /* graphs per batch (0 = 4096) */
-  int32_t reserved0;
+  int32_t max_large_inflight;  /* batches of large requests (>= 2^21 entries or 2^16 vertices) in
+                                  flight at once, each graph of them peeled by a team of workgroups
+                                  within half the device; the other slots serve small requests
+                                  (0 = max_inflight / 4, at least 1, below max_inflight) */
   int64_t max_batch_vertices;  /* vertices per batch (0 = 1 << 24) */
   int64_t hbm_budget_bytes;    /* device bytes all in-flight batches may hold (0 = 8 GiB) */
   int64_t max_request_vertices;/* larger requests are rejected with KCORE_ETOOBIG (0 = no limit) */

@@ -53,7 +53,7 @@ class Options(ctypes.Structure):
                 ("residual", ctypes.c_int32), ("tail", ctypes.c_int32),
                 ("buckets", ctypes.c_int32), ("sample_threshold", ctypes.c_int32),
                 ("sample_mu", ctypes.c_int32), ("debug_phase", ctypes.c_int32),
-                ("test_tail_entries", ctypes.c_int64), ("steal", ctypes.c_int32),
+                ("test_tail_entries", ctypes.c_int64), ("team_size", ctypes.c_int32),
                 ("batch_teams", ctypes.c_int32), ("status_out", ctypes.c_void_p)]
 
 
@@ -74,7 +74,7 @@ class Stats(ctypes.Structure):
 
 class ServerConfig(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("max_inflight", ctypes.c_int32),
-                ("max_batch_graphs", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("max_batch_graphs", ctypes.c_int32), ("max_large_inflight", ctypes.c_int32),
                 ("max_batch_vertices", ctypes.c_int64), ("hbm_budget_bytes", ctypes.c_int64),
                 ("max_request_vertices", ctypes.c_int64), ("batch_wait_us", ctypes.c_double),
                 ("borrow_inputs", ctypes.c_int32), ("reserved1", ctypes.c_int32),
@@ -196,7 +196,7 @@ def _stream_ptr(stream) -> int:
 def _options(mode, validate, num_entries, hub_degree=0, local_budget=0, tile_edges=0,
              blocks_per_cu=0, async_frontier=0, async_scan=0, block_tiles=0,
              block_queue=0, tile_probe=0, residual=0, tail=0, buckets=0, sample_threshold=0,
-             sample_mu=0, debug_phase=0, test_tail_entries=0, steal=0, batch_teams=0, status_out=None) -> Options:
+             sample_mu=0, debug_phase=0, test_tail_entries=0, team_size=0, batch_teams=0, status_out=None) -> Options:
     o = Options()
     o.mode = MODES[mode] if isinstance(mode, str) else int(mode)
     o.validate = 1 if validate else 0
@@ -217,7 +217,7 @@ def _options(mode, validate, num_entries, hub_degree=0, local_budget=0, tile_edg
     o.sample_mu = sample_mu
     o.debug_phase = debug_phase
     o.test_tail_entries = test_tail_entries
-    o.steal = steal
+    o.team_size = team_size
     o.batch_teams = batch_teams
     o.status_out = status_out
     return o
@@ -281,7 +281,7 @@ def kcore_subgraph(offsets, adj, k, out=None, *, mode="auto", stats=False, valid
 
 
 def decompose_batched(vptr, offsets, adj, out=None, *, mode="auto", stats=False, validate=False,
-                      stream=None, tuned=False, blocks_per_cu=0, batch_teams=0):
+                      stream=None, tuned=False, blocks_per_cu=0, batch_teams=0, team_size=0):
     """Coreness for a segmented batch of independent graphs (device tensors, global ids).
     ``mode``: "auto"/"levelsync" (barrier-separated subrounds inside each graph's workgroup) or
     "chained" (each round peeled through a dynamic workgroup queue). ``tuned=True`` applies the
@@ -293,6 +293,7 @@ def decompose_batched(vptr, offsets, adj, out=None, *, mode="auto", stats=False,
         mode = t.get("mode", mode)
         blocks_per_cu = t.get("blocks_per_cu", blocks_per_cu)
         batch_teams = t.get("batch_teams", batch_teams)
+        team_size = t.get("team_size", team_size)
     _dev_tensor(vptr, torch.int64, "vptr")
     _dev_tensor(offsets, torch.int64, "offsets")
     _dev_tensor(adj, torch.int32, "adj")
@@ -303,7 +304,8 @@ def decompose_batched(vptr, offsets, adj, out=None, *, mode="auto", stats=False,
     if out is None:
         out = torch.empty(max(V, 0), dtype=torch.int32, device=offsets.device)
     _dev_tensor(out, torch.int32, "out")
-    opt = _options(mode, validate, adj.numel(), blocks_per_cu=blocks_per_cu, batch_teams=batch_teams)
+    opt = _options(mode, validate, adj.numel(), blocks_per_cu=blocks_per_cu, batch_teams=batch_teams,
+                   team_size=team_size)
     st = Stats() if stats else None
     rc = _lib.kcore_decompose_batched_ex(vptr.data_ptr(), offsets.data_ptr(), adj.data_ptr(), G, V,
                                          out.data_ptr() if V else None, _stream_ptr(stream),
@@ -330,11 +332,12 @@ class Server:
                  max_batch_vertices: int = 0, hbm_budget_bytes: int = 0,
                  max_request_vertices: int = 0, batch_wait_us: float = 0.0,
                  borrow_inputs: bool = False, reserve_vertices: int = 0, reserve_entries: int = 0,
-                 fail_ticket: int = 0):
+                 fail_ticket: int = 0, max_large_inflight: int = 0):
         cfg = ServerConfig()
         cfg.device = device
         cfg.max_inflight = max_inflight
         cfg.max_batch_graphs = max_batch_graphs
+        cfg.max_large_inflight = max_large_inflight
         cfg.max_batch_vertices = max_batch_vertices
         cfg.hbm_budget_bytes = hbm_budget_bytes
         cfg.max_request_vertices = max_request_vertices

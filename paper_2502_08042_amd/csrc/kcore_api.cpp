@@ -417,8 +417,9 @@ int check_opts(const kcore_options* o) {
   if (o->async_frontier < -1 || o->async_scan < -1 || o->block_tiles < -1)
     return fail(KCORE_EINVAL, "async and block-tile thresholds must be >= -1");
   if (o->buckets < -1) return fail(KCORE_EINVAL, "buckets must be >= -1");
-  if (o->steal < -1 || o->steal > kc::kBlockQ) return fail(KCORE_EINVAL, "steal must be in [-1, %d]", kc::kBlockQ);
   if (o->batch_teams < -1) return fail(KCORE_EINVAL, "batch_teams must be >= -1");
+  if (o->team_size < 0 || o->team_size > kc::kMaxTeamSize)
+    return fail(KCORE_EINVAL, "team_size must be in [0, %d]", kc::kMaxTeamSize);
   if (o->sample_threshold < 0 || o->sample_mu < 0 || o->debug_phase < 0 || o->test_tail_entries < 0)
     return fail(KCORE_EINVAL, "sampling parameters and test hooks must be >= 0");
   return KCORE_OK;
@@ -584,8 +585,6 @@ static int peel_impl(const int64_t* offsets, const int32_t* adj, int64_t n, int3
   const int32_t bt = opt ? opt->block_tiles : 0;
   a.bq_max_tiles = bt < 0 ? 0 : (bt ? bt : 32);
   a.bq_backlog = (opt && opt->block_queue) ? opt->block_queue : 64;
-  const int32_t so = opt ? opt->steal : 0;
-  a.steal_backlog = so < 0 ? 0 : (so ? so : 0);
   a.tile_probe_always = !(opt && opt->tile_probe < 0);
   a.k_query = k_query;
   a.rrow = w->rrow;
@@ -873,13 +872,15 @@ static int batched_impl(const int64_t* graph_vptr, const int64_t* offsets, const
   const int32_t bt = opt ? opt->batch_teams : 0;
   const bool coop_teams = !local_ids && !a.chained && bt >= 0 && blocks >= 4 * kc::kTeamSize &&
                           !(opt && opt->blocks_per_cu);
-  const bool serve_teams = local_ids && team_wgs >= kc::kTeamSize;
+  a.team_size = (opt && opt->team_size) ? opt->team_size : kc::kTeamSize;
+  const bool serve_teams = local_ids && team_wgs >= a.team_size;
   a.teams = (coop_teams || serve_teams) ? 1 : 0;
-  if (serve_teams) blocks = std::min(blocks, std::min(team_wgs, num_graphs * kc::kTeamSize));
+  if (serve_teams) blocks = std::min(blocks, std::min(team_wgs, num_graphs * a.team_size));
   if (a.teams)
+    // (a caller's batch keeps three quarters of its workgroups for the many small graphs)
     HIP_TRY(kc::launch_team_plan(graph_vptr, offsets, num_graphs, w->order, blocks,
-                                 serve_teams ? blocks : blocks / 2, serve_teams ? 1 : 0, bt > 0 ? bt : 0,
-                                 w->ctl, stream));
+                                 serve_teams ? blocks : blocks / 4, a.team_size, serve_teams ? 1 : 0,
+                                 bt > 0 ? bt : 0, w->ctl, stream));
   if (stats_host) HIP_TRY(hipEventRecord(w->ev0, stream));
   if (coop_teams) {
     if (int rc = launch_ordered(dev, stream, [&] { return kc::launch_batched_coop(a, blocks, lds, stream); }))

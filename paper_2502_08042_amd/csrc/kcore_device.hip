@@ -258,8 +258,6 @@ struct WaveCtx {
   bool async;          // phase-uniform: pushes go to the async work queue
   bool arbitrate;      // phase-uniform: crossings may race with a scan (chained scan phases)
   bool bq_open;        // phase-uniform: small hubs go to the workgroup's tile queue
-  bool steal;          // phase-uniform: hub tiles the workgroup queue refuses go to the phase's
-                       // shared work queue, which every workgroup helps to drain after its share
   unsigned long long* bq;  // LDS, kBlockQ entries: (tile << 32) | vertex, kQEmpty or kQSkip
   int* bqc;            // LDS: claimed, reserved, busy waves, [4..5] debug counts
   const int32_t* adj;  // adjacency the rows point into: the input, or the residual rows
@@ -490,15 +488,10 @@ __device__ __forceinline__ void push_vertices(const PeelArgs& a, WaveCtx& c, con
       return;
     }
     bool pg = ph;
-    if (c.bq_open && block_push(c, rb, deg, a.tile, (ph && nt <= a.bq_max_tiles) ? nt : 0,
-                                c.steal ? a.steal_backlog : a.bq_backlog))
+    if (c.bq_open && block_push(c, rb, deg, a.tile, (ph && nt <= a.bq_max_tiles) ? nt : 0, a.bq_backlog))
       pg = false;
     if (!pg) nt = 0;
     if (__ballot(pg) == 0) return;
-    if (c.steal) {
-      queue_push(a, o, v, nt, true);
-      return;
-    }
     const long long incl = wave_incl_scan(nt);
     const long long tot = __shfl(incl, 63, 64);
     unsigned long long base = 0;
@@ -579,7 +572,7 @@ __device__ __forceinline__ void sample_hit(const PeelArgs& a, const WaveCtx& c, 
 // latency-bound phases the probe is skipped (decrementing a peeled vertex is harmless: it can
 // never cross k again, and each neighbour decrements it once, so it never drops below zero).
 // The lane whose decrement takes u from k+1 to k pushes it.
-template <bool S, int U>
+template <bool S, bool H, int U>
 __device__ __forceinline__ void edges_batch(const PeelArgs& a, WaveCtx& c, const PhaseOut& o,
                                             const int32_t (&u)[U], unsigned valid, uint32_t k) {
   uint32_t sw[U];
@@ -627,7 +620,7 @@ __device__ __forceinline__ void edges_batch(const PeelArgs& a, WaveCtx& c, const
     for (int j = 0; j < U; ++j)
       if ((did >> j) & 1u) check_decrement(old[j] & DMASK, 1u, &a.ctl->status);
   }
-  if constexpr (!S) {
+  if constexpr (!S && H) {
     if (c.hbs) {
 #pragma unroll
       for (int j = 0; j < U; ++j) {
@@ -661,7 +654,7 @@ __device__ __forceinline__ void edges_batch(const PeelArgs& a, WaveCtx& c, const
 // Expands the rows of up to 64 vertices (one per lane, -1 = none) edge-balanced across the wave:
 // an exclusive scan of the degrees, then each lane finds the row of each of its entries by binary
 // search over the scan.
-template <bool S>
+template <bool S, bool H>
 __device__ __forceinline__ void expand_rows(const PeelArgs& a, WaveCtx& c, const PhaseOut& o, int32_t v, uint32_t k) {
   long long b = 0, d = 0;
   if (v >= 0) row_of(a, c, v, b, d);
@@ -689,12 +682,12 @@ __device__ __forceinline__ void expand_rows(const PeelArgs& a, WaveCtx& c, const
         valid |= 1u << q;
       }
     }
-    edges_batch<S>(a, c, o, u, valid, k);
+    edges_batch<S, H>(a, c, o, u, valid, k);
   }
 }
 
 // A hub tile: adjacency entries [pos, pos + len), len <= 64 * kTileUnroll for default tiles.
-template <bool S>
+template <bool S, bool H>
 __device__ __forceinline__ void expand_span(const PeelArgs& a, WaveCtx& c, const PhaseOut& o, long long pos,
                                             long long len, uint32_t k) {
   // hub rows mostly point at vertices peeled long ago: probe the peeled bits here (in every phase
@@ -715,24 +708,25 @@ __device__ __forceinline__ void expand_span(const PeelArgs& a, WaveCtx& c, const
         valid |= 1u << q;
       }
     }
-    edges_batch<S>(a, c, o, u, valid, k);
+    edges_batch<S, H>(a, c, o, u, valid, k);
   }
   c.precheck = saved;
 }
 
 // Tile j of the row of v (async queue entries name the vertex).
-template <bool S>
+template <bool S, bool H>
 __device__ __forceinline__ void expand_tile(const PeelArgs& a, WaveCtx& c, const PhaseOut& o, int32_t v, int32_t j,
                                             uint32_t k) {
   long long rb = 0, d = 0;
   row_of(a, c, v, rb, d);
   const long long b = rb + (long long)j * a.tile;
-  expand_span<S>(a, c, o, b, min(rb + d, b + a.tile) - b, k);
+  expand_span<S, H>(a, c, o, b, min(rb + d, b + a.tile) - b, k);
 }
 
 // Applies the block's combined decrements: one atomic subtraction of c per target; exactly one
 // subtraction takes a target from above k to k or below (old > k >= old - c), and that one pushes
 // it. Clears the table for the next phase. All threads of the block call.
+template <bool H>
 __device__ __forceinline__ void comb_flush(const PeelArgs& a, WaveCtx& c, const PhaseOut& o, uint32_t k) {
   __syncthreads();
   for (int s0 = 0; s0 < kCombSlots; s0 += kPeelThreads) {
@@ -760,7 +754,9 @@ __device__ __forceinline__ void comb_flush(const PeelArgs& a, WaveCtx& c, const 
         }
       }
     }
-    if (c.hbs) hbs_move(a, c, o, u >= 0 && hxo >= hxn, u, hxo, hxn, k);
+    if constexpr (H) {
+      if (c.hbs) hbs_move(a, c, o, u >= 0 && hxo >= hxn, u, hxo, hxn, k);
+    }
     push_vertices(a, c, o, crossed, u, hub);
   }
   __syncthreads();
@@ -768,7 +764,7 @@ __device__ __forceinline__ void comb_flush(const PeelArgs& a, WaveCtx& c, const 
 
 // Chained mode: peel what the wave queued locally, in packets of up to 64 vertices, until the
 // queue is empty or the wave's budget for this phase is spent; what is left joins the frontier.
-template <bool S>
+template <bool S, bool H>
 __device__ __forceinline__ void drain_local(const PeelArgs& a, WaveCtx& c, const PhaseOut& o, uint32_t k) {
   while (c.lq_cnt > 0 && c.lq_used < a.lq_budget) {
     const int take = c.lq_cnt < 64 ? c.lq_cnt : 64;
@@ -777,7 +773,7 @@ __device__ __forceinline__ void drain_local(const PeelArgs& a, WaveCtx& c, const
     c.lq_cnt -= take;
     c.lq_used += take;
     if (lane_id() == 0) atomicAdd(&c.bqc[5], take);
-    expand_rows<S>(a, c, o, v, k);
+    expand_rows<S, H>(a, c, o, v, k);
   }
   while (c.lq_cnt > 0) {
     const int take = c.lq_cnt < 64 ? c.lq_cnt : 64;
@@ -798,7 +794,7 @@ __device__ __forceinline__ void drain_local(const PeelArgs& a, WaveCtx& c, const
 // busy wave (busy first) and then no unclaimed slot: entries are only reserved by busy waves, and a
 // wave that reserved entries stays until it sees them claimed, so no entry is left behind. Waits
 // are bounded.
-template <bool S>
+template <bool S, bool H>
 __device__ __forceinline__ void block_loop(const PeelArgs& a, WaveCtx& c, const PhaseOut& o, uint32_t k) {
   int* head = &c.bqc[0];
   int* tail = &c.bqc[1];
@@ -854,8 +850,8 @@ __device__ __forceinline__ void block_loop(const PeelArgs& a, WaveCtx& c, const 
     if (state != 1) return;
     e = __shfl(e, 0, 64);
     if (e == kQSkip) continue;
-    expand_span<S>(a, c, o, (long long)((unsigned long long)e >> 16), e & 0xffff, k);
-    drain_local<S>(a, c, o, k);
+    expand_span<S, H>(a, c, o, (long long)((unsigned long long)e >> 16), e & 0xffff, k);
+    drain_local<S, H>(a, c, o, k);
   }
 }
 
@@ -866,7 +862,7 @@ __device__ __forceinline__ void block_loop(const PeelArgs& a, WaveCtx& c, const 
 // (read after done) nothing is left in flight and nothing more can be created. Only wave 0 of a
 // workgroup polls those shared counters (and publishes the outcome in LDS for its siblings), so
 // waiting waves do not slow down the atomics of working ones. Waits are bounded.
-template <bool S>
+template <bool S, bool H>
 __device__ __forceinline__ void async_loop(const PeelArgs& a, WaveCtx& c, const PhaseOut& o, uint32_t k,
                                            volatile int* s_quiet) {
   PhaseSlot* PS = o.slot;
@@ -926,10 +922,10 @@ __device__ __forceinline__ void async_loop(const PeelArgs& a, WaveCtx& c, const 
     const uint32_t j = (uint32_t)((unsigned long long)e >> 32);
     c.lq_used = 0;
     if (j == kWholeRow)
-      expand_rows<S>(a, c, o, lane_id() == 0 ? v : -1, k);
+      expand_rows<S, H>(a, c, o, lane_id() == 0 ? v : -1, k);
     else
-      expand_tile<S>(a, c, o, v, (int32_t)j, k);
-    if (a.chained) drain_local<S>(a, c, o, k);
+      expand_tile<S, H>(a, c, o, v, (int32_t)j, k);
+    if (a.chained) drain_local<S, H>(a, c, o, k);
     __builtin_amdgcn_s_waitcnt(0);
     if (lane_id() == 0) aadd(&PS->qdone, 1ull);
   }
@@ -937,7 +933,7 @@ __device__ __forceinline__ void async_loop(const PeelArgs& a, WaveCtx& c, const 
 
 enum PhaseKind { PH_SCAN = 0, PH_EXPAND = 1, PH_ASYNC = 2, PH_RESIDUAL = 3, PH_TAIL = 4, PH_SAMPLE = 5 };
 
-template <bool S>
+template <bool S, bool H>
 __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
   __shared__ int32_t s_sf[kWaves][kStage];
   __shared__ int32_t s_sa[kWaves][kStage];
@@ -990,7 +986,6 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
   c.bq = s_bq;
   c.bqc = s_bqc;
   c.bq_open = false;
-  c.steal = false;
   if (threadIdx.x == 0) s_anew = 0;
   c.adj = a.adj;
   c.rows = reinterpret_cast<const long long*>(a.off);
@@ -1036,7 +1031,7 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
           }
         }
         ast(&a.dt[v], (uint32_t)d | (hub ? HUBBIT : 0u) | sbit);
-        if (a.hlo) ast(&a.hlo[v], 0u);  // filed nowhere yet
+        if (H && a.hlo) ast(&a.hlo[v], 0u);  // filed nowhere yet
         bits |= (hot ? 1u : 0u) << (16 + j);
         mn = min(mn, (unsigned)d);
       }
@@ -1413,7 +1408,7 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
       continue;
     }
     c.lq_used = 0;
-    if (kind == PH_SCAN && a.hbs_vmax > 0) {
+    if (H && kind == PH_SCAN && a.hbs_vmax > 0) {
       if (!hbs_on && kx >= (long long)kBucketMinK && n - total_peeled <= a.hbs_vmax) {
         // the multi-bucket set starts: this scan files every live vertex of the active list
         // (frozen from now on; the row rewrite and the tail handoff still read it, with the
@@ -1448,7 +1443,6 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
     c.combine = c.precheck && !c.async;
     c.arbitrate = kind == PH_SCAN && a.chained;
     c.bq_open = a.chained && a.bq_max_tiles > 0 && !c.async;
-    c.steal = c.bq_open && kind == PH_SCAN && a.steal_backlog > 0;
     if (tr) {
       C->trace[p][4] = (unsigned long long)kind | (c.precheck ? 16ull : 0ull) | (c.async ? 32ull : 0ull) |
                        ((unsigned long long)k << 8);
@@ -1513,21 +1507,18 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
         if (it < npk) {
           const long long i = it * per + l;
           const int32_t v = (l < per && i < fs) ? ald(&fcur[i]) : -1;
-          expand_rows<S>(a, c, o, v, k);
+          expand_rows<S, H>(a, c, o, v, k);
         } else {
           const unsigned long long sw = ald(&tcur[it - npk]);
-          expand_span<S>(a, c, o, (long long)(sw >> 16), (long long)(sw & 0xffff), k);
+          expand_span<S, H>(a, c, o, (long long)(sw >> 16), (long long)(sw & 0xffff), k);
         }
       }
     }
-    if (a.chained) drain_local<S>(a, c, o, k);
+    if (a.chained) drain_local<S, H>(a, c, o, k);
     if (c.bq_open) {
-      block_loop<S>(a, c, o, k);
+      block_loop<S, H>(a, c, o, k);
       c.bq_open = false;
     }
-    // work stealing: what the workgroup queues refused is drained by everyone, as in an
-    // asynchronous phase (pushes made meanwhile go to the shared queue too)
-    if (c.steal) c.async = true;
     if (c.async) {
       if (threadIdx.x == 0) s_quiet = 0;
       __syncthreads();
@@ -1537,17 +1528,14 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
       }
       // a few waves per workgroup take part in the dynamic part: every claim is an atomic on one
       // shared counter, so thousands of claimers would serialise there
-      if ((threadIdx.x >> 6) < kAsyncWaves) async_loop<S>(a, c, o, k, &s_quiet);
+      if ((threadIdx.x >> 6) < kAsyncWaves) async_loop<S, H>(a, c, o, k, &s_quiet);
     }
-    // (after quiescence nothing may be added to the shared queue: the combined decrements below
-    // push to the next phase)
-    if (c.steal) c.async = false;
-    comb_flush(a, c, o, k);
+    comb_flush<H>(a, c, o, k);
     // every wave has left the tile queue (comb_flush starts with a workgroup barrier): reset it for
     // the next phase; the barriers of the flushes below order this before its next use
     for (int i = threadIdx.x; i < kBlockQ; i += kPeelThreads) s_bq[i] = (unsigned long long)kQEmpty;
     if (threadIdx.x < 4) s_bqc[threadIdx.x] = threadIdx.x == 2 ? kWaves : 0;
-    if (a.chained) drain_local<S>(a, c, o, k);
+    if (a.chained) drain_local<S, H>(a, c, o, k);
     if (tr) C->trace[p][1] = wall_clock64();
     if (dbg) C->dbg[p - a.dbg_lo][blockIdx.x][1] = wall_clock64();
 
@@ -1757,15 +1745,22 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
 
 hipError_t launch_peel(const PeelArgs& a, int blocks, hipStream_t s) {
   void* args[] = {const_cast<PeelArgs*>(&a)};
-  return hipLaunchCooperativeKernel(a.sampling ? reinterpret_cast<const void*>(peel_kernel<true>)
-                                               : reinterpret_cast<const void*>(peel_kernel<false>), dim3(blocks),
+  // instances: sampling, multi-bucket active set, neither (each keeps the others' code out of its
+  // registers)
+  const void* f = a.sampling ? reinterpret_cast<const void*>(peel_kernel<true, false>)
+                  : a.hbs_vmax > 0 ? reinterpret_cast<const void*>(peel_kernel<false, true>)
+                                   : reinterpret_cast<const void*>(peel_kernel<false, false>);
+  return hipLaunchCooperativeKernel(f, dim3(blocks),
                                     dim3(kPeelThreads), args, 0, s);
 }
 
 hipError_t peel_occupancy(int* blocks_per_cu) {
   int b0 = 0, b1 = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b0, peel_kernel<false>, kPeelThreads, 0);
-  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b1, peel_kernel<true>, kPeelThreads, 0);
+  int b2 = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b0, peel_kernel<false, false>, kPeelThreads, 0);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b1, peel_kernel<true, false>, kPeelThreads, 0);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b2, peel_kernel<false, true>, kPeelThreads, 0);
+  if (b2 < b1) b1 = b2;
   *blocks_per_cu = b0 < b1 ? b0 : b1;
   return e;
 }
@@ -1927,7 +1922,7 @@ __device__ __forceinline__ bool batch_chain(const BatchArgs& a, uint32_t* d, int
 }
 
 // ------------------------------------------------------------------------------------------
-// Teams: a graph too large for one workgroup's share of the batch is peeled by kTeamSize
+// Teams: a graph too large for one workgroup's share of the batch is peeled by team_size
 // workgroups together (the launch is cooperative, so they are all resident). Induced degrees and
 // the peel queue live in global memory at the graph's own vertex range; decrements are agent-scope
 // atomics, and the team synchronises at every round scan and subround with a counter barrier
@@ -1996,8 +1991,9 @@ __device__ __forceinline__ void team_peel(const BatchArgs& a, int team, int memb
   uint32_t* d = a.gdt + base;
   int32_t* q = a.gq + base;
   const int tid = threadIdx.x, l = lane_id(), w = threadIdx.x >> 6;
+  const int tsz = a.team_size;
   const long long gtid = (long long)member * kBatchThreads + tid;
-  const long long GT = (long long)kTeamSize * kBatchThreads;
+  const long long GT = (long long)tsz * kBatchThreads;
   unsigned epoch = 0;
   const bool lead = member == 0;
 
@@ -2017,7 +2013,7 @@ __device__ __forceinline__ void team_peel(const BatchArgs& a, int team, int memb
     if (m != 0xffffffffu) __hip_atomic_fetch_max(&T->rmx[2], ~m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   long long tail = 0;
-  if (!team_sync(T, kTeamSize, epoch, status, tail)) return;
+  if (!team_sync(T, tsz, epoch, status, tail)) return;
   unsigned k = ~ald(&T->rmx[2]);
   long long head = 0;
   for (long long r = 0;; ++r) {
@@ -2041,7 +2037,7 @@ __device__ __forceinline__ void team_peel(const BatchArgs& a, int team, int memb
       for (int i = 0; i < kBatchThreads / 64; ++i) m = min(m, s_min[i]);
       if (m != 0xffffffffu) __hip_atomic_fetch_max(rmx, ~m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    if (!team_sync(T, kTeamSize, epoch, status, tail)) return;
+    if (!team_sync(T, tsz, epoch, status, tail)) return;
     if (tail == head) {
       const unsigned mv = ~ald(rmx);
       if (mv == 0xffffffffu || tail >= ng) return;  // (nothing live: cannot happen before tail == ng)
@@ -2052,8 +2048,8 @@ __device__ __forceinline__ void team_peel(const BatchArgs& a, int team, int memb
     kmax_all = max(kmax_all, k);
     while (head < tail) {
       if (lead) st_sub++;
-      const long long c0 = head + (tail - head) * member / kTeamSize;
-      const long long c1 = head + (tail - head) * (member + 1) / kTeamSize;
+      const long long c0 = head + (tail - head) * member / tsz;
+      const long long c1 = head + (tail - head) * (member + 1) / tsz;
       for (long long cb = c0; cb < c1; cb += kBatchThreads) {
         const long long i = cb + tid;
         long long dg = 0, rb = 0;
@@ -2092,7 +2088,7 @@ __device__ __forceinline__ void team_peel(const BatchArgs& a, int team, int memb
         __syncthreads();
       }
       head = tail;
-      if (!team_sync(T, kTeamSize, epoch, status, tail)) return;
+      if (!team_sync(T, tsz, epoch, status, tail)) return;
     }
     if (tail >= ng) return;
     k = k + 1;
@@ -2114,8 +2110,8 @@ __global__ __launch_bounds__(kBatchThreads) void batched_kernel(BatchArgs a) {
   const int tid = threadIdx.x, l = lane_id(), w = threadIdx.x >> 6;
   // the leading nteams graphs of the order are peeled by teams of the first workgroups
   const int nteams = a.teams ? (int)a.ctl->nteams : 0;
-  if ((int)blockIdx.x < nteams * kTeamSize)
-    team_peel(a, blockIdx.x / kTeamSize, blockIdx.x % kTeamSize, s_pref, s_rb, s_w, s_min, st_edges, st_decr,
+  if ((int)blockIdx.x < nteams * a.team_size)
+    team_peel(a, blockIdx.x / a.team_size, blockIdx.x % a.team_size, s_pref, s_rb, s_w, s_min, st_edges, st_decr,
               st_rounds, st_sub, st_scanned, kmax_all);
 
   for (;;) {
@@ -2325,13 +2321,14 @@ hipError_t launch_batched_coop(const BatchArgs& a, int blocks, size_t lds_bytes,
 // LDS-resident small graphs that make up most of a batch, hence the low default threshold.
 __global__ __launch_bounds__(64) void team_plan_kernel(const int64_t* vptr, const int64_t* off, int32_t G,
                                                        const int32_t* order, int32_t blocks, int32_t team_wgs,
-                                                       int32_t all, long long min_entries, BatchCtl* ctl) {
+                                                       int32_t team_size, int32_t all, long long min_entries,
+                                                       BatchCtl* ctl) {
   if (threadIdx.x != 0) return;
   const long long total = off[vptr[G]] - off[vptr[0]];
   const long long share = total / (blocks > 0 ? blocks : 1);
   const long long thr = min_entries > 0 ? min_entries : share / 2;
   int nt = 0;
-  while (nt < kMaxTeams && nt < G && (nt + 1) * kTeamSize <= team_wgs) {
+  while (nt < kMaxTeams && nt < G && (nt + 1) * team_size <= team_wgs) {
     const int32_t g = order[nt];
     const long long e = off[vptr[g + 1]] - off[vptr[g]];
     if (!all && e <= thr) break;
@@ -2341,10 +2338,10 @@ __global__ __launch_bounds__(64) void team_plan_kernel(const int64_t* vptr, cons
 }
 
 hipError_t launch_team_plan(const int64_t* vptr, const int64_t* off, int32_t G, const int32_t* order,
-                            int32_t blocks, int32_t team_wgs, int32_t all, int64_t min_entries, BatchCtl* ctl,
-                            hipStream_t s) {
-  hipLaunchKernelGGL(team_plan_kernel, dim3(1), dim3(64), 0, s, vptr, off, G, order, blocks, team_wgs, all,
-                     (long long)min_entries, ctl);
+                            int32_t blocks, int32_t team_wgs, int32_t team_size, int32_t all, int64_t min_entries,
+                            BatchCtl* ctl, hipStream_t s) {
+  hipLaunchKernelGGL(team_plan_kernel, dim3(1), dim3(64), 0, s, vptr, off, G, order, blocks, team_wgs, team_size,
+                     all, (long long)min_entries, ctl);
   return hipGetLastError();
 }
 
@@ -2459,16 +2456,37 @@ __device__ __forceinline__ void tail_tile(const PeelArgs& a, uint32_t* d, uint16
 // it sees no busy wave (busy first) and then no unclaimed entry; entries are reserved before they
 // are written, so a claimed slot is read once it is no longer -1. False on a timeout. All threads
 // call.
+// Tiles of long rows a wavefront claimed are shared with the other wavefronts through a small
+// LDS ring (start << 16 | length, kTileEmpty = free slot), so that a chain level with a few long
+// rows keeps all wavefronts busy; when the ring has no room the claiming wavefront streams them.
+constexpr int kTailRing = 256;
+constexpr unsigned long long kTileEmpty = ~0ull;
+
 __device__ __forceinline__ bool tail_chain(const PeelArgs& a, uint32_t* d, uint16_t* q, int L, uint32_t k,
-                                           int* s_claim, int* s_tail, int* s_busy, long long& st_edges) {
+                                           int* s_claim, int* s_tail, int* s_busy, unsigned long long* s_ring,
+                                           int* s_rclaim, int* s_rtail, long long& st_edges) {
   constexpr int nw = kTailThreads / 64;
   const int l = lane_id();
   const unsigned long long t_start = wall_clock64();
   for (;;) {
-    int state = 0, h = 0, cnt = 0;  // state: 1 claimed, 2 done, 3 timeout
+    int state = 0, h = 0, cnt = 0;  // state: 1 vertices claimed, 4 a tile claimed, 2 done, 3 timeout
     if (l == 0) {
       bool counted = true;
       for (int spin = 0;; ++spin) {
+        // shared tiles first: they finish rows that are already under way
+        const int rh = lds_ld(s_rclaim);
+        if (rh < lds_ld(s_rtail)) {
+          if (!counted) {
+            atomicAdd(s_busy, 1);
+            counted = true;
+          }
+          if (atomicCAS(s_rclaim, rh, rh + 1) == rh) {
+            h = rh;
+            state = 4;
+            break;
+          }
+          continue;
+        }
         const int hh = lds_ld(s_claim);
         const int tt = lds_ld(s_tail);
         if (hh < tt) {
@@ -2491,7 +2509,7 @@ __device__ __forceinline__ bool tail_chain(const PeelArgs& a, uint32_t* d, uint1
           continue;
         }
         if (lds_ld(s_busy) == 0) {
-          if (lds_ld(s_claim) >= lds_ld(s_tail)) {
+          if (lds_ld(s_claim) >= lds_ld(s_tail) && lds_ld(s_rclaim) >= lds_ld(s_rtail)) {
             state = 2;
             break;
           }
@@ -2505,6 +2523,29 @@ __device__ __forceinline__ bool tail_chain(const PeelArgs& a, uint32_t* d, uint1
       }
     }
     state = __shfl(state, 0, 64);
+    if (state == 4) {
+      // a shared tile: its slot was reserved before it was written, so wait for the entry, then
+      // free the slot and stream the tile
+      h = __shfl(h, 0, 64);
+      unsigned long long e = kTileEmpty;
+      int full = 0;
+      if (l == 0) {
+        unsigned long long* slot = &s_ring[h & (kTailRing - 1)];
+        for (int spin = 0;; ++spin) {
+          e = lds_ld(slot);
+          if (e != kTileEmpty) break;
+          if ((spin & 255) == 255 && wall_clock64() - t_start > 400000000ull) break;
+        }
+        if (e != kTileEmpty) lds_st(slot, kTileEmpty);
+        full = lds_ld(s_tail) >= L;
+      }
+      e = __shfl(e, 0, 64);
+      if (e == kTileEmpty) return false;
+      const int tlen = (int)(e & 0xffffull);
+      if (l == 0) st_edges += tlen;
+      if (!__shfl(full, 0, 64)) tail_tile(a, d, q, s_tail, L, (int)(e >> 16), tlen, k);
+      continue;
+    }
     if (state != 1) return state == 2;
     h = __shfl(h, 0, 64);
     cnt = __shfl(cnt, 0, 64);
@@ -2534,6 +2575,40 @@ __device__ __forceinline__ bool tail_chain(const PeelArgs& a, uint32_t* d, uint1
       continue;
     }
     unsigned long long big = __ballot(dg >= kTailBig);
+    if (big) {
+      // hand the long rows' tiles to the ring when it has room for all of them
+      const int nt = dg >= kTailBig ? (dg + kTailTile - 1) / kTailTile : 0;
+      const int tincl = wave_incl_scan(nt);
+      const int ttot = __shfl(tincl, 63, 64);
+      int base = -1;
+      if (l == 0) {
+        for (;;) {
+          const int rt = lds_ld(s_rtail);
+          if (rt + ttot - lds_ld(s_rclaim) > kTailRing) break;
+          if (atomicCAS(s_rtail, rt, rt + ttot) == rt) {
+            base = rt;
+            break;
+          }
+        }
+      }
+      base = __shfl(base, 0, 64);
+      if (base >= 0) {
+        bool late = false;
+        for (int j = 0; j < nt; ++j) {
+          // (a slot may still hold an older tile that was claimed but not yet read)
+          unsigned long long* slot = &s_ring[(base + tincl - nt + j) & (kTailRing - 1)];
+          for (int spin = 0; lds_ld(slot) != kTileEmpty; ++spin)
+            if ((spin & 255) == 255 && wall_clock64() - t_start > 400000000ull) {
+              late = true;
+              break;
+            }
+          lds_st(slot, ((unsigned long long)(rb + j * kTailTile) << 16) |
+                           (unsigned long long)min(kTailTile, dg - j * kTailTile));
+        }
+        if (__ballot(late)) return false;
+        big = 0;
+      }
+    }
     while (big) {
       const int j = __ffsll((long long)big) - 1;
       big &= big - 1;
@@ -2608,6 +2683,8 @@ __global__ __launch_bounds__(kTailThreads) void tail_kernel(PeelArgs a, int32_t 
   __shared__ unsigned s_min[kTailThreads / 64];
   __shared__ int s_tail;
   __shared__ int s_claim, s_busy;
+  __shared__ unsigned long long s_ring[kChained ? kTailRing : 1];  // shared long-row tiles
+  __shared__ int s_rclaim, s_rtail;
   const int tid = threadIdx.x, l = lane_id(), w = tid >> 6;
   const long long Ln = (long long)ald(&a.ctl->tail_n);
   if (Ln == 0) return;
@@ -2634,6 +2711,8 @@ __global__ __launch_bounds__(kTailThreads) void tail_kernel(PeelArgs a, int32_t 
     mn = min(mn, dg);
   }
   if (tid < 64) d[L + tid] = 0x7fffffffu;  // spare slots: never near any k
+  if (kChained)
+    for (int i = tid; i < kTailRing; i += kTailThreads) s_ring[i] = kTileEmpty;
   mn = wave_min(mn);
   if (l == 0) s_min[w] = mn;
   if (tid == 0) s_tail = 0;
@@ -2688,9 +2767,11 @@ __global__ __launch_bounds__(kTailThreads) void tail_kernel(PeelArgs a, int32_t 
       if (tid == 0) {
         s_claim = head;
         s_busy = kTailThreads / 64;
+        s_rclaim = 0;
+        s_rtail = 0;
       }
       __syncthreads();
-      if (!tail_chain(a, d, q, L, k, &s_claim, &s_tail, &s_busy, st_edges) && l == 0)
+      if (!tail_chain(a, d, q, L, k, &s_claim, &s_tail, &s_busy, s_ring, &s_rclaim, &s_rtail, st_edges) && l == 0)
         aor(&a.ctl->status, (unsigned)KC_ERR_TIMEOUT);
       __syncthreads();
       st_sub++;

@@ -120,8 +120,6 @@ struct PeelArgs {
   int64_t async_scan_max; // chained mode: active sets up to this size scan and peel in one phase
   int32_t bq_max_tiles;   // chained mode: hubs of at most this many tiles stay in the workgroup (0 = off)
   int32_t bq_backlog;     //   while at most this many tiles wait unclaimed in the workgroup's queue
-  int32_t steal_backlog;  // chained scan phases: > 0 = tiles beyond this backlog go to the shared
-                          // queue that all workgroups drain (0 = off)
   int64_t dbg_lo;         // first phase of the per-workgroup debug record (-1 = none)
   int32_t tile_probe_always; // hub tiles probe peeled bits in every phase (else in large ones only)
   long long* rrow;        // residual rows: [2v] first entry, [2v + 1] end, in radj
@@ -164,8 +162,9 @@ struct PeelArgs {
   int32_t* srl;
 };
 
-constexpr int kMaxTeams = 16;       // batched peel: largest graphs peeled by a team of workgroups
-constexpr int kTeamSize = 8;        //   workgroups per team
+constexpr int kMaxTeams = 64;       // batched peel: largest graphs peeled by a team of workgroups
+constexpr int kTeamSize = 8;        //   workgroups per team (default; at most kMaxTeamSize)
+constexpr int kMaxTeamSize = 32;
 
 // One team's control block: barrier arrivals, the graph's peel-queue tail, and the per-round
 // minimum of the kept induced degrees (three-way rotation, stored complemented so that zero
@@ -203,8 +202,9 @@ struct BatchArgs {
   BatchCtl* ctl;
   int32_t lds_cap;        // vertices per graph held in LDS
   int32_t chained;        // 1: each round is peeled through a dynamic workgroup queue (no subround barriers)
-  int32_t teams;          // 1: the plan kernel may give the largest graphs a team of kTeamSize
-                          // workgroups (the launch is then cooperative: teams wait for each other)
+  int32_t teams;          // 1: the plan kernel may give the largest graphs a team of team_size
+                          // workgroups (teams wait for each other: see the launch)
+  int32_t team_size;
 };
 
 // Error text returned by kcore_last_error (thread-local; defined in kcore_api.cpp).
@@ -239,8 +239,8 @@ hipError_t launch_order(const int64_t* vptr, const int64_t* off, int32_t G, int3
 // most team_wgs workgroups; writes ctl->nteams.
 // min_entries > 0 replaces the size rule: graphs with more entries than that get teams.
 hipError_t launch_team_plan(const int64_t* vptr, const int64_t* off, int32_t G, const int32_t* order,
-                            int32_t blocks, int32_t team_wgs, int32_t all, int64_t min_entries, BatchCtl* ctl,
-                            hipStream_t s);
+                            int32_t blocks, int32_t team_wgs, int32_t team_size, int32_t all, int64_t min_entries,
+                            BatchCtl* ctl, hipStream_t s);
 hipError_t launch_fill_u32(void* p, uint32_t v, size_t count, hipStream_t s);
 // Adds offsets[n] - offsets[0] - sum(core[0..n)) (the live decrements of a finished decomposition)
 // to *out.

@@ -336,7 +336,7 @@ void dispatcher(kcore_server* s) {
       int busy_large = 0;
       for (Slot* sl : s->slots)
         if (sl->busy && sl->large) ++busy_large;
-      const bool large_ok = s->slots.size() == 1 || busy_large + 1 < (int)s->slots.size();
+      const bool large_ok = s->slots.size() == 1 || busy_large < s->cfg.max_large_inflight;
       const bool large = large_ok && is_large(s->queue.front()->n, s->queue.front()->m);
       int64_t V = 0, bytes = 0;
       std::vector<Request*> take;
@@ -348,7 +348,7 @@ void dispatcher(kcore_server* s) {
         }
         if ((int64_t)take.size() >= s->cfg.max_batch_graphs) break;
         // (a large batch holds at most as many graphs as it has teams)
-        if (large && s->team_wgs > 0 && (int64_t)take.size() * kc::kTeamSize >= s->team_wgs) break;
+        if (large && s->team_wgs > 0 && ((int64_t)take.size() + 1) * kc::kTeamSize > s->team_wgs) break;
         if (!take.empty() && (r->solo || take.front()->solo)) break;
         if (!take.empty() && V + r->n > s->cfg.max_batch_vertices) break;
         if (s->bytes_in_use + bytes + r->bytes > s->cfg.hbm_budget_bytes) break;
@@ -413,7 +413,7 @@ kcore_server* kcore_server_create(const kcore_server_config* cfg) {
   if (cfg) c = *cfg;
   if (c.max_inflight < 0 || c.max_batch_graphs < 0 || c.max_batch_vertices < 0 || c.hbm_budget_bytes < 0 ||
       c.max_request_vertices < 0 || c.batch_wait_us < 0 || c.reserve_vertices < 0 || c.reserve_entries < 0 ||
-      c.reserved0 || c.reserved1) {
+      c.max_large_inflight < 0 || c.reserved1) {
     kc::set_error("negative server configuration field");
     return nullptr;
   }
@@ -422,6 +422,8 @@ kcore_server* kcore_server_create(const kcore_server_config* cfg) {
   if (!c.max_batch_vertices) c.max_batch_vertices = 1 << 24;
   if (!c.hbm_budget_bytes) c.hbm_budget_bytes = 8ll << 30;
   if (!c.batch_wait_us) c.batch_wait_us = 50;
+  if (!c.max_large_inflight) c.max_large_inflight = std::max(1, c.max_inflight / 4);
+  if (c.max_inflight > 1 && c.max_large_inflight >= c.max_inflight) c.max_large_inflight = c.max_inflight - 1;
   int ndev = 0;
   (void)hipGetLastError();  // an earlier, unrelated failure must not be reported as ours
   const hipError_t de = hipGetDeviceCount(&ndev);
@@ -440,9 +442,10 @@ kcore_server* kcore_server_create(const kcore_server_config* cfg) {
   s->t0 = std::chrono::steady_clock::now();
   s->log = getenv("KCORE_SERVER_LOG") != nullptr;
   {
+    // the team workgroups of all large batches in flight fit in half the device (the other half
+    // stays with the small batches); each team completes since nothing it waits for is blocked
     const int res = kc::batched_resident_wgs();
-    const int large_slots = c.max_inflight > 1 ? c.max_inflight - 1 : 1;
-    int tw = res / large_slots / kc::kTeamSize * kc::kTeamSize;
+    int tw = res / 2 / c.max_large_inflight / kc::kTeamSize * kc::kTeamSize;
     if (tw > kc::kMaxTeams * kc::kTeamSize) tw = kc::kMaxTeams * kc::kTeamSize;
     s->team_wgs = tw >= kc::kTeamSize ? tw : 0;
   }

@@ -416,22 +416,3 @@ def test_batched_teams_for_the_largest_graphs():
         assert not first_mismatch(got, want), first_mismatch(got, want)
         assert st["device_status"] == 0, st
         assert st["edges"] == len(adj), st
-
-
-@pytest.mark.parametrize("steal", [1, 8, 64])
-def test_work_stealing_does_not_change_results(steal):
-    """Chained scan phases with work stealing: hub tiles beyond the workgroup backlog go to the
-    shared queue that every workgroup drains (quiescence ends the phase). Every vertex must be
-    peeled once with the oracle's coreness, also with tiny hub thresholds (many tiles shared)."""
-    cases = [("rmat13", gg.rmat(13, 16, 7), {}), ("rmat16", gg.config_rmat16(), {}),
-             ("road256", gg.grid_road(256, 0.05, 0.01, 3), {}), ("hcns200", None, {}),
-             ("rmat13-small-tiles", gg.rmat(13, 16, 7), {"hub_degree": 16, "tile_edges": 64}),
-             ("rmat14-notail", gg.rmat(14, 32, 3), {"tail": -1})]
-    for name, g, kw in cases:
-        off, adj = (g.offsets, g.adj) if g is not None else G.hcns(200)
-        want = oracle.bz(off, adj)
-        say(f"[gpu] steal={steal} {name} {kw}")
-        got, st = run_single(off, adj, mode="chained", steal=steal, **kw)
-        assert not first_mismatch(got, want), first_mismatch(got, want)
-        assert st["peeled"] == len(off) - 1 and st["edges"] == len(adj), (name, st)
-        assert st["device_status"] == 0, (name, st)
