@@ -146,11 +146,22 @@ def build_workload(name: str):
     return torch.from_numpy(g.offsets).cuda(), torch.from_numpy(g.adj).cuda(), desc
 
 
+def tuned_for(off, batched=False, explicit=None):
+    """The autotuner's cached options for this device and the graph's class (explicit options
+    win), and the class name."""
+    import paper_2502_08042_amd.autotune as A
+    opts = {} if explicit else A.tuned_options(off, batched=batched)
+    return opts, A.workload_class(off, batched=batched)
+
+
 def measure_single(off, adj, steps, warmup, mode="auto", **tuning):
-    """Times kcore_decompose on a resident graph. Returns (result dict, stats, coreness tensor)."""
+    """Times kcore_decompose on a resident graph with the autotuner's options for its class (when
+    the cache has them and no option is given). Returns (result dict, stats, coreness tensor)."""
     import torch
     import paper_2502_08042_amd as K
     n, m = off.numel() - 1, adj.numel()
+    auto, cls = tuned_for(off, explicit=tuning)
+    tuning = {**auto, **tuning}
     out = torch.empty(n, dtype=torch.int32, device=off.device)
     K.decompose(off, adj, out, mode=mode, **tuning)  # workspace allocation, outside the timing
     _, st = K.decompose(off, adj, out, mode=mode, stats=True, **tuning)
@@ -165,8 +176,9 @@ def measure_single(off, adj, steps, warmup, mode="auto", **tuning):
            "live_decrements": st["live_decrements"], "scanned": st["scanned"],
            "bucket_inserts": st["bucket_inserts"],
            "alg_bytes": B, "hbm_frac": round(B / (ev["mean"] / 1000.0) / 1e9 / HBM_PEAK_GBS, 5)}
-    if tuning:
-        res["options"] = tuning
+    res["options"] = tuning
+    res["workload_class"] = cls
+    res["tuned"] = bool(auto)
     return res, st, out
 
 
@@ -190,7 +202,8 @@ def bench_chunglu(args):
         "data": "synthetic",
         "config": {"workload": desc, "n": n, "m": m, "mode": args.mode, "kmax": r["kmax"],
                    "rounds": r["rounds"], "subrounds": r["subrounds"], "barriers": r["barriers"],
-                   "tail_vertices": r["tail_vertices"]},
+                   "tail_vertices": r["tail_vertices"], "options": r["options"],
+                   "tuned": r["tuned"], "workload_class": r["workload_class"]},
         "gpu_event_ms": ev,
         # one decomposition = the persistent peel kernel, then the single-workgroup tail kernel on
         # the last live vertices (plus two tiny set-up kernels), all inside the events
@@ -287,11 +300,12 @@ def bench_batch(args, steps, warmup):
     adj = torch.from_numpy(b.adj).cuda()
     log(f"[bench] batch G={G} V={V} m={m} built in {time.time() - t0:.1f}s")
     out = torch.empty(V, dtype=torch.int32, device="cuda")
-    K.decompose_batched(vptr, off, adj, out)
-    _, st = K.decompose_batched(vptr, off, adj, out, stats=True)
+    topts, cls = tuned_for(off, batched=True)
+    K.decompose_batched(vptr, off, adj, out, **topts)
+    _, st = K.decompose_batched(vptr, off, adj, out, stats=True, **topts)
     want = oracle.bz(b.offsets, b.adj)
     parity = bool(np.array_equal(out.cpu().numpy(), want))
-    wall_ms, per = timed_calls(lambda: K.decompose_batched(vptr, off, adj, out), steps, warmup)
+    wall_ms, per = timed_calls(lambda: K.decompose_batched(vptr, off, adj, out, **topts), steps, warmup)
     K.check()
     ev = summary(per)
     # the same graphs, one single-graph call each (local ids)
@@ -318,7 +332,7 @@ def bench_batch(args, steps, warmup):
            "event_ms": ev, "graphs_per_s": round(G / (wall_ms / 1000.0), 1),
            "gteps": round(m / (wall_ms / 1000.0) / 1e9, 4),
            "per_graph_loop_ms": round(ms_loop, 3), "speedup_vs_loop": round(ms_loop / wall_ms, 2),
-           "parity": parity and loop_parity,
+           "parity": parity and loop_parity, "options": topts, "tuned": bool(topts), "workload_class": cls,
            "roofline": {"bound": "hbm", "achieved": round(B / (ev["mean"] / 1000.0) / 1e9, 2),
                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": round(B / (ev["mean"] / 1000.0) / 1e9 / HBM_PEAK_GBS, 5),

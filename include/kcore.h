@@ -150,7 +150,8 @@ typedef struct {
                             part of this header); 0 = off */
   int64_t test_tail_entries; /* testing: pretend the tail's local rows hold at most this many
                             entries, so that handoffs are called off and retried; 0 = off */
-  int32_t team_size;     /* batched peel: workgroups per team (see batch_teams); 0 = default (4),
+  int32_t team_size;     /* batched peel: workgroups per team (see batch_teams); 0 = default (the
+                            teams share a quarter of the grid equally, 8 to 32 workgroups each),
                             at most 32 */
   int32_t batch_teams;   /* batched peel (level-sync): a graph with more adjacency entries than this
                             is peeled by a team of workgroups; 0 = default (half a workgroup's

@@ -46,6 +46,8 @@ SINGLE_SPACE = {
 BATCHED_SPACE = {
     "mode": ["levelsync", "chained"],
     "blocks_per_cu": [0, 1],
+    "team_size": [0, 8, 16],
+    "batch_teams": [0, -1, 200000],
 }
 
 
@@ -99,7 +101,9 @@ def tuned_options(offsets, batched: bool = False, path: str = DEFAULT_CACHE) -> 
     ent = cache.get(device_key(), {}).get(workload_class(offsets, batched))
     if not ent:
         return {}
-    return _resolve(ent["options"], offsets.numel() - 1)
+    # (only what differs from the library defaults)
+    return {k: v for k, v in _resolve(ent["options"], offsets.numel() - 1).items()
+            if v != 0 and v != "levelsync"}
 
 
 def _time_single(off, adj, opts, reps):

@@ -841,8 +841,8 @@ static int batched_impl(const int64_t* graph_vptr, const int64_t* offsets, const
   int bpc = di.batch_bpc;
   if (opt && opt->blocks_per_cu && opt->blocks_per_cu < bpc) bpc = opt->blocks_per_cu;
   if (bpc < 1) return fail(KCORE_EDEVICE, "batched kernel cannot be resident on this device");
-  int blocks = bpc * di.cus;
-  if (num_graphs < blocks) blocks = num_graphs;
+  const int blocks_full = bpc * di.cus;
+  int blocks = std::min(blocks_full, num_graphs);
 
   HIP_TRY(kc::launch_fill_u32(w->ctl, 0u, sizeof(kc::BatchCtl) / 4, stream));
   if (KCORE_CHECKS) HIP_TRY(kc::launch_fill_u32(coreness_out, 0xffffffffu, (size_t)total_vertices, stream));
@@ -870,16 +870,19 @@ static int batched_impl(const int64_t* graph_vptr, const int64_t* offsets, const
   // large batches (team_wgs > 0) put every graph in a team, in a grid of only the team workgroups
   // whose total over its concurrent batches it keeps within what the device holds.
   const int32_t bt = opt ? opt->batch_teams : 0;
-  const bool coop_teams = !local_ids && !a.chained && bt >= 0 && blocks >= 4 * kc::kTeamSize &&
+  // (the grid is then the full resident size, whatever the number of graphs: spare workgroups
+  // form the teams)
+  const bool coop_teams = !local_ids && !a.chained && bt >= 0 && blocks_full >= 4 * kc::kTeamSize &&
                           !(opt && opt->blocks_per_cu);
-  a.team_size = (opt && opt->team_size) ? opt->team_size : kc::kTeamSize;
-  const bool serve_teams = local_ids && team_wgs >= a.team_size;
+  const int32_t tsz = opt ? opt->team_size : 0;
+  const bool serve_teams = local_ids && team_wgs >= kc::kTeamSize;
   a.teams = (coop_teams || serve_teams) ? 1 : 0;
-  if (serve_teams) blocks = std::min(blocks, std::min(team_wgs, num_graphs * a.team_size));
+  if (coop_teams) blocks = blocks_full;
+  if (serve_teams) blocks = std::min(blocks_full, team_wgs);
   if (a.teams)
     // (a caller's batch keeps three quarters of its workgroups for the many small graphs)
     HIP_TRY(kc::launch_team_plan(graph_vptr, offsets, num_graphs, w->order, blocks,
-                                 serve_teams ? blocks : blocks / 4, a.team_size, serve_teams ? 1 : 0,
+                                 serve_teams ? blocks : blocks / 4, tsz, serve_teams ? 1 : 0,
                                  bt > 0 ? bt : 0, w->ctl, stream));
   if (stats_host) HIP_TRY(hipEventRecord(w->ev0, stream));
   if (coop_teams) {

@@ -1991,7 +1991,7 @@ __device__ __forceinline__ void team_peel(const BatchArgs& a, int team, int memb
   uint32_t* d = a.gdt + base;
   int32_t* q = a.gq + base;
   const int tid = threadIdx.x, l = lane_id(), w = threadIdx.x >> 6;
-  const int tsz = a.team_size;
+  const int tsz = (int)a.ctl->team_size;
   const long long gtid = (long long)member * kBatchThreads + tid;
   const long long GT = (long long)tsz * kBatchThreads;
   unsigned epoch = 0;
@@ -2110,9 +2110,10 @@ __global__ __launch_bounds__(kBatchThreads) void batched_kernel(BatchArgs a) {
   const int tid = threadIdx.x, l = lane_id(), w = threadIdx.x >> 6;
   // the leading nteams graphs of the order are peeled by teams of the first workgroups
   const int nteams = a.teams ? (int)a.ctl->nteams : 0;
-  if ((int)blockIdx.x < nteams * a.team_size)
-    team_peel(a, blockIdx.x / a.team_size, blockIdx.x % a.team_size, s_pref, s_rb, s_w, s_min, st_edges, st_decr,
-              st_rounds, st_sub, st_scanned, kmax_all);
+  const int tsz = a.teams ? (int)a.ctl->team_size : 1;
+  if ((int)blockIdx.x < nteams * tsz)
+    team_peel(a, blockIdx.x / tsz, blockIdx.x % tsz, s_pref, s_rb, s_w, s_min, st_edges, st_decr, st_rounds, st_sub,
+              st_scanned, kmax_all);
 
   for (;;) {
     if (tid == 0) s_g = (long long)aadd(&a.ctl->next, 1ull) + nteams;
@@ -2318,7 +2319,9 @@ hipError_t launch_batched_coop(const BatchArgs& a, int blocks, size_t lds_bytes,
 // with more entries than min_entries (default: half a workgroup's average share of the batch; every
 // leading graph when `all`) get a team; at most kMaxTeams, and at most team_wgs workgroups in teams.
 // One workgroup peels a graph held in global memory several times slower per entry than the
-// LDS-resident small graphs that make up most of a batch, hence the low default threshold.
+// LDS-resident small graphs that make up most of a batch, hence the low default threshold. Teams
+// have team_size workgroups, or (team_size 0) an equal share of team_wgs, at least kTeamSize and
+// at most kMaxTeamSize, so that a few huge graphs get large teams and many big ones teams of 8.
 __global__ __launch_bounds__(64) void team_plan_kernel(const int64_t* vptr, const int64_t* off, int32_t G,
                                                        const int32_t* order, int32_t blocks, int32_t team_wgs,
                                                        int32_t team_size, int32_t all, long long min_entries,
@@ -2327,14 +2330,18 @@ __global__ __launch_bounds__(64) void team_plan_kernel(const int64_t* vptr, cons
   const long long total = off[vptr[G]] - off[vptr[0]];
   const long long share = total / (blocks > 0 ? blocks : 1);
   const long long thr = min_entries > 0 ? min_entries : share / 2;
-  int nt = 0;
-  while (nt < kMaxTeams && nt < G && (nt + 1) * team_size <= team_wgs) {
-    const int32_t g = order[nt];
+  int want = 0;
+  while (want < kMaxTeams && want < G) {
+    const int32_t g = order[want];
     const long long e = off[vptr[g + 1]] - off[vptr[g]];
     if (!all && e <= thr) break;
-    ++nt;
+    ++want;
   }
+  int ts = team_size;
+  if (ts <= 0) ts = want > 0 ? max(kTeamSize, min(kMaxTeamSize, team_wgs / want)) : kTeamSize;
+  int nt = min(want, team_wgs / ts);
   ctl->nteams = (unsigned)nt;
+  ctl->team_size = (unsigned)ts;
 }
 
 hipError_t launch_team_plan(const int64_t* vptr, const int64_t* off, int32_t G, const int32_t* order,

@@ -183,7 +183,8 @@ struct BatchCtl {
   unsigned long long next;
   unsigned int status;
   unsigned int nteams;    // leading graphs of the processing order peeled by teams
-  unsigned int pad[28];
+  unsigned int team_size; // workgroups per team
+  unsigned int pad[27];
   unsigned long long stats[kStatWords];
   TeamCtl team[kMaxTeams];
 };
@@ -202,9 +203,9 @@ struct BatchArgs {
   BatchCtl* ctl;
   int32_t lds_cap;        // vertices per graph held in LDS
   int32_t chained;        // 1: each round is peeled through a dynamic workgroup queue (no subround barriers)
-  int32_t teams;          // 1: the plan kernel may give the largest graphs a team of team_size
-                          // workgroups (teams wait for each other: see the launch)
-  int32_t team_size;
+  int32_t teams;          // 1: the plan kernel may give the largest graphs teams of workgroups (it
+                          // writes ctl->nteams and ctl->team_size; teams wait for each other: see
+                          // the launch)
 };
 
 // Error text returned by kcore_last_error (thread-local; defined in kcore_api.cpp).
@@ -235,8 +236,8 @@ hipError_t batched_occupancy(size_t lds_bytes, int* blocks_per_cu);
 hipError_t launch_order(const int64_t* vptr, const int64_t* off, int32_t G, int32_t* order,
                         hipStream_t s);
 // Picks the leading graphs of `order` whose entries exceed half a workgroup's average share
-// (blocks workgroups; every leading graph when `all`) for teams of kTeamSize workgroups, using at
-// most team_wgs workgroups; writes ctl->nteams.
+// (blocks workgroups; every leading graph when `all`) for teams of team_size workgroups (0: sized
+// from team_wgs), using at most team_wgs workgroups; writes ctl->nteams and ctl->team_size.
 // min_entries > 0 replaces the size rule: graphs with more entries than that get teams.
 hipError_t launch_team_plan(const int64_t* vptr, const int64_t* off, int32_t G, const int32_t* order,
                             int32_t blocks, int32_t team_wgs, int32_t team_size, int32_t all, int64_t min_entries,
