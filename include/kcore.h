@@ -235,6 +235,20 @@ int kcore_decompose_batched_ex(const int64_t* graph_vptr, const int64_t* offsets
                                int32_t* coreness_out, hipStream_t stream, const kcore_options* opt,
                                kcore_stats* stats_host);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): kcore_decompose_batched without any allocation. Same
+ * arguments, layout and result as kcore_decompose_batched (level-sync mode); its workspace is a
+ * device array inside the library, one per GPU, held until the process ends: 12.8 MB for at most
+ * 2^20 vertices and 2^16 graphs per call (larger batches: KCORE_ETOOBIG, nothing enqueued). Every
+ * call on a GPU shares that GPU's array, so calls that overlap on one GPU (from several streams
+ * or threads) race and must be serialised by the caller. The control block is cleared by a kernel
+ * at the start of each call (no memset node), so the call can be captured into a graph.
+ *   status_out  nullable, device or pinned host memory: receives the device status word (0 =
+ *               success) when `stream` reaches the end of the call */
+int kcore_decompose_batched_noalloc(const int64_t* graph_vptr, const int64_t* offsets, const int32_t* adj,
+                                    int32_t num_graphs, int64_t total_vertices, int32_t* coreness_out,
+                                    uint32_t* status_out, hipStream_t stream);
+
 /* Frees every cached workspace after synchronising the device. */
 int kcore_release_workspaces(void);
 

@@ -100,6 +100,7 @@ SIGNATURES = {
     "kcore_kcore_subgraph": (ctypes.c_int, [P, P, I64, I32, P, P, ctypes.POINTER(Options),
                                             ctypes.POINTER(Stats)]),
     "kcore_decompose_batched": (ctypes.c_int, [P, P, P, I32, I64, P, P]),
+    "kcore_decompose_batched_noalloc": (ctypes.c_int, [P, P, P, I32, I64, P, P, P]),
     "kcore_decompose_batched_ex": (ctypes.c_int, [P, P, P, I32, I64, P, P, ctypes.POINTER(Options),
                                                   ctypes.POINTER(Stats)]),
     "kcore_release_workspaces": (ctypes.c_int, []),

@@ -915,7 +915,91 @@ static int batched_impl(const int64_t* graph_vptr, const int64_t* offsets, const
   return KCORE_OK;
 }
 
+// ---- no-allocation batched entry point ---------------------------------------------------
+// Its workspace is a file-scope device array (one per GPU, alive until the process ends): the
+// control block, the largest-first order of the graphs and the global induced degrees, peel
+// queues and active lists of graphs beyond the LDS capacity. Host code reaches it only through
+// the address hipGetSymbolAddress reports for the current device.
+namespace {
+constexpr int64_t kNoAllocVertices = 1ll << 20;  // vertices per call at most
+constexpr int32_t kNoAllocGraphs = 1 << 16;      // graphs per call at most
+constexpr size_t kNoAllocCtlBytes = (sizeof(kc::BatchCtl) + 255) / 256 * 256;
+constexpr size_t kNoAllocOrderOff = kNoAllocCtlBytes;
+constexpr size_t kNoAllocStateOff = kNoAllocOrderOff + 4 * (size_t)kNoAllocGraphs;
+constexpr size_t kScratchBytes = kNoAllocStateOff + 3 * 4 * (size_t)kNoAllocVertices;
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, unsigned char*> g_scratch;  // device -> device address of that device's scratch
+
+// Device address of the current device's scratch array, looked up once per device.
+int scratch_ptr(int dev, unsigned char*& out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch.find(dev);
+  if (it != g_scratch.end()) {
+    out = it->second;
+    return KCORE_OK;
+  }
+  void* ptr = nullptr;
+  HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+  if (!ptr) return fail(KCORE_EDEVICE, "no device address for the scratch array on device %d", dev);
+  out = static_cast<unsigned char*>(ptr);
+  g_scratch[dev] = out;
+  return KCORE_OK;
+}
+}  // namespace
+
 extern "C" {
+
+int kcore_decompose_batched_noalloc(const int64_t* graph_vptr, const int64_t* offsets, const int32_t* adj,
+                                    int32_t num_graphs, int64_t total_vertices, int32_t* coreness_out,
+                                    uint32_t* status_out, hipStream_t stream) {
+  g_err.clear();
+  if (num_graphs < 0 || total_vertices < 0) return fail(KCORE_EINVAL, "negative num_graphs or total_vertices");
+  if (total_vertices > kNoAllocVertices || num_graphs > kNoAllocGraphs)
+    return fail(KCORE_ETOOBIG, "the no-allocation call takes at most %lld vertices and %d graphs (got %lld, %d)",
+                (long long)kNoAllocVertices, kNoAllocGraphs, (long long)total_vertices, num_graphs);
+  if (num_graphs == 0 || total_vertices == 0) return KCORE_OK;
+  if (!graph_vptr || !offsets || !adj || !coreness_out) return fail(KCORE_EINVAL, "null pointer argument");
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  DevInfo di;
+  if (int rc = dev_info(dev, di)) return rc;
+  unsigned char* sp = nullptr;
+  if (int rc = scratch_ptr(dev, sp)) return rc;
+  const int32_t cap = (int32_t)(di.batch_lds / 8);
+  const int bpc = di.batch_bpc;
+  if (bpc < 1) return fail(KCORE_EDEVICE, "batched kernel cannot be resident on this device");
+  const int blocks = std::min(bpc * di.cus, num_graphs);
+  kc::BatchCtl* ctl = reinterpret_cast<kc::BatchCtl*>(sp);
+  // the control block starts at zero in every call (a fill kernel, not a memset node)
+  HIP_TRY(kc::launch_fill_u32(ctl, 0u, sizeof(kc::BatchCtl) / 4, stream));
+  if (KCORE_CHECKS) HIP_TRY(kc::launch_fill_u32(coreness_out, 0xffffffffu, (size_t)total_vertices, stream));
+  int32_t* order = reinterpret_cast<int32_t*>(sp + kNoAllocOrderOff);
+  HIP_TRY(kc::launch_order(graph_vptr, offsets, num_graphs, order, stream));
+  kc::BatchArgs a;
+  a.vptr = graph_vptr;
+  a.off = offsets;
+  a.adj = adj;
+  a.G = num_graphs;
+  a.core = coreness_out;
+  a.order = order;
+  a.gdt = reinterpret_cast<uint32_t*>(sp + kNoAllocStateOff);
+  a.gq = reinterpret_cast<int32_t*>(sp + kNoAllocStateOff + 4 * (size_t)kNoAllocVertices);
+  a.ga = reinterpret_cast<int32_t*>(sp + kNoAllocStateOff + 8 * (size_t)kNoAllocVertices);
+  a.local_ids = 0;
+  a.ctl = ctl;
+  a.lds_cap = cap;
+  a.chained = 0;
+  a.teams = 0;  // (teams need the ordered cooperative launch, whose event the library allocates)
+  HIP_TRY(kc::launch_batched(a, blocks, di.batch_lds, stream));
+  if (status_out)
+    HIP_TRY(hipMemcpyAsync(status_out, &ctl->status, sizeof(unsigned), hipMemcpyDefault, stream));
+  return KCORE_OK;
+}
 
 int kcore_decompose_batched(const int64_t* graph_vptr, const int64_t* offsets, const int32_t* adj,
                             int32_t num_graphs, int64_t total_vertices, int32_t* coreness_out,
