@@ -387,7 +387,8 @@ def bench_serve(args, seconds: float = 5.0, rate: float = 20000.0, warm: float =
     log(f"[bench] serving {nreq} requests over {arrivals[-1] / 1e6:.1f}s, {int(is_big.sum())} large")
     # four slots, one per hardware queue of the process (streams beyond that share queues, and a
     # small batch would wait behind a large one); slot buffers sized up front for full small batches
-    srv = K.Server(device=0, max_inflight=4, hbm_budget_bytes=64 << 30, max_batch_vertices=1 << 25,
+    server_kw.setdefault("max_inflight", 4)
+    srv = K.Server(device=0, hbm_budget_bytes=64 << 30, max_batch_vertices=1 << 25,
                    borrow_inputs=True, reserve_vertices=1 << 24, reserve_entries=160 << 20, **server_kw)
     tickets = [None] * nreq
     results = {}
@@ -427,12 +428,16 @@ def bench_serve(args, seconds: float = 5.0, rate: float = 20000.0, warm: float =
     done_evt.wait()
     srv.close()
     lat = np.empty(nreq)
+    wait = np.empty(nreq)    # arrival -> admitted into a batch (host queue)
+    dev = np.empty(nreq)     # batch enqueued -> result visible (copies and the peel on the device)
     ok = True
     last_done = 0.0
     batches = {}
     for i in range(nreq):
         core, (admit_us, launch_us, done_us, bid, bg) = results[i]
         lat[i] = done_us - (t0 + arrivals[i])
+        wait[i] = admit_us - (t0 + arrivals[i])
+        dev[i] = done_us - launch_us
         want = want_big[pick[i] % 2] if is_big[i] else want_small[pick[i]]
         ok = ok and bool(np.array_equal(core, want))
         if arrivals[i] < warm * 1e6:
@@ -441,7 +446,7 @@ def bench_serve(args, seconds: float = 5.0, rate: float = 20000.0, warm: float =
         batches[bid] = (bool(is_big[i]), bg, launch_us - admit_us, done_us - launch_us)
     meas = arrivals >= warm * 1e6
     nmeas = int(meas.sum())
-    lat, is_big = lat[meas], is_big[meas]
+    lat, wait, dev, is_big = lat[meas], wait[meas], dev[meas], is_big[meas]
     span_s = (last_done - (t0 + warm * 1e6)) / 1e6
     per_class = {}
     for cls, name in ((False, "small"), (True, "large")):
@@ -461,6 +466,8 @@ def bench_serve(args, seconds: float = 5.0, rate: float = 20000.0, warm: float =
         "p99_ms": round(float(np.percentile(lat, 99)) / 1000, 3),
         "p99_small_ms": round(float(np.percentile(lat[~is_big], 99)) / 1000, 3),
         "p99_large_ms": round(float(np.percentile(lat[is_big], 99)) / 1000, 3) if is_big.any() else None,
+        "p99_small_wait_ms": round(float(np.percentile(wait[~is_big], 99)) / 1000, 3),
+        "p99_small_device_ms": round(float(np.percentile(dev[~is_big], 99)) / 1000, 3),
         "batches": per_class, "parity": ok,
     }
 

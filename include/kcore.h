@@ -153,6 +153,12 @@ typedef struct {
   int32_t team_size;     /* batched peel: workgroups per team (see batch_teams); 0 = default (the
                             teams share a quarter of the grid equally, 8 to 32 workgroups each),
                             at most 32 */
+  int32_t combine_degree;/* chained and level-sync modes: in large phases, decrements of vertices of at
+                            least this degree are combined in the workgroup's LDS table and applied
+                            once per target; 0 = default (max(1024, hub_degree)) */
+  int32_t big_phase;     /* frontier size (entries of small vertices plus 16 per hub tile) from
+                            which a phase probes peeled bits before decrementing and combines; 0 =
+                            default (16384) */
   int32_t batch_teams;   /* batched peel (level-sync): a graph with more adjacency entries than this
                             is peeled by a team of workgroups; 0 = default (half a workgroup's
                             average share of the batch's entries), -1 = never */
@@ -277,7 +283,7 @@ typedef struct {
   int32_t max_large_inflight;  /* batches of large requests (>= 2^21 entries or 2^16 vertices) in
                                   flight at once, each graph of them peeled by a team of workgroups
                                   within half the device; the other slots serve small requests
-                                  (0 = max_inflight / 4, at least 1, below max_inflight) */
+                                  (0 = max_inflight / 2, at least 1, below max_inflight) */
   int64_t max_batch_vertices;  /* vertices per batch (0 = 1 << 24) */
   int64_t hbm_budget_bytes;    /* device bytes all in-flight batches may hold (0 = 8 GiB) */
   int64_t max_request_vertices;/* larger requests are rejected with KCORE_ETOOBIG (0 = no limit) */

@@ -53,7 +53,7 @@ class Options(ctypes.Structure):
                 ("residual", ctypes.c_int32), ("tail", ctypes.c_int32),
                 ("buckets", ctypes.c_int32), ("sample_threshold", ctypes.c_int32),
                 ("sample_mu", ctypes.c_int32), ("debug_phase", ctypes.c_int32),
-                ("test_tail_entries", ctypes.c_int64), ("team_size", ctypes.c_int32),
+                ("test_tail_entries", ctypes.c_int64), ("team_size", ctypes.c_int32), ("combine_degree", ctypes.c_int32), ("big_phase", ctypes.c_int32),
                 ("batch_teams", ctypes.c_int32), ("status_out", ctypes.c_void_p)]
 
 
@@ -197,7 +197,8 @@ def _stream_ptr(stream) -> int:
 def _options(mode, validate, num_entries, hub_degree=0, local_budget=0, tile_edges=0,
              blocks_per_cu=0, async_frontier=0, async_scan=0, block_tiles=0,
              block_queue=0, tile_probe=0, residual=0, tail=0, buckets=0, sample_threshold=0,
-             sample_mu=0, debug_phase=0, test_tail_entries=0, team_size=0, batch_teams=0, status_out=None) -> Options:
+             sample_mu=0, debug_phase=0, test_tail_entries=0, team_size=0, combine_degree=0, big_phase=0, batch_teams=0,
+             status_out=None) -> Options:
     o = Options()
     o.mode = MODES[mode] if isinstance(mode, str) else int(mode)
     o.validate = 1 if validate else 0
@@ -219,6 +220,8 @@ def _options(mode, validate, num_entries, hub_degree=0, local_budget=0, tile_edg
     o.debug_phase = debug_phase
     o.test_tail_entries = test_tail_entries
     o.team_size = team_size
+    o.combine_degree = combine_degree
+    o.big_phase = big_phase
     o.batch_teams = batch_teams
     o.status_out = status_out
     return o

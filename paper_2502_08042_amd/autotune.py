@@ -42,6 +42,8 @@ SINGLE_SPACE = {
     "residual": [0, -1, "n/64", "n/1024"],
     "tail": [0, -1, "n/32", "n/2"],
     "buckets": [0, "n"],
+    "combine_degree": [0, 256, 4096],
+    "big_phase": [0, 4096, 65536],
 }
 BATCHED_SPACE = {
     "mode": ["levelsync", "chained"],

@@ -418,6 +418,7 @@ int check_opts(const kcore_options* o) {
     return fail(KCORE_EINVAL, "async and block-tile thresholds must be >= -1");
   if (o->buckets < -1) return fail(KCORE_EINVAL, "buckets must be >= -1");
   if (o->batch_teams < -1) return fail(KCORE_EINVAL, "batch_teams must be >= -1");
+  if (o->combine_degree < 0 || o->big_phase < 0) return fail(KCORE_EINVAL, "combine_degree and big_phase must be >= 0");
   if (o->team_size < 0 || o->team_size > kc::kMaxTeamSize)
     return fail(KCORE_EINVAL, "team_size must be in [0, %d]", kc::kMaxTeamSize);
   if (o->sample_threshold < 0 || o->sample_mu < 0 || o->debug_phase < 0 || o->test_tail_entries < 0)
@@ -567,11 +568,12 @@ static int peel_impl(const int64_t* offsets, const int32_t* adj, int64_t n, int3
   a.ctl = w->ctl;
   a.hub = hub;
   // offline mode: every target is combined (Alg. 2's histogram, per workgroup), in every phase
-  a.comb_degree = offline ? 0u : (hub > 1024u ? hub : 1024u);
+  a.comb_degree = offline ? 0u
+                          : (opt && opt->combine_degree) ? (uint32_t)opt->combine_degree : (hub > 1024u ? hub : 1024u);
   a.tile = tile;
   a.chained = (mode == KCORE_MODE_CHAINED || sampling) ? 1 : 0;
   a.lq_budget = budget;
-  a.big_phase = offline ? 0 : 16384;
+  a.big_phase = offline ? 0 : ((opt && opt->big_phase) ? opt->big_phase : 16384);
   a.aq = w->aq;
   // this call's share of the work queue (the cached workspace may be larger)
   a.qcap = std::min<int64_t>(w->q_cap, n + tcap + 256 * 64 * 64);

@@ -218,9 +218,9 @@ int reserve_batched(hipStream_t stream, int64_t V, int32_t G);
 // Frees the batched-peel workspace of (current device, stream), if any (before the stream goes).
 void release_batched(hipStream_t stream);
 // team_wgs > 0: every graph of the batch (up to kMaxTeams, within team_wgs workgroups) is peeled
-// by a team, in a grid of team_wgs workgroups launched without co-residency guarantee; the caller
-// keeps the team workgroups of all such batches that may run at once within what the device holds
-// resident (other kernels' workgroups do not wait on anything, so teams then always complete).
+// by a team, in a grid launched without co-residency guarantee; the caller keeps the team
+// workgroups of all such batches that may run at once within what the device holds resident (other
+// workgroups do not wait on anything, so teams then always complete).
 int decompose_batched_local(const int64_t* graph_vptr, const int64_t* offsets, const int32_t* adj,
                             int32_t num_graphs, int64_t total_vertices, int32_t* coreness_out,
                             hipStream_t stream, unsigned* status_out, int32_t team_wgs = 0);

@@ -110,8 +110,8 @@ struct kcore_server {
   int64_t next_batch = 1;
   bool stop = false;
   bool log = false;  // KCORE_SERVER_LOG set: one line per batch on stderr
-  // workgroups a large batch may put in teams: the team workgroups of all large batches that can
-  // run at once (every slot but one) fit on the device together, so their teams always complete
+  // workgroups a large batch puts in teams (every graph of it in a team): the team workgroups of all
+  // large batches in flight fit in half the device, so every team completes
   int32_t team_wgs = 0;
   std::thread th;
 
@@ -422,7 +422,7 @@ kcore_server* kcore_server_create(const kcore_server_config* cfg) {
   if (!c.max_batch_vertices) c.max_batch_vertices = 1 << 24;
   if (!c.hbm_budget_bytes) c.hbm_budget_bytes = 8ll << 30;
   if (!c.batch_wait_us) c.batch_wait_us = 50;
-  if (!c.max_large_inflight) c.max_large_inflight = std::max(1, c.max_inflight / 4);
+  if (!c.max_large_inflight) c.max_large_inflight = std::max(1, c.max_inflight / 2);
   if (c.max_inflight > 1 && c.max_large_inflight >= c.max_inflight) c.max_large_inflight = c.max_inflight - 1;
   int ndev = 0;
   (void)hipGetLastError();  // an earlier, unrelated failure must not be reported as ours

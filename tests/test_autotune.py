@@ -39,3 +39,20 @@ def test_descent_keeps_only_exact_and_faster_candidates():
     assert best["a"] != 2
     assert best["b"] == 7 and best_ms == 0.5
     assert any(t.get("exact") is False for t in trials)
+
+
+def test_shipped_cache_names_only_known_options():
+    """The cache that ships with the package: every entry's options are fields the binding passes
+    to the library (single graph: kcore_options; batched: the batched call's keywords)."""
+    import paper_2502_08042_amd as K
+    cache = A.load_cache()
+    fields = {f for f, _ in K.Options._fields_}
+    batched_kw = {"mode", "blocks_per_cu", "team_size", "batch_teams"}
+    for dev, classes in cache.items():
+        for cls, ent in classes.items():
+            keys = set(ent["options"])
+            if cls.startswith("batched/"):
+                assert keys <= batched_kw, (dev, cls, keys)
+            else:
+                assert keys <= fields, (dev, cls, keys - fields)
+            assert ent["ms"] <= ent["default_ms"] + 1e-9, (dev, cls)
