@@ -2367,6 +2367,22 @@ hipError_t batched_occupancy(size_t lds_bytes, int* blocks_per_cu) {
 // degree == k picks the round's first frontier. The queue holds vertices in peel order; a
 // subround's frontier is the queue segment between two marks.
 // ------------------------------------------------------------------------------------------
+// A tail vertex's coreness is recorded when its row is claimed (every peeled vertex is claimed
+// exactly once, in the round that peels it), as -(k + 1) in the end word of its local row bounds,
+// which nothing reads after the claim; one pass at the end of the tail peel moves the recorded
+// values to the output. So no store on the peel's critical path waits for the local-to-global id
+// lookup. Returns the row end read before the overwrite.
+__device__ __forceinline__ long long tail_claim(const PeelArgs& a, int32_t v, uint32_t k) {
+  long long* p = &a.trow[2 * (long long)v + 1];
+  const long long e = *p;
+  if (KCORE_CHECKS && e < 0) {  // claimed twice
+    aor(&a.ctl->status, (unsigned)KC_ERR_CHECK);
+    return p[-1];
+  }
+  *p = -(long long)k - 1;
+  return e;
+}
+
 // Decrements of the induced degrees of N neighbours per lane (local ids; a lane with no entry
 // passes L + lane, a private spare slot past the vertices, so that no lane branches). A vertex
 // peeled before is at or below k and stays there, and every neighbour decrements it once, so its
@@ -2391,7 +2407,6 @@ __device__ __forceinline__ void tail_edges(const PeelArgs& a, uint32_t* d, uint1
     const bool crossed = (cm >> j) & 1u;
     const unsigned long long m = __ballot(crossed);
     if (!m) continue;
-    if (crossed) put_core(a.core, a.tgid[u[j]], k, &a.ctl->status);
     int b = 0;
     if (lane_id() == 0) b = atomicAdd(s_tail, __popcll(m));
     b = __shfl(b, 0, 64);
@@ -2425,7 +2440,6 @@ __device__ __forceinline__ void tail_edges16(const PeelArgs& a, uint32_t* d, uin
     const unsigned long long m = __ballot(crossed);
     if (!m) continue;
     const int32_t u = (int32_t)((w[e >> 1] >> (16 * (e & 1))) & 0xffffu);
-    if (crossed) put_core(a.core, a.tgid[u], k, &a.ctl->status);
     int b = 0;
     if (lane_id() == 0) b = atomicAdd(s_tail, __popcll(m));
     b = __shfl(b, 0, 64);
@@ -2569,7 +2583,7 @@ __device__ __forceinline__ bool tail_chain(const PeelArgs& a, uint32_t* d, uint1
     int rb = 0, dg = 0;
     if (v >= 0) {
       rb = (int)a.trow[2 * (long long)v];
-      dg = (int)(a.trow[2 * (long long)v + 1] - rb);
+      dg = (int)(tail_claim(a, v, k) - rb);
     }
     // once every local vertex is queued, the rows still waiting can only decrement peeled vertices
     // (the last round of a dense core queues all of it after a fraction of its rows): they count
@@ -2588,7 +2602,7 @@ __device__ __forceinline__ bool tail_chain(const PeelArgs& a, uint32_t* d, uint1
       const int tincl = wave_incl_scan(nt);
       const int ttot = __shfl(tincl, 63, 64);
       int base = -1;
-      if (l == 0) {
+      if (l == 0 && ttot > 1) {  // (a single tile is streamed by the wave that holds it)
         for (;;) {
           const int rt = lds_ld(s_rtail);
           if (rt + ttot - lds_ld(s_rclaim) > kTailRing) break;
@@ -2746,7 +2760,6 @@ __global__ __launch_bounds__(kTailThreads) void tail_kernel(PeelArgs a, int32_t 
         const int i = i0 + r * kTailThreads + tid;
         const bool ext = i < L && x[r] == k;
         if (x[r] > k) nm = min(nm, x[r]);
-        if (ext) put_core(a.core, a.tgid[i], k, &a.ctl->status);
         team_push(ext, i, q, &s_tail);
       }
     }
@@ -2797,7 +2810,7 @@ __global__ __launch_bounds__(kTailThreads) void tail_kernel(PeelArgs a, int32_t 
         if (i < tail) {
           const int32_t v = (int32_t)q[i];
           rb = (int)rows[2 * (long long)v];
-          dg = (int)(rows[2 * (long long)v + 1] - rb);
+          dg = (int)(tail_claim(a, v, k) - rb);
         }
         const bool big = dg >= kTailBig;
         int total, tiles;
@@ -2850,6 +2863,13 @@ __global__ __launch_bounds__(kTailThreads) void tail_kernel(PeelArgs a, int32_t 
     }
     if (tail >= L) break;
     k = k + 1;
+  }
+  // every local vertex has been claimed: its coreness goes to the output
+  __syncthreads();
+  for (int i = tid; i < L; i += kTailThreads) {
+    const long long x = a.trow[2 * (long long)i + 1];
+    if (KCORE_CHECKS && x >= 0) aor(&a.ctl->status, (unsigned)KC_ERR_CHECK);  // never claimed
+    put_core(a.core, a.tgid[i], (uint32_t)(-x - 1), &a.ctl->status);
   }
   // statistics: the tail's share of the decomposition's counters (its decrements are LDS
   // operations, not counted with the global ones)
