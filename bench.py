@@ -31,6 +31,10 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+# The serving workload keeps one batch slot per hardware queue of the process; HIP gives a process
+# four unless told otherwise when it initialises (streams beyond that share queues, so a small
+# batch could wait behind a large one). Eight slots: two for large batches, six for small ones.
+os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
 
 METRIC = "peeled directed edges/sec (GTEPS) + % HBM peak; batched graphs/sec & p99 latency"
 HBM_PEAK_GBS = 8000.0
@@ -339,9 +343,37 @@ def bench_batch(args, steps, warmup):
                         "traffic": traffic_from_profile("batched_kernel_batch4096_traffic.txt", "auto"),
                         "alg_bytes_per_launch": B, "kernel": "batched_kernel",
                         "kernel_ms_per_launch": ev["mean"]}}
+    # where the launch's time goes: the same call on the graphs of one size class alone
+    ns = np.diff(b.vptr)
+    res["by_size"] = {}
+    for name, sel in (("n<=9152 (LDS-resident)", ns <= 9152), ("n>9152", ns > 9152), ("n>20000", ns > 20000)):
+        sv, so, sa = sub_batch(b, np.flatnonzero(sel))
+        sc = torch.empty(int(sv[-1]), dtype=torch.int32, device="cuda")
+        t = [torch.from_numpy(x).cuda() for x in (sv, so, sa)]
+        K.decompose_batched(*t, sc, **topts)
+        _, per_s = timed_calls(lambda: K.decompose_batched(*t, sc, **topts), 5, 1)
+        res["by_size"][name] = {"graphs": int(sel.sum()), "entries": int(so[-1]),
+                                "event_ms_median": summary(per_s)["median"]}
+        del t, sc
+    K.check()
     del parts, vptr, off, adj, out
     release()
     return res
+
+
+def sub_batch(b, sel):
+    """Segmented CSR (vptr, offsets, adj with ids renumbered) of the graphs `sel` of batch b."""
+    import numpy as np
+    vp, offs, adjs, e0 = [0], [np.zeros(1, np.int64)], [], 0
+    for g in sel:
+        v0, v1 = int(b.vptr[g]), int(b.vptr[g + 1])
+        o = b.offsets[v0:v1 + 1].astype(np.int64)
+        adjs.append((b.adj[o[0]:o[-1]].astype(np.int64) - v0 + vp[-1]).astype(np.int32))
+        offs.append(o[1:] - o[0] + e0)
+        e0 += int(o[-1] - o[0])
+        vp.append(vp[-1] + (v1 - v0))
+    return (np.array(vp, np.int64), np.concatenate(offs),
+            np.concatenate(adjs) if adjs else np.zeros(0, np.int32))
 
 
 def bench_serve(args, seconds: float = 5.0, rate: float = 20000.0, warm: float = 1.0, **server_kw):
@@ -385,9 +417,11 @@ def bench_serve(args, seconds: float = 5.0, rate: float = 20000.0, warm: float =
     is_big = u[nreq:2 * nreq] < 0.01
     pick = (u[2 * nreq:] * 512).astype(np.int64)
     log(f"[bench] serving {nreq} requests over {arrivals[-1] / 1e6:.1f}s, {int(is_big.sum())} large")
-    # four slots, one per hardware queue of the process (streams beyond that share queues, and a
-    # small batch would wait behind a large one); slot buffers sized up front for full small batches
-    server_kw.setdefault("max_inflight", 4)
+    # one slot per hardware queue of the process (streams beyond that share queues, and a small
+    # batch would wait behind a large one), two of them for large batches; slot buffers sized up
+    # front for full small batches
+    server_kw.setdefault("max_inflight", max(2, int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))))
+    server_kw.setdefault("max_large_inflight", 2 if server_kw["max_inflight"] > 2 else 1)
     srv = K.Server(device=0, hbm_budget_bytes=64 << 30, max_batch_vertices=1 << 25,
                    borrow_inputs=True, reserve_vertices=1 << 24, reserve_entries=160 << 20, **server_kw)
     tickets = [None] * nreq
@@ -408,7 +442,8 @@ def bench_serve(args, seconds: float = 5.0, rate: float = 20000.0, warm: float =
                                 ctypes.byref(rs), 0.0)
             if rc != 0:
                 raise K.KcoreError(rc, "kcore_wait", K.last_error())
-            results[i] = (out, (rs.admit_us, rs.launch_us, rs.done_us, rs.batch_id, rs.batch_graphs))
+            results[i] = (out, (rs.submit_us, rs.admit_us, rs.launch_us, rs.done_us, rs.batch_id,
+                                rs.batch_graphs))
         done_evt.set()
 
     th = threading.Thread(target=collector, daemon=True)
@@ -428,15 +463,17 @@ def bench_serve(args, seconds: float = 5.0, rate: float = 20000.0, warm: float =
     done_evt.wait()
     srv.close()
     lat = np.empty(nreq)
-    wait = np.empty(nreq)    # arrival -> admitted into a batch (host queue)
+    late = np.empty(nreq)    # scheduled arrival -> submitted (the client's own lag)
+    wait = np.empty(nreq)    # submitted -> admitted into a batch (the server's queue)
     dev = np.empty(nreq)     # batch enqueued -> result visible (copies and the peel on the device)
     ok = True
     last_done = 0.0
     batches = {}
     for i in range(nreq):
-        core, (admit_us, launch_us, done_us, bid, bg) = results[i]
+        core, (submit_us, admit_us, launch_us, done_us, bid, bg) = results[i]
         lat[i] = done_us - (t0 + arrivals[i])
-        wait[i] = admit_us - (t0 + arrivals[i])
+        late[i] = submit_us - (t0 + arrivals[i])
+        wait[i] = admit_us - submit_us
         dev[i] = done_us - launch_us
         want = want_big[pick[i] % 2] if is_big[i] else want_small[pick[i]]
         ok = ok and bool(np.array_equal(core, want))
@@ -446,7 +483,7 @@ def bench_serve(args, seconds: float = 5.0, rate: float = 20000.0, warm: float =
         batches[bid] = (bool(is_big[i]), bg, launch_us - admit_us, done_us - launch_us)
     meas = arrivals >= warm * 1e6
     nmeas = int(meas.sum())
-    lat, wait, dev, is_big = lat[meas], wait[meas], dev[meas], is_big[meas]
+    lat, late, wait, dev, is_big = lat[meas], late[meas], wait[meas], dev[meas], is_big[meas]
     span_s = (last_done - (t0 + warm * 1e6)) / 1e6
     per_class = {}
     for cls, name in ((False, "small"), (True, "large")):
@@ -466,6 +503,7 @@ def bench_serve(args, seconds: float = 5.0, rate: float = 20000.0, warm: float =
         "p99_ms": round(float(np.percentile(lat, 99)) / 1000, 3),
         "p99_small_ms": round(float(np.percentile(lat[~is_big], 99)) / 1000, 3),
         "p99_large_ms": round(float(np.percentile(lat[is_big], 99)) / 1000, 3) if is_big.any() else None,
+        "p99_small_submit_lag_ms": round(float(np.percentile(late[~is_big], 99)) / 1000, 3),
         "p99_small_wait_ms": round(float(np.percentile(wait[~is_big], 99)) / 1000, 3),
         "p99_small_device_ms": round(float(np.percentile(dev[~is_big], 99)) / 1000, 3),
         "batches": per_class, "parity": ok,

@@ -278,12 +278,20 @@ typedef struct kcore_server kcore_server;
 
 typedef struct {
   int32_t device;              /* HIP device ordinal */
-  int32_t max_inflight;        /* concurrent batches on the device (>= 1; 0 = 4) */
+  int32_t max_inflight;        /* concurrent batches on the device, one stream each (>= 1; 0 = 4);
+                                  each stream needs a hardware queue of its own, else batches
+                                  share queues and wait for each other: HIP gives a process
+                                  GPU_MAX_HW_QUEUES of them (4 unless the environment says
+                                  otherwise before HIP initialises) */
   int32_t max_batch_graphs;    /* graphs per batch (0 = 4096) */
-  int32_t max_large_inflight;  /* batches of large requests (>= 2^21 entries or 2^16 vertices) in
-                                  flight at once, each graph of them peeled by a team of workgroups
-                                  within half the device; the other slots serve small requests
-                                  (0 = max_inflight / 2, at least 1, below max_inflight) */
+  int32_t max_large_inflight;  /* batches of large requests (see large_vertices) in flight at
+                                  once, each graph of them peeled by a team of workgroups within
+                                  half the device (0 = max_inflight / 2, at least 1, below
+                                  max_inflight). Requests between the batched peel's LDS capacity
+                                  (about 9,000 vertices, by device) and the large class are
+                                  medium: batched apart from the small ones, in at most half of
+                                  the other slots (at least 1), so that small requests always have
+                                  slots that no slower graph holds up */
   int64_t max_batch_vertices;  /* vertices per batch (0 = 1 << 24) */
   int64_t hbm_budget_bytes;    /* device bytes all in-flight batches may hold (0 = 8 GiB) */
   int64_t max_request_vertices;/* larger requests are rejected with KCORE_ETOOBIG (0 = no limit) */
@@ -293,7 +301,8 @@ typedef struct {
                                   adj unchanged and alive until kcore_poll/kcore_wait returns the
                                   result (host-to-device copies then read them directly, at DMA
                                   speed when the caller's memory is pinned) */
-  int32_t reserved1;
+  int32_t large_vertices;      /* requests with at least this many vertices, or 32 times as many
+                                  adjacency entries, are large (0 = 65,536, i.e. also 2^21 entries) */
   int64_t reserve_vertices;    /* nonzero: every slot allocates, at creation, device and pinned
                                   buffers for batches of this many vertices and reserve_entries
                                   adjacency entries, and a peel workspace for max_batch_vertices,

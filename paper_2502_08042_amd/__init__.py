@@ -77,7 +77,7 @@ class ServerConfig(ctypes.Structure):
                 ("max_batch_graphs", ctypes.c_int32), ("max_large_inflight", ctypes.c_int32),
                 ("max_batch_vertices", ctypes.c_int64), ("hbm_budget_bytes", ctypes.c_int64),
                 ("max_request_vertices", ctypes.c_int64), ("batch_wait_us", ctypes.c_double),
-                ("borrow_inputs", ctypes.c_int32), ("reserved1", ctypes.c_int32),
+                ("borrow_inputs", ctypes.c_int32), ("large_vertices", ctypes.c_int32),
                 ("reserve_vertices", ctypes.c_int64), ("reserve_entries", ctypes.c_int64),
                 ("fail_ticket", ctypes.c_uint64)]
 
@@ -336,12 +336,13 @@ class Server:
                  max_batch_vertices: int = 0, hbm_budget_bytes: int = 0,
                  max_request_vertices: int = 0, batch_wait_us: float = 0.0,
                  borrow_inputs: bool = False, reserve_vertices: int = 0, reserve_entries: int = 0,
-                 fail_ticket: int = 0, max_large_inflight: int = 0):
+                 fail_ticket: int = 0, max_large_inflight: int = 0, large_vertices: int = 0):
         cfg = ServerConfig()
         cfg.device = device
         cfg.max_inflight = max_inflight
         cfg.max_batch_graphs = max_batch_graphs
         cfg.max_large_inflight = max_large_inflight
+        cfg.large_vertices = large_vertices
         cfg.max_batch_vertices = max_batch_vertices
         cfg.hbm_budget_bytes = hbm_budget_bytes
         cfg.max_request_vertices = max_request_vertices

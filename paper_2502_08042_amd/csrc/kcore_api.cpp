@@ -814,6 +814,14 @@ int kc::batched_resident_wgs() {
   return di.batch_bpc * di.cus;
 }
 
+int64_t kc::batched_lds_vertices() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  DevInfo di;
+  if (dev_info(dev, di)) return 0;
+  return (int64_t)(di.batch_lds / 8);
+}
+
 static int batched_impl(const int64_t* graph_vptr, const int64_t* offsets, const int32_t* adj,
                         int32_t num_graphs, int64_t total_vertices, int32_t* coreness_out,
                         hipStream_t stream, const kcore_options* opt, kcore_stats* stats_host,

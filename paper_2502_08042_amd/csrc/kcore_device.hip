@@ -2075,7 +2075,7 @@ __device__ __forceinline__ void team_peel(const BatchArgs& a, int team, int memb
             }
             ul = a.adj[s_rb[lo] + (t - s_pref[lo])] - (a.local_ids ? 0 : (int32_t)base);
             st_edges++;
-            if (ald(&d[ul]) > k) {
+            {  // (no liveness probe: a peeled target is at or below k, so its decrement never crosses)
               const unsigned old = asub(&d[ul], 1u);
               st_decr++;
               check_decrement(old, 1u, status);
@@ -2126,9 +2126,17 @@ __global__ __launch_bounds__(kBatchThreads) void batched_kernel(BatchArgs a) {
     const int64_t ng = a.vptr[g + 1] - base;
     if (ng <= 0) continue;
     const bool inl = ng <= a.lds_cap;
-    uint32_t* d = inl ? s_dyn : a.gdt + base;
-    int32_t* q = inl ? reinterpret_cast<int32_t*>(s_dyn + a.lds_cap) : a.gq + base;
     const int64_t* off = a.off + base;
+    // A level-sync graph whose rows fit beside its degrees and queue keeps them in LDS too: row
+    // starts relative to its first entry, then its adjacency as 16-bit local ids (ng <= lds_cap <
+    // 65,536), copied once with coalesced loads, so that no subround waits on global memory.
+    const int64_t mg = inl ? off[ng] - off[0] : 0;
+    const bool staged = inl && !a.chained && 12 * ng + 4 + 2 * mg <= 8ll * a.lds_cap;
+    uint32_t* d = inl ? s_dyn : a.gdt + base;
+    int32_t* q = staged ? reinterpret_cast<int32_t*>(s_dyn + ng)
+                        : inl ? reinterpret_cast<int32_t*>(s_dyn + a.lds_cap) : a.gq + base;
+    uint32_t* srow = staged ? s_dyn + 2 * ng : nullptr;                           // ng + 1 starts
+    uint16_t* sadj = staged ? reinterpret_cast<uint16_t*>(s_dyn + 3 * ng + 1) : nullptr;  // mg ids
     // a graph held in global memory keeps a peeled bitmap in the (then unused) LDS, so that the
     // liveness test before a decrement costs no global load
     uint32_t* pb = (!inl && ng <= 64ll * a.lds_cap) ? s_dyn : nullptr;
@@ -2139,6 +2147,12 @@ __global__ __launch_bounds__(kBatchThreads) void batched_kernel(BatchArgs a) {
       const unsigned dg = (unsigned)(off[i + 1] - off[i]);
       d[i] = dg;
       mn = min(mn, dg);
+    }
+    if (staged) {
+      const int64_t e0 = off[0];
+      const int32_t shift = a.local_ids ? 0 : (int32_t)base;
+      for (long long i = tid; i <= ng; i += kBatchThreads) srow[i] = (uint32_t)(off[i] - e0);
+      for (long long e = tid; e < mg; e += kBatchThreads) sadj[e] = (uint16_t)(a.adj[e0 + e] - shift);
     }
     if (pb)
       for (long long i = tid; i < (ng + 31) / 32; i += kBatchThreads) pb[i] = 0u;
@@ -2245,8 +2259,13 @@ __global__ __launch_bounds__(kBatchThreads) void batched_kernel(BatchArgs a) {
           long long dg = 0, rb = 0;
           if (i < tail) {
             const int32_t v = q[i];
-            rb = off[v];
-            dg = off[v + 1] - rb;
+            if (staged) {
+              rb = srow[v];
+              dg = srow[v + 1] - rb;
+            } else {
+              rb = off[v];
+              dg = off[v + 1] - rb;
+            }
           }
           long long total;
           const long long ex = block_excl_scan(dg, s_w, total);
@@ -2264,7 +2283,7 @@ __global__ __launch_bounds__(kBatchThreads) void batched_kernel(BatchArgs a) {
                 if (s_pref[mid] <= t) lo = mid; else hi = mid - 1;
               }
               const long long pos = s_rb[lo] + (t - s_pref[lo]);
-              ul = a.adj[pos] - (a.local_ids ? 0 : (int32_t)base);
+              ul = staged ? (int32_t)sadj[pos] : a.adj[pos] - (a.local_ids ? 0 : (int32_t)base);
               st_edges++;
               const bool live = pb ? !((pb[ul >> 5] >> (ul & 31)) & 1u) : d[ul] > k;
               if (live) {

@@ -226,6 +226,7 @@ int decompose_batched_local(const int64_t* graph_vptr, const int64_t* offsets, c
                             hipStream_t stream, unsigned* status_out, int32_t team_wgs = 0);
 // Workgroups of the batched peel resident on the current device at once (0 if unknown).
 int batched_resident_wgs();
+int64_t batched_lds_vertices();  // vertices of a graph the batched peel keeps in LDS
 
 // Launch helpers (defined in kcore_device.hip).
 hipError_t launch_peel(const PeelArgs& a, int blocks, hipStream_t s);

@@ -46,6 +46,9 @@ struct Request {
   kcore_request_stats st{};
 };
 
+// request size classes (see size_class)
+enum SizeClass { SC_SMALL = 0, SC_MEDIUM = 1, SC_LARGE = 2 };
+
 struct Slot {
   hipStream_t stream = nullptr;
   bool busy = false;
@@ -63,14 +66,19 @@ struct Slot {
   int64_t batch_id = 0;
   int rc = 0;
   bool large = false;
+  int cls = SC_SMALL;
 };
 
 int64_t footprint(int64_t n, int64_t m) { return 8 * (n + 1) + 4 * m + 16 * n + 64; }
 
-// Requests at least this large run in batches of their own class, so that a large graph (peeled by
-// one workgroup) never holds up the completion of a batch of small ones.
-constexpr int64_t kLargeEntries = 1 << 21;
-bool is_large(int64_t n, int64_t m) { return m >= kLargeEntries || n >= (1 << 16); }
+// Size classes, each batched on its own so that a bigger graph never holds up the completion of a
+// batch of smaller ones: large (at least large_n vertices or 32 large_n entries; every graph peeled
+// by a team of workgroups), medium (more vertices than the batched peel holds in LDS: one
+// workgroup with its state in global memory, several times slower per entry) and small.
+int size_class(int64_t n, int64_t m, int64_t large_n, int64_t medium_n) {
+  if (n >= large_n || m >= 32 * large_n) return SC_LARGE;
+  return n > medium_n ? SC_MEDIUM : SC_SMALL;
+}
 
 // memcpy split over a few threads for large buffers (request intake and batch packing are the
 // host-side cost of serving large graphs).
@@ -113,6 +121,8 @@ struct kcore_server {
   // workgroups a large batch puts in teams (every graph of it in a team): the team workgroups of all
   // large batches in flight fit in half the device, so every team completes
   int32_t team_wgs = 0;
+  int64_t medium_n = 0;  // graphs with more vertices are medium (the batched peel's LDS capacity)
+  int medium_slots = 1;  // medium batches in flight at most (half the slots large ones cannot hold)
   std::thread th;
 
   double now_us() const {
@@ -267,7 +277,8 @@ int launch_slot(kcore_server* s, Slot* sl) {
   }
   if (s->log)
     fprintf(stderr, "[kcore server] batch %lld %s: %lld graphs, %lld vertices, %lld entries; grow %.2f ms, "
-            "pack %.2f ms, enqueue %.2f ms\n", (long long)sl->batch_id, sl->large ? "large" : "small",
+            "pack %.2f ms, enqueue %.2f ms\n", (long long)sl->batch_id,
+            sl->cls == SC_LARGE ? "large" : sl->cls == SC_MEDIUM ? "medium" : "small",
             (long long)G, (long long)V, (long long)E, (t_grown - t_start) / 1000, (t_packed - t_grown) / 1000,
             (s->now_us() - t_packed) / 1000);
   return 0;
@@ -330,19 +341,30 @@ void dispatcher(kcore_server* s) {
       }
     }
     if (!s->stop && free_slot && !s->queue.empty()) {
-      // Admit in arrival order, one size class per batch: the class of the oldest request, then
-      // every queued request of that class while the budget and batch limits allow. Large
-      // batches may not take the last free slot, so small requests always have one.
-      int busy_large = 0;
+      // Admit in arrival order, one size class per batch: the class of the oldest request whose
+      // class may take a slot now, then every queued request of that class while the budget and
+      // batch limits allow. Large batches hold at most max_large_inflight slots and medium ones at
+      // most medium_slots, so small requests always have a slot of their own.
+      int busy_cls[3] = {0, 0, 0};
       for (Slot* sl : s->slots)
-        if (sl->busy && sl->large) ++busy_large;
-      const bool large_ok = s->slots.size() == 1 || busy_large < s->cfg.max_large_inflight;
-      const bool large = large_ok && is_large(s->queue.front()->n, s->queue.front()->m);
+        if (sl->busy) ++busy_cls[sl->cls];
+      const bool one = s->slots.size() == 1;
+      const bool ok[3] = {true, one || busy_cls[SC_MEDIUM] < s->medium_slots,
+                          one || busy_cls[SC_LARGE] < s->cfg.max_large_inflight};
+      int cls = SC_SMALL;
+      for (Request* r : s->queue) {
+        const int c = size_class(r->n, r->m, s->cfg.large_vertices, s->medium_n);
+        if (ok[c]) {
+          cls = c;
+          break;
+        }
+      }
+      const bool large = cls == SC_LARGE;
       int64_t V = 0, bytes = 0;
       std::vector<Request*> take;
       for (auto it = s->queue.begin(); it != s->queue.end();) {
         Request* r = *it;
-        if (is_large(r->n, r->m) != large) {
+        if (size_class(r->n, r->m, s->cfg.large_vertices, s->medium_n) != cls) {
           ++it;
           continue;
         }
@@ -358,6 +380,7 @@ void dispatcher(kcore_server* s) {
         bytes += r->bytes;
       }
       free_slot->large = large;
+      free_slot->cls = cls;
       if (!take.empty()) {
         const double t = s->now_us();
         free_slot->busy = true;
@@ -413,7 +436,7 @@ kcore_server* kcore_server_create(const kcore_server_config* cfg) {
   if (cfg) c = *cfg;
   if (c.max_inflight < 0 || c.max_batch_graphs < 0 || c.max_batch_vertices < 0 || c.hbm_budget_bytes < 0 ||
       c.max_request_vertices < 0 || c.batch_wait_us < 0 || c.reserve_vertices < 0 || c.reserve_entries < 0 ||
-      c.max_large_inflight < 0 || c.reserved1) {
+      c.max_large_inflight < 0 || c.large_vertices < 0) {
     kc::set_error("negative server configuration field");
     return nullptr;
   }
@@ -423,6 +446,7 @@ kcore_server* kcore_server_create(const kcore_server_config* cfg) {
   if (!c.hbm_budget_bytes) c.hbm_budget_bytes = 8ll << 30;
   if (!c.batch_wait_us) c.batch_wait_us = 50;
   if (!c.max_large_inflight) c.max_large_inflight = std::max(1, c.max_inflight / 2);
+  if (!c.large_vertices) c.large_vertices = 1 << 16;
   if (c.max_inflight > 1 && c.max_large_inflight >= c.max_inflight) c.max_large_inflight = c.max_inflight - 1;
   int ndev = 0;
   (void)hipGetLastError();  // an earlier, unrelated failure must not be reported as ours
@@ -448,6 +472,9 @@ kcore_server* kcore_server_create(const kcore_server_config* cfg) {
     int tw = res / 2 / c.max_large_inflight / kc::kTeamSize * kc::kTeamSize;
     if (tw > kc::kMaxTeams * kc::kTeamSize) tw = kc::kMaxTeams * kc::kTeamSize;
     s->team_wgs = tw >= kc::kTeamSize ? tw : 0;
+    const int64_t lv = kc::batched_lds_vertices();
+    s->medium_n = lv > 0 ? lv : INT64_MAX;
+    s->medium_slots = std::max(1, (c.max_inflight - c.max_large_inflight) / 2);
   }
   for (int i = 0; i < c.max_inflight; ++i) {
     Slot* sl = new Slot;

@@ -105,6 +105,12 @@ def test_argument_errors_without_device_work():
     assert lib.kcore_poll(None, 1, None, None) == -1
     assert lib.kcore_cancel(None, 1) == -1
     lib.kcore_server_destroy(None)
+    # server configuration: negative fields are refused before any device is touched
+    for field in ("max_inflight", "max_large_inflight", "large_vertices", "max_batch_vertices"):
+        cfg = K.ServerConfig()
+        setattr(cfg, field, -1)
+        assert not lib.kcore_server_create(ctypes.byref(cfg))
+        assert "negative" in K.last_error()
     assert lib.kcore_version() >= 10000
 
 

@@ -321,6 +321,27 @@ def test_batched_large_graph_in_global_memory(mode):
     assert not first_mismatch(got, want), first_mismatch(got, want)
 
 
+def test_batched_rows_staged_in_lds_and_not():
+    """LDS-resident graphs of the level-sync batched peel whose rows fit beside their degrees and
+    queue (12 bytes per vertex + 2 per entry within the workgroup's LDS) are peeled from an LDS copy
+    of their rows; denser ones of the same size read their rows from global memory. A batch of both
+    kinds, and of graphs on either side of the limit, must match the oracle graph by graph."""
+    # complete graphs: K_n holds n(n-1) entries, so 12n + 2n(n-1) bytes; the limit lies between
+    # K_120 (29 KB) and K_260 (136 KB) for any LDS share the device gives a workgroup
+    parts = [G.complete(n) for n in (60, 120, 170, 185, 200, 260)]
+    small = gg.batch(40, 8, hi=6000)
+    parts += [small.subgraph(g) for g in range(40)]
+    parts = [(p.offsets, p.adj) if hasattr(p, "offsets") else p for p in parts]
+    off, adj = G.union(parts)
+    vptr = np.cumsum([0] + [len(p[0]) - 1 for p in parts]).astype(np.int64)
+    want = oracle.bz(off, adj)
+    for mode in ("levelsync", "chained"):
+        say(f"[gpu] batched staged rows mode={mode} V={len(off) - 1} m={len(adj)}")
+        got, st = run_batched(off, adj, vptr, mode=mode)
+        assert not first_mismatch(got, want), first_mismatch(got, want)
+        assert st["device_status"] == 0 and st["edges"] == len(adj)
+
+
 def test_batched_plain_entry_point_large_graphs():
     # the plain entry point (no options, no statistics) on graphs above the LDS capacity
     import torch
