@@ -33,7 +33,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 # The serving workload keeps one batch slot per hardware queue of the process; HIP gives a process
 # four unless told otherwise when it initialises (streams beyond that share queues, so a small
-# batch could wait behind a large one). Eight slots: two for large batches, six for small ones.
+# batch could wait behind a large one). Eight slots: three for large batches, the rest for smaller ones.
 os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
 
 METRIC = "peeled directed edges/sec (GTEPS) + % HBM peak; batched graphs/sec & p99 latency"
@@ -418,10 +418,11 @@ def bench_serve(args, seconds: float = 5.0, rate: float = 20000.0, warm: float =
     pick = (u[2 * nreq:] * 512).astype(np.int64)
     log(f"[bench] serving {nreq} requests over {arrivals[-1] / 1e6:.1f}s, {int(is_big.sum())} large")
     # one slot per hardware queue of the process (streams beyond that share queues, and a small
-    # batch would wait behind a large one), two of them for large batches; slot buffers sized up
+    # batch would wait behind a large one), three of eight for large batches; slot buffers sized up
     # front for full small batches
     server_kw.setdefault("max_inflight", max(2, int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))))
-    server_kw.setdefault("max_large_inflight", 2 if server_kw["max_inflight"] > 2 else 1)
+    mi = server_kw["max_inflight"]
+    server_kw.setdefault("max_large_inflight", 3 if mi >= 8 else (2 if mi >= 3 else 1))
     srv = K.Server(device=0, hbm_budget_bytes=64 << 30, max_batch_vertices=1 << 25,
                    borrow_inputs=True, reserve_vertices=1 << 24, reserve_entries=160 << 20, **server_kw)
     tickets = [None] * nreq
@@ -446,6 +447,10 @@ def bench_serve(args, seconds: float = 5.0, rate: float = 20000.0, warm: float =
                                 rs.batch_graphs))
         done_evt.set()
 
+    # the submitting loop and the collector share the interpreter lock; a short switch interval
+    # keeps the submitter on schedule (its lag behind the arrival times is reported apart)
+    switch = sys.getswitchinterval()
+    sys.setswitchinterval(1e-4)
     th = threading.Thread(target=collector, daemon=True)
     th.start()
     t0 = srv.now_us()
@@ -461,6 +466,7 @@ def bench_serve(args, seconds: float = 5.0, rate: float = 20000.0, warm: float =
             raise K.KcoreError(rc, "kcore_submit", K.last_error())
         tickets[i] = tk.value
     done_evt.wait()
+    sys.setswitchinterval(switch)
     srv.close()
     lat = np.empty(nreq)
     late = np.empty(nreq)    # scheduled arrival -> submitted (the client's own lag)

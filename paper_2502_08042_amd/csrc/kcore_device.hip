@@ -1978,6 +1978,8 @@ __device__ __forceinline__ void team_push(bool p, int32_t v, int32_t* q, unsigne
   if (p) ast(&q[b + rank_in(m)], v);
 }
 
+constexpr int kTeamScan = 8;  // degrees per thread a team's round scan loads at once
+
 __device__ __forceinline__ void team_peel(const BatchArgs& a, int team, int member, long long* s_pref, long long* s_rb,
                                        long long* s_w, unsigned* s_min, long long& st_edges, long long& st_decr,
                                        long long& st_rounds, long long& st_sub, long long& st_scanned,
@@ -2019,15 +2021,27 @@ __device__ __forceinline__ void team_peel(const BatchArgs& a, int team, int memb
   for (long long r = 0;; ++r) {
     unsigned* rmx = &T->rmx[r % 3];
     if (lead && tid == 0) ast(&T->rmx[(r + 1) % 3], 0u);  // (last read two rounds ago)
-    // the round's first frontier, and the min over the others
+    // the round's first frontier, and the min over the others: kTeamScan degrees per thread in
+    // flight at once (the loads are independent; one at a time, a round's scan of a 100K-vertex
+    // graph by a team of 8 would be ~25 dependent memory round trips)
     unsigned nm = 0xffffffffu;
-    for (long long i = gtid; i < ng; i += GT) {
-      const unsigned x = ald(&d[i]);
-      st_scanned++;
-      const bool ext = x == k;
-      if (x > k) nm = min(nm, x);
-      if (ext) put_core(a.core, base + i, k, status);
-      team_push(ext, (int32_t)i, q, &T->tail);
+    for (long long b = 0; b < ng; b += GT * kTeamScan) {
+      unsigned x[kTeamScan];
+#pragma unroll
+      for (int r = 0; r < kTeamScan; ++r) {
+        const long long i = b + r * GT + gtid;
+        x[r] = i < ng ? ald(&d[i]) : 0u;
+      }
+#pragma unroll
+      for (int r = 0; r < kTeamScan; ++r) {
+        const long long i = b + r * GT + gtid;
+        const bool in = i < ng;
+        st_scanned += in ? 1 : 0;
+        const bool ext = in && x[r] == k;
+        if (in && x[r] > k) nm = min(nm, x[r]);
+        if (ext) put_core(a.core, base + i, k, status);
+        team_push(ext, (int32_t)i, q, &T->tail);
+      }
     }
     nm = wave_min(nm);
     if (l == 0) s_min[w] = nm;

@@ -53,6 +53,7 @@ struct Slot {
   hipStream_t stream = nullptr;
   bool busy = false;
   std::atomic<int> finished{0};
+  bool draining = false;  // the completion thread is copying this batch's results out
   int64_t v_cap = 0, e_cap = 0, g_cap = 0, c_cap = 0;      // device buffers (elements)
   int64_t vh_cap = 0, eh_cap = 0, gh_cap = 0, ch_cap = 0;  // pinned staging buffers
   std::vector<void*> retired_dev, retired_host;             // outgrown, freed at destroy
@@ -110,6 +111,7 @@ struct kcore_server {
   std::mutex mu;
   std::condition_variable cv;       // dispatcher wake-ups
   std::condition_variable done_cv;  // request completions
+  std::condition_variable comp_cv;  // completion-thread wake-ups (a batch finished on the device)
   std::deque<Request*> queue;
   std::unordered_map<uint64_t, Request*> all;
   std::vector<Slot*> slots;
@@ -123,7 +125,9 @@ struct kcore_server {
   int32_t team_wgs = 0;
   int64_t medium_n = 0;  // graphs with more vertices are medium (the batched peel's LDS capacity)
   int medium_slots = 1;  // medium batches in flight at most (half the slots large ones cannot hold)
-  std::thread th;
+  std::thread th;       // dispatcher: admission, packing, launches
+  std::thread comp_th;  // completion: copies results out of finished slots and frees them
+  bool comp_stop = false;
 
   double now_us() const {
     return std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
@@ -141,7 +145,7 @@ void host_done(void* p) {
     std::lock_guard<std::mutex> lk(s->mu);
     sl->finished.store(1);
   }
-  s->cv.notify_all();
+  s->comp_cv.notify_all();
 }
 
 // Grows a device buffer and, when wanted, its pinned staging twin to hold `need` elements, with
@@ -284,23 +288,30 @@ int launch_slot(kcore_server* s, Slot* sl) {
   return 0;
 }
 
-void finish_slot(kcore_server* s, Slot* sl) {
-  // called with s->mu held
-  const double t = s->now_us();
+// Results of a finished batch into its requests. Runs without s->mu: until finish_slot marks them
+// done, the batch's requests and the slot's staging belong to the thread that finishes the slot.
+void copy_results(Slot* sl) {
   if (sl->rc == 0 && sl->status_h && *sl->status_h != 0u) sl->rc = KCORE_EDEVICE;
   int64_t vb = 0;
   for (Request* r : sl->reqs) {
+    if (sl->rc == 0) r->core.assign(sl->core_h + vb, sl->core_h + vb + r->n);
+    vb += r->n;
+    std::vector<int64_t>().swap(r->off);
+    std::vector<int32_t>().swap(r->adj);
+  }
+}
+
+void finish_slot(kcore_server* s, Slot* sl) {
+  // called with s->mu held, after copy_results
+  const double t = s->now_us();
+  for (Request* r : sl->reqs) {
     if (sl->rc == 0) {
-      r->core.assign(sl->core_h + vb, sl->core_h + vb + r->n);
       r->state = RQ_DONE;
     } else {
       r->state = RQ_FAILED;
       r->err = sl->rc;
     }
-    vb += r->n;
     r->st.done_us = t;
-    std::vector<int64_t>().swap(r->off);
-    std::vector<int32_t>().swap(r->adj);
     r->offp = nullptr;
     r->adjp = nullptr;
   }
@@ -308,21 +319,42 @@ void finish_slot(kcore_server* s, Slot* sl) {
   sl->bytes = 0;
   sl->reqs.clear();
   sl->busy = false;
+  sl->draining = false;
   sl->rc = 0;
   sl->finished.store(0);
+}
+
+// Completion thread: a batch that finished on the device has its results copied out and its slot
+// freed here, outside the server lock, so that neither admission nor the runtime's completion
+// callbacks wait for the copies of a large batch.
+void completer(kcore_server* s) {
+  std::unique_lock<std::mutex> lk(s->mu);
+  for (;;) {
+    Slot* sl = nullptr;
+    for (Slot* x : s->slots)
+      if (x->busy && !x->draining && x->finished.load()) {
+        sl = x;
+        break;
+      }
+    if (!sl) {
+      if (s->comp_stop) break;
+      s->comp_cv.wait_for(lk, std::chrono::microseconds(500));
+      continue;
+    }
+    sl->draining = true;
+    lk.unlock();
+    copy_results(sl);
+    lk.lock();
+    finish_slot(s, sl);
+    s->done_cv.notify_all();
+    s->cv.notify_all();
+  }
 }
 
 void dispatcher(kcore_server* s) {
   hipSetDevice(s->cfg.device);
   std::unique_lock<std::mutex> lk(s->mu);
   for (;;) {
-    bool progressed = false;
-    for (Slot* sl : s->slots)
-      if (sl->busy && sl->finished.load()) {
-        finish_slot(s, sl);
-        progressed = true;
-      }
-    if (progressed) s->done_cv.notify_all();
     int busy = 0;
     Slot* free_slot = nullptr;
     for (Slot* sl : s->slots) {
@@ -415,6 +447,7 @@ void dispatcher(kcore_server* s) {
             free_slot->busy = false;
           } else {
             free_slot->rc = rc;
+            copy_results(free_slot);  // (a failed batch: no results to copy)
             finish_slot(s, free_slot);
             s->done_cv.notify_all();
           }
@@ -503,6 +536,7 @@ kcore_server* kcore_server_create(const kcore_server_config* cfg) {
     }
   }
   s->th = std::thread(dispatcher, s);
+  s->comp_th = std::thread(completer, s);
   return s;
 }
 
@@ -548,26 +582,29 @@ int kcore_submit(kcore_server* s, const int64_t* offsets_host, const int32_t* ad
   return KCORE_OK;
 }
 
-static int take_result(kcore_server* s, Request* r, int32_t* out, kcore_request_stats* st) {
-  // called with s->mu held
+// Hands a finished request's result to the caller. Called with the lock held (lk); the request
+// leaves the table first, so the copy runs without the lock (no one else can reach it).
+static int take_result(kcore_server* s, Request* r, int32_t* out, kcore_request_stats* st,
+                       std::unique_lock<std::mutex>& lk) {
+  s->all.erase(r->ticket);
+  lk.unlock();
   int rc = KCORE_OK;
   if (r->state == RQ_CANCELED) rc = KCORE_ECANCELED;
   else if (r->state == RQ_FAILED) rc = r->err ? r->err : KCORE_EDEVICE;
   else if (out && r->n) memcpy(out, r->core.data(), sizeof(int32_t) * r->n);
   if (st) *st = r->st;
-  s->all.erase(r->ticket);
   delete r;
   return rc;
 }
 
 int kcore_poll(kcore_server* s, uint64_t ticket, int32_t* coreness_host_out, kcore_request_stats* st) {
   if (!s) return KCORE_EINVAL;
-  std::lock_guard<std::mutex> lk(s->mu);
+  std::unique_lock<std::mutex> lk(s->mu);
   auto it = s->all.find(ticket);
   if (it == s->all.end()) return KCORE_ENOTFOUND;
   Request* r = it->second;
   if (r->state == RQ_QUEUED || r->state == RQ_RUNNING) return KCORE_PENDING;
-  return take_result(s, r, coreness_host_out, st);
+  return take_result(s, r, coreness_host_out, st, lk);
 }
 
 int kcore_wait(kcore_server* s, uint64_t ticket, int32_t* coreness_host_out, kcore_request_stats* st,
@@ -580,7 +617,7 @@ int kcore_wait(kcore_server* s, uint64_t ticket, int32_t* coreness_host_out, kco
     auto it = s->all.find(ticket);
     if (it == s->all.end()) return KCORE_ENOTFOUND;
     Request* r = it->second;
-    if (r->state != RQ_QUEUED && r->state != RQ_RUNNING) return take_result(s, r, coreness_host_out, st);
+    if (r->state != RQ_QUEUED && r->state != RQ_RUNNING) return take_result(s, r, coreness_host_out, st, lk);
     if (timeout_us > 0 && std::chrono::steady_clock::now() >= deadline) return KCORE_PENDING;
     s->done_cv.wait_for(lk, std::chrono::microseconds(500));
   }
@@ -618,7 +655,13 @@ void kcore_server_destroy(kcore_server* s) {
     s->queue.clear();
   }
   s->cv.notify_all();
-  if (s->th.joinable()) s->th.join();
+  if (s->th.joinable()) s->th.join();  // (it returns once every slot has been freed)
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->comp_stop = true;
+  }
+  s->comp_cv.notify_all();
+  if (s->comp_th.joinable()) s->comp_th.join();
   hipSetDevice(s->cfg.device);
   for (Slot* sl : s->slots) {
     hipStreamSynchronize(sl->stream);
