@@ -9,6 +9,8 @@
         that bench.py reads back (keyed by the kernel source hash)
     python -m paper_2502_08042_amd.profile_summary counters DIR --match peel_kernel
         mean per dispatch of every counter in a --pmc run
+    python -m paper_2502_08042_amd.profile_summary dispatches DIR --match batched_kernel --first 5
+        durations of the first N dispatches of a kernel, in launch order, from a --kernel-trace run
 
 DIR is the rocprofv3 output directory (-d); its CSV files are found recursively.
 """
@@ -62,8 +64,9 @@ def kernel_stats(d: str, match):
     return out
 
 
-def counter_means(d: str, match, counter=None):
-    """Mean per dispatch of each counter, per kernel (dispatches summed over counter instances)."""
+def counter_means(d: str, match, counter=None, first: int = 0):
+    """Mean per dispatch of each counter, per kernel (dispatches summed over counter instances);
+    with `first`, over each kernel's first dispatches in launch order only."""
     per = defaultdict(lambda: defaultdict(float))  # (kernel, dispatch) -> counter -> value
     for r in _rows(d, "counter_collection.csv"):
         name = _col(r, "Kernel_Name", "Kernel-Name", "KernelName")
@@ -75,7 +78,11 @@ def counter_means(d: str, match, counter=None):
         disp = _col(r, "Dispatch_Id", "Dispatch-Id", "DispatchId")
         per[(_short(name), disp)][cname] += float(_col(r, "Counter_Value", "Counter-Value", "CounterValue"))
     acc = defaultdict(lambda: defaultdict(list))
-    for (k, _), cs in per.items():
+    seen = defaultdict(int)
+    for (k, _), cs in sorted(per.items(), key=lambda kv: (kv[0][0], int(kv[0][1]))):
+        seen[k] += 1
+        if first and seen[k] > first:
+            continue
         for c, v in cs.items():
             acc[k][c].append(v)
     return {k: {c: sum(v) / len(v) for c, v in cs.items()} for k, cs in acc.items()}
@@ -93,9 +100,14 @@ def main(argv=None):
     b.add_argument("--match", required=True)
     b.add_argument("--workload", required=True)
     b.add_argument("--mode", default="auto")
+    b.add_argument("--first", type=int, default=0, help="only each kernel's first N dispatches")
     c = sub.add_parser("counters")
     c.add_argument("dir")
     c.add_argument("--match", default="")
+    e = sub.add_parser("dispatches")
+    e.add_argument("dir")
+    e.add_argument("--match", required=True)
+    e.add_argument("--first", type=int, default=0)
     args = ap.parse_args(argv)
     match = [m for m in args.match.split(",") if m]
     if args.cmd == "stats":
@@ -110,6 +122,17 @@ def main(argv=None):
     if args.cmd == "counters":
         print(json.dumps(counter_means(args.dir, match), indent=1, sort_keys=True))
         return
+    if args.cmd == "dispatches":
+        rows = [r for r in _rows(args.dir, "kernel_trace.csv")
+                if any(m in _col(r, "Kernel_Name", "KernelName") for m in match)]
+        rows.sort(key=lambda r: int(_col(r, "Start_Timestamp")))
+        ms = [(int(_col(r, "End_Timestamp")) - int(_col(r, "Start_Timestamp"))) / 1e6 for r in rows]
+        if args.first > 0:
+            ms = ms[:args.first]
+        print(json.dumps({"dispatches": len(ms), "mean_ms": round(sum(ms) / max(len(ms), 1), 4),
+                          "min_ms": round(min(ms), 4) if ms else None,
+                          "max_ms": round(max(ms), 4) if ms else None, "each_ms": [round(x, 4) for x in ms]}))
+        return
     copy = ["copyBuffer", "copy_kernel", "elementwise", "Copy"]
     cf = counter_means(args.copy_fetch, copy, "FETCH_SIZE")
     cw = counter_means(args.copy_write, copy, "WRITE_SIZE")
@@ -117,8 +140,8 @@ def main(argv=None):
     cwk = max(v["WRITE_SIZE"] for v in cw.values())
     copy_bytes = 1 << 30
     ff, wf = copy_bytes / (cfk * 1024), copy_bytes / (cwk * 1024)
-    fk = {k: v["FETCH_SIZE"] for k, v in counter_means(args.fetch, match, "FETCH_SIZE").items()}
-    wk = {k: v["WRITE_SIZE"] for k, v in counter_means(args.write, match, "WRITE_SIZE").items()}
+    fk = {k: v["FETCH_SIZE"] for k, v in counter_means(args.fetch, match, "FETCH_SIZE", args.first).items()}
+    wk = {k: v["WRITE_SIZE"] for k, v in counter_means(args.write, match, "WRITE_SIZE", args.first).items()}
     sys.path.insert(0, ROOT)
     import bench
     fb = sum(fk.values()) * 1024 * ff
