@@ -31,10 +31,12 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
-# The serving workload keeps one batch slot per hardware queue of the process; HIP gives a process
-# four unless told otherwise when it initialises (streams beyond that share queues, so a small
-# batch could wait behind a large one). Eight slots: three for large batches, the rest for smaller ones.
-os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
+# The serving workload gives each of its eight batch slots (three for large batches) a stream on a
+# hardware queue of its own; HIP gives a process four queues unless told otherwise when it
+# initialises, and streams beyond that share queues, so a small batch could wait behind a large
+# one. Sixteen leave room for the queues the runtime takes for itself (the cooperative launches of
+# the other workloads take one).
+os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
 
 METRIC = "peeled directed edges/sec (GTEPS) + % HBM peak; batched graphs/sec & p99 latency"
 HBM_PEAK_GBS = 8000.0
@@ -417,10 +419,10 @@ def bench_serve(args, seconds: float = 5.0, rate: float = 20000.0, warm: float =
     is_big = u[nreq:2 * nreq] < 0.01
     pick = (u[2 * nreq:] * 512).astype(np.int64)
     log(f"[bench] serving {nreq} requests over {arrivals[-1] / 1e6:.1f}s, {int(is_big.sum())} large")
-    # one slot per hardware queue of the process (streams beyond that share queues, and a small
-    # batch would wait behind a large one), three of eight for large batches; slot buffers sized up
-    # front for full small batches
-    server_kw.setdefault("max_inflight", max(2, int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))))
+    # a slot per two hardware queues of the process, at most eight (streams beyond the queues share
+    # them, and a small batch would wait behind a large one), three of eight for large batches;
+    # slot buffers sized up front for full small batches
+    server_kw.setdefault("max_inflight", max(2, min(8, int(os.environ.get("GPU_MAX_HW_QUEUES", "4")) // 2)))
     mi = server_kw["max_inflight"]
     server_kw.setdefault("max_large_inflight", 3 if mi >= 8 else (2 if mi >= 3 else 1))
     srv = K.Server(device=0, hbm_budget_bytes=64 << 30, max_batch_vertices=1 << 25,

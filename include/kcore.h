@@ -282,7 +282,8 @@ typedef struct {
                                   each stream needs a hardware queue of its own, else batches
                                   share queues and wait for each other: HIP gives a process
                                   GPU_MAX_HW_QUEUES of them (4 unless the environment says
-                                  otherwise before HIP initialises) */
+                                  otherwise before HIP initialises), and the runtime takes some
+                                  for itself (cooperative launches use one), so leave room */
   int32_t max_batch_graphs;    /* graphs per batch (0 = 4096) */
   int32_t max_large_inflight;  /* batches of large requests (see large_vertices) in flight at
                                   once, each graph of them peeled by a team of workgroups within
