@@ -32,11 +32,11 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 # The serving workload gives each of its eight batch slots (three for large batches) a stream on a
-# hardware queue of its own; HIP gives a process four queues unless told otherwise when it
-# initialises, and streams beyond that share queues, so a small batch could wait behind a large
-# one. Sixteen leave room for the queues the runtime takes for itself (the cooperative launches of
-# the other workloads take one).
-os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
+# hardware queue of its own; HIP gives a process the number of queues GPU_MAX_HW_QUEUES says when
+# it initialises (4 by default, and environments often set 4 explicitly), and streams beyond that
+# share queues, so a small batch could wait behind a large one. The bench raises it to 16, with
+# room for the queues the runtime uses itself, before anything initialises HIP.
+os.environ["GPU_MAX_HW_QUEUES"] = "16"
 
 METRIC = "peeled directed edges/sec (GTEPS) + % HBM peak; batched graphs/sec & p99 latency"
 HBM_PEAK_GBS = 8000.0

@@ -53,7 +53,8 @@ struct Slot {
   hipStream_t stream = nullptr;
   bool busy = false;
   std::atomic<int> finished{0};
-  bool draining = false;  // the completion thread is copying this batch's results out
+  bool draining = false;   // the completion thread is copying this batch's results out
+  bool launching = false;  // the dispatcher is still enqueueing this batch (its requests are its)
   int64_t v_cap = 0, e_cap = 0, g_cap = 0, c_cap = 0;      // device buffers (elements)
   int64_t vh_cap = 0, eh_cap = 0, gh_cap = 0, ch_cap = 0;  // pinned staging buffers
   std::vector<void*> retired_dev, retired_host;             // outgrown, freed at destroy
@@ -332,7 +333,7 @@ void completer(kcore_server* s) {
   for (;;) {
     Slot* sl = nullptr;
     for (Slot* x : s->slots)
-      if (x->busy && !x->draining && x->finished.load()) {
+      if (x->busy && !x->draining && !x->launching && x->finished.load()) {
         sl = x;
         break;
       }
@@ -426,11 +427,16 @@ void dispatcher(kcore_server* s) {
           r->st.batch_id = free_slot->batch_id;
           r->st.batch_graphs = (int32_t)take.size();
         }
+        // (the batch may finish on the device before launch_slot returns: the completion thread
+        // leaves the slot alone until the dispatcher is done with its requests)
+        free_slot->launching = true;
         lk.unlock();
         int rc = launch_slot(s, free_slot);
         const double tl = s->now_us();
         lk.lock();
         for (Request* r : take) r->st.launch_us = tl;
+        free_slot->launching = false;
+        s->comp_cv.notify_all();
         if (rc) {
           // the failure belongs to this batch only. A batch of several requests is retried one
           // request per batch, at the head of the queue, so that only a failing request fails.
@@ -508,6 +514,10 @@ kcore_server* kcore_server_create(const kcore_server_config* cfg) {
     const int64_t lv = kc::batched_lds_vertices();
     s->medium_n = lv > 0 ? lv : INT64_MAX;
     s->medium_slots = std::max(1, (c.max_inflight - c.max_large_inflight) / 2);
+    if (s->log)
+      fprintf(stderr, "[kcore server] %d slots (large %d, medium %d), %d resident batched workgroups, %d in "
+              "teams per large batch, medium above %lld vertices\n", c.max_inflight, c.max_large_inflight,
+              s->medium_slots, res, s->team_wgs, (long long)s->medium_n);
   }
   for (int i = 0; i < c.max_inflight; ++i) {
     Slot* sl = new Slot;
