@@ -140,3 +140,25 @@ def test_serving_injected_launch_failure_fails_only_its_request():
                 assert e.value.code == -3
             else:
                 assert np.array_equal(s.wait(t), w), f"request {i}"
+
+
+def test_serving_size_classes_never_share_a_batch():
+    """Small (held in LDS by the batched peel), medium (more vertices than that) and large
+    (large_vertices and up) requests run in batches of their own class; results stay exact."""
+    import paper_2502_08042_amd as K
+    small = [gg.batch(24, 10, hi=3000).subgraph(g) for g in range(24)]
+    medium = [gg.rmat(14, 8, 40 + i) for i in range(4)]       # 16,384 vertices
+    large = [gg.rmat(15, 8, 50 + i) for i in range(2)]        # 32,768 vertices with large_vertices 20,000
+    graphs = small[:8] + medium[:2] + small[8:16] + large[:1] + medium[2:] + small[16:] + large[1:]
+    cls = {id(g): c for c, gs in (("small", small), ("medium", medium), ("large", large)) for g in gs}
+    want = [oracle.bz(g.offsets, g.adj) for g in graphs]
+    say(f"[gpu] serving: {len(graphs)} requests of three size classes")
+    with K.Server(device=0, max_inflight=4, max_large_inflight=1, large_vertices=20000) as s:
+        ts = [s.submit(g.offsets, g.adj) for g in graphs]
+        by_batch = {}
+        for t, g, w in zip(ts, graphs, want):
+            core, st = s.wait(t, with_stats=True)
+            assert np.array_equal(core, w)
+            by_batch.setdefault(st["batch_id"], set()).add(cls[id(g)])
+    assert all(len(c) == 1 for c in by_batch.values()), by_batch
+    assert {next(iter(c)) for c in by_batch.values()} == {"small", "medium", "large"}
