@@ -465,7 +465,7 @@ void kc::set_error(const char* msg) { g_err = msg ? msg : ""; }
 
 extern "C" {
 
-int kcore_version(void) { return 10100; }
+int kcore_version(void) { return 10200; }
 
 const char* kcore_last_error(void) { return g_err.c_str(); }
 
