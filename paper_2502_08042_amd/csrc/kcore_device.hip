@@ -459,16 +459,17 @@ __device__ __forceinline__ void queue_push(const PeelArgs& a, const PhaseOut& o,
 // Pushes crossed/extracted vertices: hubs are split into tiles, small vertices go to the wave's
 // local queue (chained mode, while it has room). Outside async phases the rest goes to the next
 // frontier (staged) and the tile list; in async phases both go to the async queue. All lanes call.
+template <bool CH>
 __device__ __forceinline__ void push_vertices(const PeelArgs& a, WaveCtx& c, const PhaseOut& o,
                                               bool p, int32_t v, bool hub) {
   const bool ps = p && !hub;
   const unsigned long long ms = __ballot(ps);
   if (ms) {
     const int cnt = __popcll(ms);
-    if (a.chained && c.lq_cnt + cnt <= kLocalQ) {
+    if (CH && c.lq_cnt + cnt <= kLocalQ) {
       if (ps) c.lq[(c.lq_head + c.lq_cnt + rank_in(ms)) & (kLocalQ - 1)] = v;
       c.lq_cnt += cnt;
-    } else if (c.async) {
+    } else if (CH && c.async) {
       queue_push(a, o, v, ps ? 1 : 0, false);
     } else {
       stage_push(c.sf, ps, v, &o.slot->small, o.fr, a.fcap, &a.ctl->status);
@@ -483,12 +484,12 @@ __device__ __forceinline__ void push_vertices(const PeelArgs& a, WaveCtx& c, con
       nt = (deg + a.tile - 1) / a.tile;
     }
     if (lane_id() == 0) aadd(&o.slot->hubv, (unsigned long long)__popcll(mh));
-    if (c.async) {
+    if (CH && c.async) {
       queue_push(a, o, v, nt, true);
       return;
     }
     bool pg = ph;
-    if (c.bq_open && block_push(c, rb, deg, a.tile, (ph && nt <= a.bq_max_tiles) ? nt : 0, a.bq_backlog))
+    if (CH && c.bq_open && block_push(c, rb, deg, a.tile, (ph && nt <= a.bq_max_tiles) ? nt : 0, a.bq_backlog))
       pg = false;
     if (!pg) nt = 0;
     if (__ballot(pg) == 0) return;
@@ -572,7 +573,7 @@ __device__ __forceinline__ void sample_hit(const PeelArgs& a, const WaveCtx& c, 
 // latency-bound phases the probe is skipped (decrementing a peeled vertex is harmless: it can
 // never cross k again, and each neighbour decrements it once, so it never drops below zero).
 // The lane whose decrement takes u from k+1 to k pushes it.
-template <bool S, bool H, int U>
+template <bool S, bool H, bool CH, int U>
 __device__ __forceinline__ void edges_batch(const PeelArgs& a, WaveCtx& c, const PhaseOut& o,
                                             const int32_t (&u)[U], unsigned valid, uint32_t k) {
   uint32_t sw[U];
@@ -635,7 +636,7 @@ __device__ __forceinline__ void edges_batch(const PeelArgs& a, WaveCtx& c, const
     const bool hub = (old[j] & HUBBIT) != 0u;
     if (crossed) {
       const uint32_t bit = 1u << (u[j] & 15);
-      if (c.arbitrate) {
+      if (CH && c.arbitrate) {
         // a scan of this phase may find u at the same time: the peeled bit decides ownership
         if (aor(&a.state[u[j] >> 4], bit) & bit) crossed = false;
       } else {
@@ -647,14 +648,14 @@ __device__ __forceinline__ void edges_batch(const PeelArgs& a, WaveCtx& c, const
         c.peeled += 1;
       }
     }
-    push_vertices(a, c, o, crossed, u[j], hub);
+    push_vertices<CH>(a, c, o, crossed, u[j], hub);
   }
 }
 
 // Expands the rows of up to 64 vertices (one per lane, -1 = none) edge-balanced across the wave:
 // an exclusive scan of the degrees, then each lane finds the row of each of its entries by binary
 // search over the scan.
-template <bool S, bool H>
+template <bool S, bool H, bool CH>
 __device__ __forceinline__ void expand_rows(const PeelArgs& a, WaveCtx& c, const PhaseOut& o, int32_t v, uint32_t k) {
   long long b = 0, d = 0;
   if (v >= 0) row_of(a, c, v, b, d);
@@ -682,12 +683,12 @@ __device__ __forceinline__ void expand_rows(const PeelArgs& a, WaveCtx& c, const
         valid |= 1u << q;
       }
     }
-    edges_batch<S, H>(a, c, o, u, valid, k);
+    edges_batch<S, H, CH>(a, c, o, u, valid, k);
   }
 }
 
 // A hub tile: adjacency entries [pos, pos + len), len <= 64 * kTileUnroll for default tiles.
-template <bool S, bool H>
+template <bool S, bool H, bool CH>
 __device__ __forceinline__ void expand_span(const PeelArgs& a, WaveCtx& c, const PhaseOut& o, long long pos,
                                             long long len, uint32_t k) {
   // hub rows mostly point at vertices peeled long ago: probe the peeled bits here (in every phase
@@ -708,25 +709,25 @@ __device__ __forceinline__ void expand_span(const PeelArgs& a, WaveCtx& c, const
         valid |= 1u << q;
       }
     }
-    edges_batch<S, H>(a, c, o, u, valid, k);
+    edges_batch<S, H, CH>(a, c, o, u, valid, k);
   }
   c.precheck = saved;
 }
 
 // Tile j of the row of v (async queue entries name the vertex).
-template <bool S, bool H>
+template <bool S, bool H, bool CH>
 __device__ __forceinline__ void expand_tile(const PeelArgs& a, WaveCtx& c, const PhaseOut& o, int32_t v, int32_t j,
                                             uint32_t k) {
   long long rb = 0, d = 0;
   row_of(a, c, v, rb, d);
   const long long b = rb + (long long)j * a.tile;
-  expand_span<S, H>(a, c, o, b, min(rb + d, b + a.tile) - b, k);
+  expand_span<S, H, CH>(a, c, o, b, min(rb + d, b + a.tile) - b, k);
 }
 
 // Applies the block's combined decrements: one atomic subtraction of c per target; exactly one
 // subtraction takes a target from above k to k or below (old > k >= old - c), and that one pushes
 // it. Clears the table for the next phase. All threads of the block call.
-template <bool H>
+template <bool H, bool CH>
 __device__ __forceinline__ void comb_flush(const PeelArgs& a, WaveCtx& c, const PhaseOut& o, uint32_t k) {
   __syncthreads();
   for (int s0 = 0; s0 < kCombSlots; s0 += kPeelThreads) {
@@ -757,14 +758,14 @@ __device__ __forceinline__ void comb_flush(const PeelArgs& a, WaveCtx& c, const 
     if constexpr (H) {
       if (c.hbs) hbs_move(a, c, o, u >= 0 && hxo >= hxn, u, hxo, hxn, k);
     }
-    push_vertices(a, c, o, crossed, u, hub);
+    push_vertices<CH>(a, c, o, crossed, u, hub);
   }
   __syncthreads();
 }
 
 // Chained mode: peel what the wave queued locally, in packets of up to 64 vertices, until the
 // queue is empty or the wave's budget for this phase is spent; what is left joins the frontier.
-template <bool S, bool H>
+template <bool S, bool H, bool CH>
 __device__ __forceinline__ void drain_local(const PeelArgs& a, WaveCtx& c, const PhaseOut& o, uint32_t k) {
   while (c.lq_cnt > 0 && c.lq_used < a.lq_budget) {
     const int take = c.lq_cnt < 64 ? c.lq_cnt : 64;
@@ -773,7 +774,7 @@ __device__ __forceinline__ void drain_local(const PeelArgs& a, WaveCtx& c, const
     c.lq_cnt -= take;
     c.lq_used += take;
     if (lane_id() == 0) atomicAdd(&c.bqc[5], take);
-    expand_rows<S, H>(a, c, o, v, k);
+    expand_rows<S, H, CH>(a, c, o, v, k);
   }
   while (c.lq_cnt > 0) {
     const int take = c.lq_cnt < 64 ? c.lq_cnt : 64;
@@ -794,7 +795,7 @@ __device__ __forceinline__ void drain_local(const PeelArgs& a, WaveCtx& c, const
 // busy wave (busy first) and then no unclaimed slot: entries are only reserved by busy waves, and a
 // wave that reserved entries stays until it sees them claimed, so no entry is left behind. Waits
 // are bounded.
-template <bool S, bool H>
+template <bool S, bool H, bool CH>
 __device__ __forceinline__ void block_loop(const PeelArgs& a, WaveCtx& c, const PhaseOut& o, uint32_t k) {
   int* head = &c.bqc[0];
   int* tail = &c.bqc[1];
@@ -850,8 +851,8 @@ __device__ __forceinline__ void block_loop(const PeelArgs& a, WaveCtx& c, const 
     if (state != 1) return;
     e = __shfl(e, 0, 64);
     if (e == kQSkip) continue;
-    expand_span<S, H>(a, c, o, (long long)((unsigned long long)e >> 16), e & 0xffff, k);
-    drain_local<S, H>(a, c, o, k);
+    expand_span<S, H, CH>(a, c, o, (long long)((unsigned long long)e >> 16), e & 0xffff, k);
+    drain_local<S, H, CH>(a, c, o, k);
   }
 }
 
@@ -862,7 +863,7 @@ __device__ __forceinline__ void block_loop(const PeelArgs& a, WaveCtx& c, const 
 // (read after done) nothing is left in flight and nothing more can be created. Only wave 0 of a
 // workgroup polls those shared counters (and publishes the outcome in LDS for its siblings), so
 // waiting waves do not slow down the atomics of working ones. Waits are bounded.
-template <bool S, bool H>
+template <bool S, bool H, bool CH>
 __device__ __forceinline__ void async_loop(const PeelArgs& a, WaveCtx& c, const PhaseOut& o, uint32_t k,
                                            volatile int* s_quiet) {
   PhaseSlot* PS = o.slot;
@@ -922,10 +923,10 @@ __device__ __forceinline__ void async_loop(const PeelArgs& a, WaveCtx& c, const 
     const uint32_t j = (uint32_t)((unsigned long long)e >> 32);
     c.lq_used = 0;
     if (j == kWholeRow)
-      expand_rows<S, H>(a, c, o, lane_id() == 0 ? v : -1, k);
+      expand_rows<S, H, CH>(a, c, o, lane_id() == 0 ? v : -1, k);
     else
-      expand_tile<S, H>(a, c, o, v, (int32_t)j, k);
-    if (a.chained) drain_local<S, H>(a, c, o, k);
+      expand_tile<S, H, CH>(a, c, o, v, (int32_t)j, k);
+    if (CH) drain_local<S, H, CH>(a, c, o, k);
     __builtin_amdgcn_s_waitcnt(0);
     if (lane_id() == 0) aadd(&PS->qdone, 1ull);
   }
@@ -933,7 +934,7 @@ __device__ __forceinline__ void async_loop(const PeelArgs& a, WaveCtx& c, const 
 
 enum PhaseKind { PH_SCAN = 0, PH_EXPAND = 1, PH_ASYNC = 2, PH_RESIDUAL = 3, PH_TAIL = 4, PH_SAMPLE = 5 };
 
-template <bool S, bool H>
+template <bool S, bool H, bool CH>
 __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
   __shared__ int32_t s_sf[kWaves][kStage];
   __shared__ int32_t s_sa[kWaves][kStage];
@@ -1437,12 +1438,12 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
     // are latency bound: skip the probe and spread the frontier over as many waves as possible
     c.precheck = kind == PH_SCAN ? slen >= a.big_phase * 16 : (fs + ft * (a.tile / 16)) >= a.big_phase;
     // chained mode folds the round's whole peel into its scan phase once the active set is small
-    const bool async_scan = kind == PH_SCAN && a.chained && !hbs_on && asize <= a.async_scan_max;
+    const bool async_scan = kind == PH_SCAN && CH && !hbs_on && asize <= a.async_scan_max;
     // deferred (combined) decrements would hide work from the async quiescence test
     c.async = kind == PH_ASYNC || async_scan;
     c.combine = c.precheck && !c.async;
-    c.arbitrate = kind == PH_SCAN && a.chained;
-    c.bq_open = a.chained && a.bq_max_tiles > 0 && !c.async;
+    c.arbitrate = kind == PH_SCAN && CH;
+    c.bq_open = CH && a.bq_max_tiles > 0 && !c.async;
     if (tr) {
       C->trace[p][4] = (unsigned long long)kind | (c.precheck ? 16ull : 0ull) | (c.async ? 32ull : 0ull) |
                        ((unsigned long long)k << 8);
@@ -1492,7 +1493,7 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
             c.peeled += 1;
           }
         }
-        push_vertices(a, c, o, ext, v, (word & HUBBIT) != 0u);
+        push_vertices<CH>(a, c, o, ext, v, (word & HUBBIT) != 0u);
       }
     } else {
       // Alg. 3 over the frontier: packets of small vertices, then hub tiles (the static share of
@@ -1507,19 +1508,19 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
         if (it < npk) {
           const long long i = it * per + l;
           const int32_t v = (l < per && i < fs) ? ald(&fcur[i]) : -1;
-          expand_rows<S, H>(a, c, o, v, k);
+          expand_rows<S, H, CH>(a, c, o, v, k);
         } else {
           const unsigned long long sw = ald(&tcur[it - npk]);
-          expand_span<S, H>(a, c, o, (long long)(sw >> 16), (long long)(sw & 0xffff), k);
+          expand_span<S, H, CH>(a, c, o, (long long)(sw >> 16), (long long)(sw & 0xffff), k);
         }
       }
     }
-    if (a.chained) drain_local<S, H>(a, c, o, k);
+    if (CH) drain_local<S, H, CH>(a, c, o, k);
     if (c.bq_open) {
-      block_loop<S, H>(a, c, o, k);
+      block_loop<S, H, CH>(a, c, o, k);
       c.bq_open = false;
     }
-    if (c.async) {
+    if (CH && c.async) {
       if (threadIdx.x == 0) s_quiet = 0;
       __syncthreads();
       if (threadIdx.x == 0) {
@@ -1528,14 +1529,14 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
       }
       // a few waves per workgroup take part in the dynamic part: every claim is an atomic on one
       // shared counter, so thousands of claimers would serialise there
-      if ((threadIdx.x >> 6) < kAsyncWaves) async_loop<S, H>(a, c, o, k, &s_quiet);
+      if ((threadIdx.x >> 6) < kAsyncWaves) async_loop<S, H, CH>(a, c, o, k, &s_quiet);
     }
-    comb_flush<H>(a, c, o, k);
+    comb_flush<H, CH>(a, c, o, k);
     // every wave has left the tile queue (comb_flush starts with a workgroup barrier): reset it for
     // the next phase; the barriers of the flushes below order this before its next use
     for (int i = threadIdx.x; i < kBlockQ; i += kPeelThreads) s_bq[i] = (unsigned long long)kQEmpty;
     if (threadIdx.x < 4) s_bqc[threadIdx.x] = threadIdx.x == 2 ? kWaves : 0;
-    if (a.chained) drain_local<S, H>(a, c, o, k);
+    if (CH) drain_local<S, H, CH>(a, c, o, k);
     if (tr) C->trace[p][1] = wall_clock64();
     if (dbg) C->dbg[p - a.dbg_lo][blockIdx.x][1] = wall_clock64();
 
@@ -1620,7 +1621,7 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
     removed_since += npeel;
     if (kind != PH_SCAN) st_sub++;
     // small frontiers of chained mode are peeled by the async phase
-    const bool go_async = a.chained && nfs <= a.async_small && nft <= a.async_tiles;
+    const bool go_async = CH && nfs <= a.async_small && nft <= a.async_tiles;
     if (npeel > 0) kmax_seen = k;
     if (kind == PH_SCAN && compact) {
       aseg = 64 * (((asize + 63) / 64 + nb - 1) / nb);
@@ -1745,11 +1746,14 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
 
 hipError_t launch_peel(const PeelArgs& a, int blocks, hipStream_t s) {
   void* args[] = {const_cast<PeelArgs*>(&a)};
-  // instances: sampling, multi-bucket active set, neither (each keeps the others' code out of its
-  // registers)
-  const void* f = a.sampling ? reinterpret_cast<const void*>(peel_kernel<true, false>)
-                  : a.hbs_vmax > 0 ? reinterpret_cast<const void*>(peel_kernel<false, true>)
-                                   : reinterpret_cast<const void*>(peel_kernel<false, false>);
+  // instances: sampling (always chained), multi-bucket active set, neither; each in a chained and a
+  // level-synchronous form (each keeps the others' code out of its registers)
+  const void* f = a.sampling ? reinterpret_cast<const void*>(peel_kernel<true, false, true>)
+                  : a.hbs_vmax > 0
+                      ? (a.chained ? reinterpret_cast<const void*>(peel_kernel<false, true, true>)
+                                   : reinterpret_cast<const void*>(peel_kernel<false, true, false>))
+                      : (a.chained ? reinterpret_cast<const void*>(peel_kernel<false, false, true>)
+                                   : reinterpret_cast<const void*>(peel_kernel<false, false, false>));
   return hipLaunchCooperativeKernel(f, dim3(blocks),
                                     dim3(kPeelThreads), args, 0, s);
 }
@@ -1757,10 +1761,15 @@ hipError_t launch_peel(const PeelArgs& a, int blocks, hipStream_t s) {
 hipError_t peel_occupancy(int* blocks_per_cu) {
   int b0 = 0, b1 = 0;
   int b2 = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b0, peel_kernel<false, false>, kPeelThreads, 0);
-  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b1, peel_kernel<true, false>, kPeelThreads, 0);
-  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b2, peel_kernel<false, true>, kPeelThreads, 0);
+  int b3 = 0, b4 = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b0, peel_kernel<false, false, true>, kPeelThreads, 0);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b1, peel_kernel<true, false, true>, kPeelThreads, 0);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b2, peel_kernel<false, true, true>, kPeelThreads, 0);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b3, peel_kernel<false, false, false>, kPeelThreads, 0);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b4, peel_kernel<false, true, false>, kPeelThreads, 0);
   if (b2 < b1) b1 = b2;
+  if (b3 < b1) b1 = b3;
+  if (b4 < b1) b1 = b4;
   *blocks_per_cu = b0 < b1 ? b0 : b1;
   return e;
 }
