@@ -96,7 +96,8 @@ typedef struct {
                             checks offsets[n] against the size used before it reads any entry
                             (a failure reported through the status word, see kcore_check) */
   int32_t local_budget;  /* chained mode: vertices one wavefront may peel from its local queue per
-                            phase before handing the rest to the global frontier; 0 = default */
+                            phase (or per asynchronous queue entry) before handing the rest to the
+                            global frontier or queue; 0 = default (1024) */
   int32_t tile_edges;    /* adjacency entries per hub tile (multiple of 64, at most 32768);
                             0 = default */
   int32_t async_frontier;/* chained mode: a frontier of at most this many vertices (and as many

@@ -44,6 +44,7 @@ SINGLE_SPACE = {
     "buckets": [0, "n"],
     "combine_degree": [0, 256, 4096],
     "big_phase": [0, 4096, 65536],
+    "local_budget": [0, 512, 4096],
 }
 BATCHED_SPACE = {
     "mode": ["levelsync", "chained"],

@@ -495,7 +495,10 @@ static int peel_impl(const int64_t* offsets, const int32_t* adj, int64_t n, int3
     return fail(KCORE_EINVAL, "sampling mode takes at most 2^30 vertices (n = %lld)", (long long)n);
   const uint32_t hub = (opt && opt->hub_degree) ? (uint32_t)opt->hub_degree : 256u;
   const int tile = (opt && opt->tile_edges) ? opt->tile_edges : 256;
-  const int budget = (opt && opt->local_budget) ? opt->local_budget : 4096;
+  // (1,024: a wave hands its queue on to the others after that many; on the road grid, whose time
+  // is one asynchronous phase of chains, 25.1 ms against 26.8 ms at 4,096 and 30.4 ms at 256; no
+  // change on Chung-Lu or RMAT-16)
+  const int budget = (opt && opt->local_budget) ? opt->local_budget : 1024;
   // m: the number of entries the workspace is sized for. The caller's num_entries when given;
   // otherwise the room left in the device allocation that holds adj (no host-device round trip),
   // at most n (n - 1), which a simple graph never exceeds. The kernel checks offsets[n] <= m.
