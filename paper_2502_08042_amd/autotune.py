@@ -16,7 +16,7 @@ largest degree exceeds 64 times the average.
 
 Command line (on a GPU machine)::
 
-    python -m paper_2502_08042_amd.autotune [--workloads rmat16,grid,chunglu,batch] [--out PATH]
+    python -m paper_2502_08042_amd.autotune [--workloads rmat16,grid,chunglu,hcns,batch] [--out PATH]
 """
 from __future__ import annotations
 
@@ -45,6 +45,8 @@ SINGLE_SPACE = {
     "combine_degree": [0, 256, 4096],
     "big_phase": [0, 4096, 65536],
     "local_budget": [0, 512, 4096],
+    "async_frontier": [0, -1, 16384],
+    "async_scan": [0, 65536],
 }
 BATCHED_SPACE = {
     "mode": ["levelsync", "chained"],
@@ -185,6 +187,10 @@ def _workloads(names):
             import graphgen.gpu as gp
             off, adj = gp.config_chung_lu_device()
             yield name, False, (off, adj)
+        elif name == "hcns":
+            import graphgen.gpu as gp
+            off, adj = gp.hcns_device(20000)
+            yield name, False, (off, adj)
         elif name == "batch":
             b = gg.config_batch()
             yield name, True, tuple(torch.from_numpy(x).cuda() for x in (b.vptr, b.offsets, b.adj))
@@ -196,7 +202,7 @@ def _workloads(names):
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
-    ap.add_argument("--workloads", default="rmat16,grid,chunglu,batch")
+    ap.add_argument("--workloads", default="rmat16,grid,chunglu,hcns,batch")
     ap.add_argument("--out", default=DEFAULT_CACHE)
     ap.add_argument("--reps", type=int, default=3)
     args = ap.parse_args(argv)
