@@ -103,6 +103,25 @@ def test_tuning_knobs_do_not_change_results(mode):
         assert not first_mismatch(got, want), first_mismatch(got, want)
 
 
+def test_cached_tuned_options_are_exact():
+    """Every option set the shipped tuning cache holds for a single-graph class, applied to graphs
+    of other shapes (they are plain launch and threshold choices), gives the oracle's coreness."""
+    import paper_2502_08042_amd.autotune as A
+    cases = [("rmat13", gg.rmat(13, 16, 7)), ("road256", gg.grid_road(256, 0.05, 0.01, 3))]
+    off, adj = G.hcns(300)
+    sets = [(dev, cls, o["options"]) for dev, classes in A.load_cache().items()
+            for cls, o in classes.items() if cls.startswith("single/")]
+    assert sets
+    for dev, cls, opts in sets:
+        for name, o_np, a_np in [(nm, g.offsets, g.adj) for nm, g in cases] + [("hcns300", off, adj)]:
+            want = oracle.bz(o_np, a_np)
+            tuning = A._resolve({k: v for k, v in opts.items() if v != 0}, len(o_np) - 1)
+            say(f"[gpu] tuned {dev} {cls} on {name}: {tuning}")
+            got, st = run_single(o_np, a_np, mode="chained", **tuning)
+            assert not first_mismatch(got, want), (cls, name, first_mismatch(got, want))
+            assert st["device_status"] == 0
+
+
 def test_chained_work_queues_do_not_change_results():
     """Chained mode's in-phase work sharing: the workgroup tile queue (off, one tile, a few tiles,
     more tiles than the queue holds, which spills to the global list) and the asynchronous phases
