@@ -1,7 +1,9 @@
 """GPU parity at the benchmark sizes, in the configuration bench.py times (default options, one
 call on the current stream), against the oracle over every vertex: the 16.8M-vertex Chung-Lu graph
-(~1B entries) and the 4096 x 4096 road grid. Also checks that the device-side Chung-Lu generator
-used by bench.py draws exactly the graph of the host generator.
+(~1B entries) and the 4096 x 4096 road grid; and the HCNS staircase of coreness 20,000 (0.8B
+entries) against its closed form, with the default options and with the options bench.py applies
+to its workload class. Also checks that the device-side Chung-Lu generator used by bench.py draws
+exactly the graph of the host generator.
 """
 import numpy as np
 import pytest
@@ -57,3 +59,21 @@ def test_full_size_road_grid_parity():
     want = oracle.bz(g.offsets, g.adj)
     assert not first_mismatch(got, want), first_mismatch(got, want)
     assert int(want.max()) <= 3
+
+
+def test_full_size_hcns_matches_closed_form():
+    import torch
+    import graphgen.gpu as gp
+    import paper_2502_08042_amd as K
+    import paper_2502_08042_amd.autotune as A
+    kk = 20000
+    say(f"[gpu] full-size HCNS K={kk}: generate, decompose (default and tuned options)")
+    off, adj = gp.hcns_device(kk)
+    # coreness K for the clique (ids 0..K), i for u_i (id K + i)
+    want = np.array([kk] * (kk + 1) + list(range(1, kk)), dtype=np.int32)
+    for tuned in (False, True):
+        out = K.decompose(off, adj, tuned=tuned)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        assert not first_mismatch(got, want), (tuned, first_mismatch(got, want))
+    assert A.tuned_options(off), "the tuning cache has an entry for this class"
