@@ -2,8 +2,9 @@
 call on the current stream), against the oracle over every vertex: the 16.8M-vertex Chung-Lu graph
 (~1B entries) and the 4096 x 4096 road grid; and the HCNS staircase of coreness 20,000 (0.8B
 entries) against its closed form, with the default options and with the options bench.py applies
-to its workload class. Also checks that the device-side Chung-Lu generator used by bench.py draws
-exactly the graph of the host generator.
+to its workload class; and the 4,096-graph batch in one batched call, with the default and the
+tuned options. Also checks that the device-side Chung-Lu generator used by bench.py draws exactly
+the graph of the host generator.
 """
 import numpy as np
 import pytest
@@ -77,3 +78,17 @@ def test_full_size_hcns_matches_closed_form():
         got = out.cpu().numpy()
         assert not first_mismatch(got, want), (tuned, first_mismatch(got, want))
     assert A.tuned_options(off), "the tuning cache has an entry for this class"
+
+
+def test_full_size_batch_parity():
+    import torch
+    import paper_2502_08042_amd as K
+    b = gg.config_batch()
+    say(f"[gpu] full-size batch: {len(b.vptr) - 1} graphs, {b.n} vertices, {b.m} entries")
+    vptr, off, adj = (torch.from_numpy(x).cuda() for x in (b.vptr, b.offsets, b.adj))
+    want = oracle.bz(b.offsets, b.adj)
+    for tuned in (False, True):
+        out = K.decompose_batched(vptr, off, adj, tuned=tuned)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        assert not first_mismatch(got, want), (tuned, first_mismatch(got, want))
