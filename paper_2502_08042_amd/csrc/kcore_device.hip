@@ -98,27 +98,36 @@ __device__ __forceinline__ unsigned wave_min(unsigned x) {
 
 // ------------------------------------------------------------------------------------------
 // Grid barrier. Arrivals go to one of kBarGroups counters, the last arrival of each group to a
-// top counter, and the last top arrival publishes the new epoch. Counters only grow, so no reset
-// races. Every thread first waits for its own memory operations to complete (s_waitcnt), which
-// with agent-scope accesses makes them visible device-wide before the arrival. Waits are bounded:
-// after ~4 s without progress, or if any workgroup has flagged an error, every workgroup leaves.
+// top counter, and the last top arrival publishes the new epoch; with ONE set (the level-sync
+// kernel instances, whose phases are short and many) every workgroup arrives at the top counter
+// directly, one atomic round trip fewer for the completing arrival (the grouped form is kept where
+// the one-counter form measured no faster). Counters only grow and are tested for equality with
+// the epoch's total, so no reset races. Every thread first waits for its own memory operations to
+// complete (s_waitcnt), which with agent-scope accesses makes them visible device-wide before the
+// arrival. Waits are bounded: after ~4 s without progress, or if any workgroup has flagged an
+// error, every workgroup leaves.
 // ------------------------------------------------------------------------------------------
+template <bool ONE = false>
 __device__ bool grid_sync(PeelCtl* C, unsigned& epoch) {
   __shared__ int s_ok;
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
     const unsigned nb = gridDim.x;
-    const unsigned ng = nb < (unsigned)kBarGroups ? nb : (unsigned)kBarGroups;
-    const unsigned grp = blockIdx.x % ng;
-    const unsigned gsize = nb / ng + ((nb % ng) > grp ? 1u : 0u);
     const unsigned target = epoch + 1;
     int ok = 1;
     bool last = false;
-    const unsigned a = aadd(&C->bar_grp[grp][0], 1u);
-    if (a == target * gsize - 1) {
-      const unsigned b = aadd(&C->bar_top, 1u);
-      if (b == target * ng - 1) last = true;
+    if constexpr (ONE) {
+      last = aadd(&C->bar_top, 1u) == target * nb - 1;
+    } else {
+      const unsigned ng = nb < (unsigned)kBarGroups ? nb : (unsigned)kBarGroups;
+      const unsigned grp = blockIdx.x % ng;
+      const unsigned gsize = nb / ng + ((nb % ng) > grp ? 1u : 0u);
+      const unsigned a = aadd(&C->bar_grp[grp][0], 1u);
+      if (a == target * gsize - 1) {
+        const unsigned b = aadd(&C->bar_top, 1u);
+        if (b == target * ng - 1) last = true;
+      }
     }
     if (last) {
       __builtin_amdgcn_s_waitcnt(0);
@@ -1047,7 +1056,7 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
       if (m < ald(&C->slot[0].minv)) amin(&C->slot[0].minv, m);
     }
   }
-  if (!grid_sync(C, epoch)) return;
+  if (!grid_sync<!CH>(C, epoch)) return;
   st_bar++;
 
   if (threadIdx.x == 0) {
@@ -1156,7 +1165,7 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
               ast(&a.aq[t0 + j], (long long)(((unsigned long long)j << 32) | (unsigned)v));
           }
         }
-        if (!grid_sync(C, epoch)) break;
+        if (!grid_sync<!CH>(C, epoch)) break;
         st_bar++;
         if (threadIdx.x == 0) {
           s_out[0] = (long long)ald(&slot->tiles);
@@ -1184,7 +1193,7 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
             ast(&a.aq[it], kQEmpty);  // the async queue starts every phase empty
           }
         }
-        if (!grid_sync(C, epoch)) break;
+        if (!grid_sync<!CH>(C, epoch)) break;
         st_bar++;
         // (3) InitSampler for the recounted vertices; the others report their next validation
         for (long long i = gt; i < nrl; i += GT) {
@@ -1224,7 +1233,7 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
           C->trace[p][6] = (unsigned long long)ntl;
           C->trace[p][7] = (unsigned long long)asize;
         }
-        if (!grid_sync(C, epoch)) break;
+        if (!grid_sync<!CH>(C, epoch)) break;
         st_bar++;
         if (tr) C->trace[p][3] = wall_clock64();
         kind = PH_SCAN;
@@ -1302,7 +1311,7 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
             ast(&a.aq[t0 + j], (long long)(((unsigned long long)j << 32) | (unsigned)v));
         }
       }
-      if (!grid_sync(C, epoch)) break;
+      if (!grid_sync<!CH>(C, epoch)) break;
       st_bar++;
       if (threadIdx.x == 0) {
         s_out[0] = (long long)ald(&slot->tiles);
@@ -1383,7 +1392,7 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
         C->trace[p][5] = C->trace[p][6] = 0;
         C->trace[p][7] = (unsigned long long)asize;
       }
-      if (!grid_sync(C, epoch)) break;
+      if (!grid_sync<!CH>(C, epoch)) break;
       st_bar++;
       if (tr) C->trace[p][3] = wall_clock64();
       if (to_tail) {
@@ -1583,7 +1592,7 @@ __global__ __launch_bounds__(kPeelThreads, 2) void peel_kernel(PeelArgs a) {
       s_bqc[4] = 0;
       s_bqc[5] = 0;
     }
-    if (!grid_sync(C, epoch)) break;
+    if (!grid_sync<!CH>(C, epoch)) break;
     st_bar++;
     if (tr) C->trace[p][3] = wall_clock64();
 
