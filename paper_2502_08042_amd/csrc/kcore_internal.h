@@ -20,7 +20,7 @@ constexpr int kDbgPhases = 64;             // phases of the per-workgroup debug 
 constexpr int kDbgBlocks = 256;
 constexpr int kBlockQ = 1024;              // workgroup-local hub tile queue (chained mode)
 constexpr int kAsyncWaves = 2;              // waves per workgroup claiming async work
-constexpr int kBarGroups = 32;       // arrival groups of the grid barrier
+constexpr int kBarGroups = 1;        // arrival groups of the grid barrier (chained instances)
 constexpr int kBatchThreads = 512;   // threads per workgroup of the batched peel
 constexpr int kTracePhases = 16384;   // phases whose timeline workgroup 0 records
 constexpr int kTailThreads = 1024;    // threads of the single-workgroup tail peel
